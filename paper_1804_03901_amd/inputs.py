@@ -1,0 +1,228 @@
+"""Seeded synthetic inputs for the Vlasov-hybrid time step.
+
+This module only *draws* initial marker populations; it holds none of the
+method's arithmetic (no weighting, no moments, no field solve, no push).  Both
+the GPU path and the CPU oracle take their inputs from here, so a parity test
+compares the two on bit-identical marker arrays.
+
+Marker loading follows the paper's simple strategy (Sec. 2, the paragraphs on
+marker weights; Sec. 3.1, marker creation): the same number of markers
+(``ppc``) is placed in every phase-space cell and each marker carries the value
+of the initial distribution at its own position, f_l = f0(x_l, v_l).
+
+Random numbers come from SplitMix64 (Steele, Lea and Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014): state advances by the golden
+gamma 0x9E3779B97F4A7C15 and each output is the finalising mix of the state;
+a uniform double is (z >> 11) * 2**-53.  The n-th output of a stream seeded with
+``seed`` is therefore mix(seed + (n + 1) * gamma), which is evaluated here in
+vectorised form.
+
+Draw order within one stream: first the phases of the perturbation modes (one
+draw each), then, marker by marker in velocity-major order (for each velocity
+cell, for each x cell, for each of the ppc markers), one draw for the in-cell x
+offset followed by one per velocity component, and finally (stress variant
+only) one draw per marker for a log-uniform weight.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Sequence
+
+import numpy as np
+
+_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(seed: int, start: int, count: int) -> np.ndarray:
+    """Outputs ``start .. start+count-1`` of the SplitMix64 stream for ``seed``."""
+    with np.errstate(over="ignore"):
+        n = np.arange(start + 1, start + 1 + count, dtype=np.uint64)
+        z = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + n * _GAMMA
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniforms(seed: int, start: int, count: int) -> np.ndarray:
+    """Uniform doubles in [0, 1) from the SplitMix64 stream (53-bit)."""
+    z = splitmix64(seed, start, count)
+    return (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+@dataclasses.dataclass(frozen=True)
+class Population:
+    """One drifting Maxwellian in every velocity component: density * prod_d M(v_d; u_d, s_d)."""
+    density: float
+    drift: tuple = (0.0, 0.0, 0.0)
+    vth: tuple = (1.0, 1.0, 1.0)
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    """A synthetic plasma: phase-space grid, species constants and initial f0.
+
+    Units are normalised (q = -1, m = 1, Poisson constant c_P = 1, so the
+    electron plasma frequency and Debye length are 1 for unit density and
+    thermal speed); the paper's CGS form is c_P = 4*pi.
+    """
+    name: str
+    vdim: int
+    nx: int
+    nv: tuple
+    L: float
+    vmin: tuple
+    vmax: tuple
+    ppc: int
+    dt: float
+    steps: int
+    seed: int
+    populations: tuple
+    # density perturbation 1 + sum_m amp_m * cos(k_m x + phi_m); phases are
+    # drawn from the stream when ``random_phases`` is set, else all zero.
+    mode_numbers: tuple = ()
+    mode_amplitude: float = 0.0
+    random_phases: bool = False
+    weights: str = "analytic"   # or "logu": f_l log-uniform in [1e-8, 1]
+    q: float = -1.0
+    m: float = 1.0
+    c_p: float = 1.0
+    first_kick: int = 0
+
+    @property
+    def n_markers(self) -> int:
+        return self.nx * int(np.prod(self.nv[: self.vdim])) * self.ppc
+
+    @property
+    def n_cells(self) -> int:
+        return self.nx * int(np.prod(self.nv[: self.vdim]))
+
+    @property
+    def dx(self) -> float:
+        return self.L / self.nx
+
+    def dv(self, d: int = 0) -> float:
+        return (self.vmax[d] - self.vmin[d]) / self.nv[d]
+
+    def replace(self, **kw) -> "Workload":
+        return dataclasses.replace(self, **kw)
+
+
+def _maxwellian(v: np.ndarray, u: float, s: float) -> np.ndarray:
+    return np.exp(-((v - u) ** 2) / (2.0 * s * s)) / (s * math.sqrt(2.0 * math.pi))
+
+
+def mode_phases(w: Workload) -> np.ndarray:
+    if not w.mode_numbers:
+        return np.zeros(0)
+    if w.random_phases:
+        return 2.0 * math.pi * uniforms(w.seed, 0, len(w.mode_numbers))
+    return np.zeros(len(w.mode_numbers))
+
+
+def f0(w: Workload, x: np.ndarray, v: Sequence[np.ndarray]) -> np.ndarray:
+    """Initial distribution at arbitrary phase points (x, v_0[, v_1, v_2])."""
+    k1 = 2.0 * math.pi / w.L
+    dens = np.ones_like(x)
+    for mnum, ph in zip(w.mode_numbers, mode_phases(w)):
+        dens = dens + w.mode_amplitude * np.cos(k1 * mnum * x + ph)
+    g = np.zeros_like(x)
+    for p in w.populations:
+        term = np.full_like(x, p.density)
+        for d in range(w.vdim):
+            term = term * _maxwellian(v[d], p.drift[d], p.vth[d])
+        g = g + term
+    return dens * g
+
+
+def _n_pre(w: Workload) -> int:
+    return len(w.mode_numbers) if w.random_phases else 0
+
+
+def markers(w: Workload, row_begin: int = 0, row_end: int | None = None):
+    """Markers of velocity rows [row_begin, row_end) as FP64 SoA arrays.
+
+    A "row" is one velocity cell (the flattened (jz, jy, jx) index in 1D-3V).
+    Returns (x[n], v[vdim, n], f[n]) in velocity-major generation order.
+    """
+    nrows = int(np.prod(w.nv[: w.vdim]))
+    if row_end is None:
+        row_end = nrows
+    per_row = w.nx * w.ppc
+    n = (row_end - row_begin) * per_row
+    nd = 1 + w.vdim
+    first = row_begin * per_row
+    u = uniforms(w.seed, _n_pre(w) + first * nd, n * nd).reshape(n, nd)
+    loc = np.arange(first, first + n, dtype=np.int64)
+    cell = loc // w.ppc
+    i = cell % w.nx
+    row = cell // w.nx
+    dx = w.dx
+    x = (i.astype(np.float64) + u[:, 0]) * dx
+    x = np.where(x >= w.L, x - w.L, x)
+    v = np.empty((w.vdim, n))
+    rem = row.copy()
+    for d in range(w.vdim):
+        j = rem % w.nv[d]
+        rem //= w.nv[d]
+        v[d] = w.vmin[d] + (j.astype(np.float64) + u[:, 1 + d]) * w.dv(d)
+    if w.weights == "logu":
+        uf = uniforms(w.seed, _n_pre(w) + w.n_markers * nd + first, n)
+        f = 10.0 ** (-8.0 + 8.0 * uf)
+    else:
+        f = f0(w, x, v)
+    return x, v, f
+
+
+# ---------------------------------------------------------------------------
+# Workloads.  L, dt and the perturbation of the larger cases are not fixed by
+# any printed source; the choices below (L = 20*pi so that k_m = 0.1 m, dt =
+# 0.1) are this project's and are listed with the other readings.
+# ---------------------------------------------------------------------------
+
+def landau_small() -> Workload:
+    """Linear Landau damping: k = 0.5, 1% density perturbation, 16,384 markers."""
+    return Workload(
+        name="landau_1d1v_nx64_nv64_ppc4", vdim=1, nx=64, nv=(64, 1, 1),
+        L=4.0 * math.pi, vmin=(-6.0, 0, 0), vmax=(6.0, 0, 0), ppc=4, dt=0.1,
+        steps=200, seed=1804, populations=(Population(1.0),),
+        mode_numbers=(1,), mode_amplitude=0.01, random_phases=False)
+
+
+def bump_on_tail(nx: int = 1024, nv: int = 1024, ppc: int = 16, seed: int = 3901,
+                 steps: int = 1000, weights: str = "analytic",
+                 beam_drift: float = 4.5, beam_density: float = 1e-6) -> Workload:
+    """Bump-on-tail: unit core Maxwellian plus a weak beam (drift 4.5, v_th 0.5)."""
+    return Workload(
+        name=f"bump_on_tail_1d1v_nx{nx}_nv{nv}_ppc{ppc}", vdim=1, nx=nx, nv=(nv, 1, 1),
+        L=20.0 * math.pi, vmin=(-8.0, 0, 0), vmax=(8.0, 0, 0), ppc=ppc, dt=0.1,
+        steps=steps, seed=seed,
+        populations=(Population(1.0), Population(beam_density, (beam_drift, 0, 0), (0.5, 1, 1))),
+        mode_numbers=tuple(range(1, 17)), mode_amplitude=1e-4, random_phases=True,
+        weights=weights)
+
+
+def two_stream_3v(nx: int = 512, nv: int = 64, ppc: int = 4, seed: int = 3,
+                  steps: int = 100) -> Workload:
+    """Two counter-drifting Maxwellians (+-3 along x), isotropic in vy and vz."""
+    return Workload(
+        name=f"two_stream_1d3v_nx{nx}_nv{nv}^3_ppc{ppc}", vdim=3, nx=nx, nv=(nv, nv, nv),
+        L=20.0 * math.pi, vmin=(-8.0, -8.0, -8.0), vmax=(8.0, 8.0, 8.0), ppc=ppc,
+        dt=0.1, steps=steps, seed=seed,
+        populations=(Population(0.5, (3.0, 0, 0)), Population(0.5, (-3.0, 0, 0))),
+        mode_numbers=(1,), mode_amplitude=1e-4, random_phases=False)
+
+
+def adjoint_case() -> Workload:
+    return bump_on_tail(nx=1024, nv=512, ppc=8, seed=5, steps=500)
+
+
+WORKLOADS = {
+    "landau": landau_small,
+    "bump_on_tail": bump_on_tail,
+    "two_stream_3v": two_stream_3v,
+    "adjoint": adjoint_case,
+}
