@@ -1,0 +1,156 @@
+"""Throughput of the VHS time step on one MI355X.
+
+Workload: 1D-1V bump-on-tail, nx = nv = 1024 cells on v in [-8, 8), 16 markers
+per cell (16,777,216 markers), synthetic seeded markers (no dataset).  A step is
+the whole hot path: gather+push, counting sort, weight-normalised
+reconstruction of f with the fused rho partials, spectral field solve.
+
+Prints ONE JSON line.  ``value`` is marker-steps/s of the FP32 form (the
+form the metric names); the plain FP64 path is measured on the same markers
+and reported beside it.  ``roofline`` is for the reconstruction kernel,
+timed with HIP events on the library's stream inside the timed region.
+``cpu_baseline`` times the CPU oracle on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import platform
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def run_form(avl, inputs, w, x, v, f, precision, steps, warmup):
+    import torch
+    sim = avl.Simulation(w, x, v, f, precision=precision)
+    torch.cuda.synchronize()
+    sim.step(warmup, graph=True, diag=False)
+    torch.cuda.synchronize()
+    # timed region: direct launches with HIP events around each kernel class
+    avl.avl_timing(sim.h, True)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(sim.stream)
+    sim.step(steps, graph=False, diag=False)
+    t1.record(sim.stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    kt = {}
+    for k, name in enumerate(avl.KERNEL_NAMES):
+        tot, cnt = avl.avl_kernel_time(sim.h, k)
+        kt[name] = {"ms_avg": tot / cnt if cnt else None, "launches": cnt,
+                    "bytes_per_launch": avl.avl_kernel_bytes(sim.h, k)}
+    avl.avl_timing(sim.h, False)
+    # graph replay of the same steps, no events (informational)
+    torch.cuda.synchronize()
+    t0.record(sim.stream)
+    sim.step(steps, graph=True, diag=False)
+    t1.record(sim.stream)
+    torch.cuda.synchronize()
+    ms_graph = t0.elapsed_time(t1)
+    sim.check()
+    sim.close()
+    return ms / steps, ms_graph / steps, kt
+
+
+def cpu_baseline(inputs, w, x, v, f, steps):
+    import oracle
+    g = oracle.Grid.from_workload(w)
+    r0 = oracle.run(g, x, v, f, 0)
+    t = time.perf_counter()
+    oracle.run(g, x, v, f, steps, E=r0["E"])
+    dt = time.perf_counter() - t
+    return x.size * steps / dt, dt
+
+
+def cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return platform.processor()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--nx", type=int, default=1024)
+    ap.add_argument("--nv", type=int, default=1024)
+    ap.add_argument("--ppc", type=int, default=16)
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--forms", default="fp32,fp64")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
+        sys.exit(2)
+
+    import torch
+    from paper_1804_03901_amd import avl, inputs
+
+    w = inputs.bump_on_tail(nx=args.nx, nv=args.nv, ppc=args.ppc)
+    log(f"generating {w.n_markers} markers ({w.name})")
+    x, v, f = inputs.markers(w)
+    v = v.reshape(-1)
+    results = {}
+    for form in args.forms.split(","):
+        prec = avl.AVL_FP32 if form == "fp32" else avl.AVL_FP64
+        log(f"form {form}: warmup {args.warmup}, timed {args.steps}")
+        results[form] = run_form(avl, inputs, w, x, v, f, prec, args.steps, args.warmup)
+        log(f"form {form}: {results[form][0]:.4f} ms/step (graph {results[form][1]:.4f})")
+    main_form = "fp32" if "fp32" in results else next(iter(results))
+    ms, ms_graph, kt = results[main_form]
+    value = w.n_markers / (ms * 1e-3)
+    rk = kt["reconstruct"]
+    achieved = rk["bytes_per_launch"] / (rk["ms_avg"] * 1e-3) / 1e9
+    out = {
+        "metric": "marker-steps/s, 1D-1V 16.8M markers, FP32+batched vs FP64 plain; % HBM peak",
+        "value": value,
+        "unit": "marker-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if main_form == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "markers": w.n_markers, "nx": w.nx, "nv": w.nv[0], "ppc": w.ppc,
+                   "form": main_form, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_recon_1v",
+                     "bytes_per_launch": rk["bytes_per_launch"], "ms_per_launch": rk["ms_avg"]},
+        "forms": {k: {"ms_per_step": r[0], "marker_steps_per_s": w.n_markers / (r[0] * 1e-3),
+                      "ms_per_step_graph": r[1], "marker_steps_per_s_graph": w.n_markers / (r[1] * 1e-3),
+                      "kernels": r[2]} for k, r in results.items()},
+    }
+    if "fp32" in results and "fp64" in results:
+        out["fp32_speedup_over_fp64"] = results["fp64"][0] / results["fp32"][0]
+    if not args.no_cpu:
+        log(f"cpu baseline: oracle, {args.cpu_steps} steps on the full marker set, 1 thread")
+        rate, secs = cpu_baseline(inputs, w, x, v.reshape(1, -1), f, args.cpu_steps)
+        out["cpu_baseline"] = {"value": rate, "unit": "marker-steps/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{args.cpu_steps} steps of the full {w.n_markers}-marker workload "
+                                         f"after the initial solve ({secs:.1f} s), FP64, single thread",
+                               "cpu": cpu_model()}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,211 @@
+/*
+ * avl.h -- C ABI of libavl, an MI355X (gfx950) implementation of one time step
+ * of the Vlasov-hybrid simulation (VHS) method of Kilian, Schreiner & Spanier,
+ * "Afterlive" (arXiv:1804.03901), for one spatial and one or three velocity
+ * dimensions, electrostatic, one kinetic species over an immobile neutralising
+ * background.
+ *
+ * The step (Sec. 2, Fig. "algorithm"): markers move along the characteristics
+ * of the Vlasov equation (Eq. (vlasov)) in the self-consistent field; the
+ * phase-space density is rebuilt on the Eulerian grid by the weight-normalised
+ * cloud-in-cell reconstruction of Eq. (reconstruction); velocity moments give
+ * the charge density; the sinc-softened spectral Poisson solve of
+ * Eq. (poissonk)/(kappasoftening) gives E; E goes back to the markers with the
+ * same area weighting.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every array argument is DEVICE memory owned by the caller unless its name
+ *    ends in _host.  libavl never allocates or frees device memory; all of its
+ *    device state lives in the caller's workspace.  The handle itself is a
+ *    small host object owned by libavl and released by avl_destroy.
+ *  - Work is enqueued on the handle's HIP stream (hipStream_t passed as void*,
+ *    NULL = legacy default stream) and is asynchronous unless stated; results
+ *    are valid after the stream is synchronised.  Calls on one handle are not
+ *    thread-safe; distinct handles are independent.
+ *  - Grid layout (Sec. 3.1, Fig. "phasespace"): x in [0, L) periodic with nx
+ *    cells (dx = L/nx); velocity component d has nv[d] cells on
+ *    [vmin[d], vmax[d]); all grid values sit at cell centres.  Phase-space
+ *    arrays are velocity-major, index ((jz*nv[1] + jy)*nv[0] + jx)*nx + i
+ *    (1D-1V: j*nx + i).  Spatial arrays (rho, E) have nx entries.
+ *  - Marker arrays are structure-of-arrays FP64: x[n], v[vdim*n] (component d
+ *    of marker l at v[d*n + l]), f[n] (the phase-space density each marker
+ *    carries, its "weight" in the paper's words, Sec. 2).
+ *  - Units are the caller's: acceleration is (q/m) E, Poisson's equation is
+ *    dE/dx = c_p * rho (c_p = 4*pi in the paper's CGS units, Eq. (poisson)).
+ *  - Return values: AVL_OK (0) or a negative avl_status.  Host-side validation
+ *    runs before anything is enqueued, so an error return leaves the handle and
+ *    the device untouched, except AVL_EDEVICE (a HIP call failed).
+ */
+#ifndef AVL_H_
+#define AVL_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#pragma GCC visibility push(default)
+#endif
+
+typedef enum {
+    AVL_OK = 0,
+    AVL_EINVAL = -1,      /* bad argument or configuration value */
+    AVL_ESIZE = -2,       /* workspace too small, or a size over the supported range */
+    AVL_EALIGN = -3,      /* workspace not 256-byte aligned, or an array not 8-byte aligned */
+    AVL_ESTATE = -4,      /* call not valid in the handle's current state */
+    AVL_EDEVICE = -5,     /* a HIP runtime call failed */
+    AVL_ENOTSUP = -6,     /* configuration outside what this build implements */
+    AVL_ENONFINITE = -7,  /* device kernels saw a non-finite marker or field value */
+    AVL_EINTERNAL = -8    /* device consistency check failed (sort slots, encoding range) */
+} avl_status;
+
+/* Marker storage form.
+ *  AVL_FP64: plain form, markers and grid in FP64.
+ *  AVL_FP32: each marker stores the integer index of the cell whose centre is
+ *            its lower-left cloud neighbour plus FP32 offsets in [0,1) from that
+ *            centre (a along x, b along each velocity component) and an FP32 f;
+ *            reconstruction sums N and D in FP32 with compensated (Kahan)
+ *            summation; rho and the field solve stay FP64. */
+typedef enum { AVL_FP64 = 0, AVL_FP32 = 1 } avl_precision;
+
+typedef struct avl_config {
+    int32_t vdim;        /* 1 (1D-1V) or 3 (1D-3V) */
+    int32_t nx;          /* power of two in [8, 4096] */
+    int32_t nv[3];       /* velocity cells per component, each >= 2 (only [0, vdim) used) */
+    int32_t precision;   /* avl_precision */
+    int32_t first_kick;  /* 0: first velocity update is a full dt from v^0; 1: half dt */
+    int32_t reserved;    /* must be 0 */
+    int64_t n_markers;   /* number of markers n, 0 <= n < 2^31 */
+    double L;            /* domain length, finite > 0 */
+    double vmin[3];      /* lower velocity bound per component */
+    double vmax[3];      /* upper velocity bound, > vmin */
+    double dt;           /* time step, finite > 0 */
+    double q;            /* species charge (enters rho) */
+    double m;            /* species mass (acceleration is q/m * E), finite != 0 */
+    double c_p;          /* Poisson constant, finite > 0 */
+} avl_config;
+
+typedef struct avl_handle avl_handle;
+
+/* Bytes of device workspace a handle for `cfg` needs (0 if cfg is invalid).
+ * Holds two marker buffers (the sort is out of place), per-cell counts and
+ * offsets, the f grid, partial and final rho, E, the field-solve tables and a
+ * diagnostics ring. */
+size_t avl_workspace_bytes(const avl_config* cfg);
+
+/* Create a handle and load the markers (Sec. 2 marker loading; Sec. 3.1: the
+ * field starts from the loaded state).  Copies x, v, f (FP64, n markers, SoA as
+ * above; x must lie in [0, L)) into `workspace` (>= avl_workspace_bytes,
+ * 256-byte aligned, caller-owned for the handle's lifetime), converting to the
+ * FP32 form if asked, sorts them by cell, then computes f^0, rho^0 and E^0 so
+ * that the first avl_step pushes with E^0.  `stream` is a hipStream_t.
+ * Synchronises the stream once to check the loaded markers: returns
+ * AVL_EINVAL if an x lies outside [0, L) or any value is non-finite. */
+int avl_init(const avl_config* cfg, void* workspace, size_t ws_bytes, void* stream,
+             const double* x, const double* v, const double* f, avl_handle** out);
+
+/* Gather and push (Sec. 2, the final paragraph of the method overview): each
+ * marker gets E at its position by the same area weighting as the
+ * reconstruction, then v += (q/m) E dt (x velocity only) and x += v dt, wrapped
+ * into [0, L).  Uses E (nx values) if non-NULL, else the handle's current
+ * field.  Marker order is preserved; the handle's f, rho and E become stale.
+ * The first push after avl_init uses a half kick when cfg.first_kick = 1. */
+int avl_push(avl_handle* h, const double* E);
+
+/* Reorder the markers by cell (a counting sort keyed on the cell whose centre
+ * is each marker's lower-left cloud neighbour).  Needed before a
+ * reconstruction; avl_reconstruct calls it itself when the order is stale. */
+int avl_sort(avl_handle* h);
+
+/* Weight-normalised reconstruction, Eq. (reconstruction): for every phase
+ * cell g, N_g = sum_l alpha_gl f_l, D_g = sum_l alpha_gl, f_g = N_g / D_g with
+ * cloud-in-cell area weights alpha (Sec. 2, Fig. "interpolation"); x periodic,
+ * cloud parts outside the velocity range dropped; f_g = 0 where D_g = 0.
+ * f_out and D_out (may be NULL) receive G = nx*prod(nv) values in the storage
+ * precision (double for AVL_FP64, float for AVL_FP32). */
+int avl_reconstruct(avl_handle* h, void* f_out, void* D_out);
+
+/* Charge-density moment (Sec. 2 overview; Sec. 3.4 spatial output):
+ * rho_i = q * prod(dv) * sum over velocity cells of f at x cell i, FP64, from
+ * the last reconstruction.  rho_out (may be NULL) receives nx doubles.
+ * AVL_ESTATE if f is stale (markers pushed since the last reconstruction). */
+int avl_moments(avl_handle* h, double* rho_out);
+
+/* Spectral field solve, Eq. (poissonk) with Eq. (kappasoftening): E_hat_m =
+ * -i c_p kappa_m / K_m^2 rho_hat_m, kappa = k sinc(k dx), K^2 = k^2
+ * sinc^2(k dx/2), E_hat_0 = 0 (DC removal) and the Nyquist mode zeroed.  Takes
+ * rho (nx doubles) or, if NULL, the handle's rho from avl_moments.  The result
+ * becomes the handle's field; E_out (nx doubles) and W_out (1 double: the field
+ * energy sum E_i^2 dx / (2 c_p), Sec. 3.4) may be NULL.  FP64 throughout. */
+int avl_poisson(avl_handle* h, const double* rho, double* E_out, double* W_out);
+
+/* `nsteps` full steps: gather+push with E^n, sort, reconstruct f^{n+1},
+ * rho^{n+1}, solve E^{n+1}.  diag_out (may be NULL) receives 2*nsteps doubles,
+ * per step the field energy W and the amplitude (2/nx)|sum_i E_i e^{-2 pi i
+ * i/nx}| of the longest-wavelength mode of E (Sec. 4.2).  AVL_ESTATE unless
+ * the handle holds a current field (after avl_init, avl_poisson or a step). */
+int avl_step(avl_handle* h, int32_t nsteps, double* diag_out);
+
+/* Same as avl_step, replaying a HIP graph of one step captured on first use
+ * (a fixed launch sequence; identical results to avl_step). */
+int avl_step_graph(avl_handle* h, int32_t nsteps, double* diag_out);
+
+/* Export the markers in FP64 (SoA as in avl_init) in the current storage
+ * order.  The FP32 form is converted: x = (i + 1/2 + a) dx, v = vmin + (j +
+ * 1/2 + b) dv with (i, j) the stored cell. */
+int avl_get_markers(avl_handle* h, double* x, double* v, double* f);
+
+/* Replace the markers (FP64 SoA, same count, x in [0, L)); the order becomes
+ * stale and f, rho, E are recomputed as in avl_init.  Synchronises. */
+int avl_set_markers(avl_handle* h, const double* x, const double* v, const double* f);
+
+/* Copy the handle's current field (nx doubles) and charge density. */
+int avl_get_field(avl_handle* h, double* E_out, double* rho_out);
+
+/* Number of full steps taken since the markers were loaded. */
+int64_t avl_step_count(const avl_handle* h);
+
+/* Synchronise the stream and report sticky device-side conditions:
+ * AVL_ENONFINITE, AVL_EINTERNAL or AVL_OK. */
+int avl_check(avl_handle* h);
+
+/* Rebind the handle to another stream (hipStream_t). */
+int avl_set_stream(avl_handle* h, void* stream);
+
+/* Kernel timing with HIP events recorded on the handle's stream around every
+ * launch of the named kernel class while enabled (see AVL_K_* below).
+ * avl_kernel_time synchronises and returns the summed milliseconds and the
+ * number of launches since timing was enabled. */
+enum { AVL_K_PUSH_COUNT = 0, AVL_K_SCAN = 1, AVL_K_SCATTER = 2, AVL_K_RECONSTRUCT = 3,
+       AVL_K_FIELD = 4, AVL_K_STEP = 5, AVL_K_COUNT = 6 };
+int avl_timing(avl_handle* h, int enable);
+int avl_kernel_time(avl_handle* h, int kernel, double* ms_total, int64_t* launches);
+
+/* Algorithmic bytes one launch of the named kernel class moves for this
+ * handle's configuration (what the method must read and write, excluding
+ * re-reads): used to express achieved bandwidth. */
+double avl_kernel_bytes(const avl_handle* h, int kernel);
+
+/* Measurement aid: copy `bytes` (multiple of 16) from src to dst with a plain
+ * streaming kernel on `stream`; calibrates achievable HBM bandwidth and the
+ * hardware byte counters. */
+int avl_copy_probe(void* dst, const void* src, size_t bytes, void* stream);
+
+/* Text for a status code. */
+const char* avl_strerror(int status);
+
+/* Release the handle (host memory only; the workspace stays the caller's). */
+int avl_destroy(avl_handle* h);
+
+#if defined(__GNUC__)
+#pragma GCC visibility pop
+#endif
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AVL_H_ */

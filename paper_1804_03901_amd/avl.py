@@ -1,0 +1,332 @@
+"""Python binding of libavl: argument marshalling only.
+
+Every entry point of ``include/avl.h`` is exposed under the same name and takes
+torch tensors (device memory) or plain numbers; the work runs in the HIP
+kernels of ``libavl.so``.  PyTorch provides device memory and the stream.  If
+the library has not been built, loading fails loudly: there is no fallback.
+
+``Simulation`` bundles one handle with its torch-owned workspace.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+from . import inputs
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libavl.so")
+
+AVL_FP64 = 0
+AVL_FP32 = 1
+K_PUSH_COUNT, K_SCAN, K_SCATTER, K_RECONSTRUCT, K_FIELD, K_STEP = range(6)
+KERNEL_NAMES = ["push_count", "scan", "scatter", "reconstruct", "field", "step"]
+
+STATUS = {0: "AVL_OK", -1: "AVL_EINVAL", -2: "AVL_ESIZE", -3: "AVL_EALIGN", -4: "AVL_ESTATE",
+          -5: "AVL_EDEVICE", -6: "AVL_ENOTSUP", -7: "AVL_ENONFINITE", -8: "AVL_EINTERNAL"}
+
+
+class AvlError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({strerror(status)})")
+
+
+class AvlConfig(ctypes.Structure):
+    _fields_ = [
+        ("vdim", ctypes.c_int32), ("nx", ctypes.c_int32), ("nv", ctypes.c_int32 * 3),
+        ("precision", ctypes.c_int32), ("first_kick", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("n_markers", ctypes.c_int64), ("L", ctypes.c_double),
+        ("vmin", ctypes.c_double * 3), ("vmax", ctypes.c_double * 3),
+        ("dt", ctypes.c_double), ("q", ctypes.c_double), ("m", ctypes.c_double), ("c_p", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+EXPORTS = ["avl_workspace_bytes", "avl_init", "avl_push", "avl_sort", "avl_reconstruct", "avl_moments",
+           "avl_poisson", "avl_step", "avl_step_graph", "avl_get_markers", "avl_set_markers", "avl_get_field",
+           "avl_step_count", "avl_check", "avl_set_stream", "avl_timing", "avl_kernel_time", "avl_kernel_bytes",
+           "avl_copy_probe", "avl_strerror", "avl_destroy"]
+
+
+def load(path: str = LIB_PATH):
+    """Load libavl.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libavl is not built ({path} missing): run paper_1804_03901_amd/build.py")
+    lib = ctypes.CDLL(path)
+    vp, c = ctypes.c_void_p, ctypes
+    P = ctypes.POINTER
+    lib.avl_workspace_bytes.argtypes = [P(AvlConfig)]
+    lib.avl_workspace_bytes.restype = c.c_size_t
+    lib.avl_init.argtypes = [P(AvlConfig), vp, c.c_size_t, vp, vp, vp, vp, P(vp)]
+    lib.avl_push.argtypes = [vp, vp]
+    lib.avl_sort.argtypes = [vp]
+    lib.avl_reconstruct.argtypes = [vp, vp, vp]
+    lib.avl_moments.argtypes = [vp, vp]
+    lib.avl_poisson.argtypes = [vp, vp, vp, vp]
+    lib.avl_step.argtypes = [vp, c.c_int32, vp]
+    lib.avl_step_graph.argtypes = [vp, c.c_int32, vp]
+    lib.avl_get_markers.argtypes = [vp, vp, vp, vp]
+    lib.avl_set_markers.argtypes = [vp, vp, vp, vp]
+    lib.avl_get_field.argtypes = [vp, vp, vp]
+    lib.avl_step_count.argtypes = [vp]
+    lib.avl_step_count.restype = c.c_int64
+    lib.avl_check.argtypes = [vp]
+    lib.avl_set_stream.argtypes = [vp, vp]
+    lib.avl_timing.argtypes = [vp, c.c_int]
+    lib.avl_kernel_time.argtypes = [vp, c.c_int, P(c.c_double), P(c.c_int64)]
+    lib.avl_kernel_bytes.argtypes = [vp, c.c_int]
+    lib.avl_kernel_bytes.restype = c.c_double
+    lib.avl_copy_probe.argtypes = [vp, vp, c.c_size_t, vp]
+    lib.avl_strerror.argtypes = [c.c_int]
+    lib.avl_strerror.restype = c.c_char_p
+    lib.avl_destroy.argtypes = [vp]
+    for name in EXPORTS:
+        if name not in ("avl_workspace_bytes", "avl_step_count", "avl_kernel_bytes", "avl_strerror"):
+            getattr(lib, name).restype = c.c_int
+    _lib = lib
+    return lib
+
+
+def strerror(status: int) -> str:
+    return load().avl_strerror(int(status)).decode()
+
+
+def _ck(rc: int, where: str) -> int:
+    if rc != 0:
+        raise AvlError(rc, where)
+    return rc
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def make_config(w: "inputs.Workload", precision: int = AVL_FP64, n_markers: Optional[int] = None) -> AvlConfig:
+    c = AvlConfig()
+    c.vdim = w.vdim
+    c.nx = w.nx
+    for d in range(3):
+        c.nv[d] = w.nv[d] if d < w.vdim else 1
+        c.vmin[d] = w.vmin[d] if d < w.vdim else 0.0
+        c.vmax[d] = w.vmax[d] if d < w.vdim else 1.0
+    c.precision = precision
+    c.first_kick = w.first_kick
+    c.reserved = 0
+    c.n_markers = w.n_markers if n_markers is None else n_markers
+    c.L = w.L
+    c.dt, c.q, c.m, c.c_p = w.dt, w.q, w.m, w.c_p
+    return c
+
+
+# ---------------------------------------------------------------------------
+# Entry points under their C names (tensors in, status checked).
+# ---------------------------------------------------------------------------
+
+def avl_workspace_bytes(cfg: AvlConfig) -> int:
+    return int(load().avl_workspace_bytes(ctypes.byref(cfg)))
+
+
+def avl_init(cfg: AvlConfig, workspace, stream, x, v, f) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _ck(load().avl_init(ctypes.byref(cfg), _ptr(workspace), workspace.numel() * workspace.element_size(),
+                        _stream_ptr(stream), _ptr(x), _ptr(v), _ptr(f), ctypes.byref(h)), "avl_init")
+    return h
+
+
+def avl_push(h, E=None):
+    return _ck(load().avl_push(h, _ptr(E)), "avl_push")
+
+
+def avl_sort(h):
+    return _ck(load().avl_sort(h), "avl_sort")
+
+
+def avl_reconstruct(h, f_out=None, D_out=None):
+    return _ck(load().avl_reconstruct(h, _ptr(f_out), _ptr(D_out)), "avl_reconstruct")
+
+
+def avl_moments(h, rho_out=None):
+    return _ck(load().avl_moments(h, _ptr(rho_out)), "avl_moments")
+
+
+def avl_poisson(h, rho=None, E_out=None, W_out=None):
+    return _ck(load().avl_poisson(h, _ptr(rho), _ptr(E_out), _ptr(W_out)), "avl_poisson")
+
+
+def avl_step(h, nsteps: int, diag_out=None):
+    return _ck(load().avl_step(h, int(nsteps), _ptr(diag_out)), "avl_step")
+
+
+def avl_step_graph(h, nsteps: int, diag_out=None):
+    return _ck(load().avl_step_graph(h, int(nsteps), _ptr(diag_out)), "avl_step_graph")
+
+
+def avl_get_markers(h, x, v, f):
+    return _ck(load().avl_get_markers(h, _ptr(x), _ptr(v), _ptr(f)), "avl_get_markers")
+
+
+def avl_set_markers(h, x, v, f):
+    return _ck(load().avl_set_markers(h, _ptr(x), _ptr(v), _ptr(f)), "avl_set_markers")
+
+
+def avl_get_field(h, E_out=None, rho_out=None):
+    return _ck(load().avl_get_field(h, _ptr(E_out), _ptr(rho_out)), "avl_get_field")
+
+
+def avl_step_count(h) -> int:
+    return int(load().avl_step_count(h))
+
+
+def avl_check(h) -> int:
+    return int(load().avl_check(h))
+
+
+def avl_set_stream(h, stream):
+    return _ck(load().avl_set_stream(h, _stream_ptr(stream)), "avl_set_stream")
+
+
+def avl_timing(h, enable: bool):
+    return _ck(load().avl_timing(h, int(bool(enable))), "avl_timing")
+
+
+def avl_kernel_time(h, kernel: int):
+    ms = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    _ck(load().avl_kernel_time(h, int(kernel), ctypes.byref(ms), ctypes.byref(cnt)), "avl_kernel_time")
+    return ms.value, cnt.value
+
+
+def avl_kernel_bytes(h, kernel: int) -> float:
+    return float(load().avl_kernel_bytes(h, int(kernel)))
+
+
+def avl_copy_probe(dst, src, nbytes: int, stream=None):
+    return _ck(load().avl_copy_probe(_ptr(dst), _ptr(src), int(nbytes), _stream_ptr(stream)), "avl_copy_probe")
+
+
+def avl_destroy(h):
+    return _ck(load().avl_destroy(h), "avl_destroy")
+
+
+# ---------------------------------------------------------------------------
+# Convenience wrapper
+# ---------------------------------------------------------------------------
+
+class Simulation:
+    """One VHS species on one GPU: owns a torch workspace and a libavl handle."""
+
+    def __init__(self, w: "inputs.Workload", x, v, f, precision: int = AVL_FP64, device: str = "cuda:0",
+                 stream=None):
+        import torch
+        self.w = w
+        self.device = torch.device(device)
+        self.precision = precision
+        x = torch.as_tensor(x, dtype=torch.float64, device=self.device).contiguous()
+        v = torch.as_tensor(v, dtype=torch.float64, device=self.device).reshape(-1).contiguous()
+        f = torch.as_tensor(f, dtype=torch.float64, device=self.device).contiguous()
+        self.n = x.numel()
+        self.cfg = make_config(w, precision, self.n)
+        nbytes = avl_workspace_bytes(self.cfg)
+        if nbytes == 0:
+            raise AvlError(-1, "avl_workspace_bytes")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self.workspace = self.workspace[off:off + nbytes]
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.h = avl_init(self.cfg, self.workspace, self.stream, x, v, f)
+        self._grid_dtype = torch.float64 if precision == AVL_FP64 else torch.float32
+
+    # shapes ---------------------------------------------------------------
+    @property
+    def grid_shape(self):
+        w = self.w
+        return tuple(w.nv[d] for d in reversed(range(w.vdim))) + (w.nx,)
+
+    def _empty(self, n, dtype=None):
+        import torch
+        return torch.empty(n, dtype=dtype or torch.float64, device=self.device)
+
+    # stages ---------------------------------------------------------------
+    def push(self, E=None):
+        avl_push(self.h, E)
+
+    def sort(self):
+        avl_sort(self.h)
+
+    def reconstruct(self, want_D: bool = False):
+        import math
+        G = math.prod(self.grid_shape)
+        fo = self._empty(G, self._grid_dtype)
+        Do = self._empty(G, self._grid_dtype) if want_D else None
+        avl_reconstruct(self.h, fo, Do)
+        fo = fo.reshape(self.grid_shape)
+        return (fo, Do.reshape(self.grid_shape)) if want_D else fo
+
+    def moments(self):
+        rho = self._empty(self.w.nx)
+        avl_moments(self.h, rho)
+        return rho
+
+    def poisson(self, rho=None):
+        E = self._empty(self.w.nx)
+        W = self._empty(1)
+        avl_poisson(self.h, rho, E, W)
+        return E, W
+
+    def step(self, nsteps: int, graph: bool = False, diag: bool = True):
+        d = self._empty(2 * max(nsteps, 1)) if diag else None
+        (avl_step_graph if graph else avl_step)(self.h, nsteps, d)
+        return d[: 2 * nsteps].reshape(nsteps, 2) if diag else None
+
+    def markers(self):
+        x = self._empty(self.n)
+        v = self._empty(self.n * self.w.vdim)
+        f = self._empty(self.n)
+        avl_get_markers(self.h, x, v, f)
+        return x, v.reshape(self.w.vdim, self.n), f
+
+    def set_markers(self, x, v, f):
+        import torch
+        x = torch.as_tensor(x, dtype=torch.float64, device=self.device).contiguous()
+        v = torch.as_tensor(v, dtype=torch.float64, device=self.device).reshape(-1).contiguous()
+        f = torch.as_tensor(f, dtype=torch.float64, device=self.device).contiguous()
+        avl_set_markers(self.h, x, v, f)
+
+    def field(self):
+        E = self._empty(self.w.nx)
+        rho = self._empty(self.w.nx)
+        avl_get_field(self.h, E, rho)
+        return E, rho
+
+    def check(self):
+        _ck(avl_check(self.h), "avl_check")
+
+    @property
+    def steps(self) -> int:
+        return avl_step_count(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            avl_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,757 @@
+// libavl host side: configuration checks, workspace layout, launch order of
+// the time step (Sec. 2, Fig. "algorithm"), HIP-graph replay and timing.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/avl.h"
+#include "avl_device.h"
+
+namespace avl {
+hipError_t launch_sort(const Geo& g, void* src, void* dst, const double* E, const RowShift* rows, double dtk,
+                       float bk, int* counts, int* offsets, int* tile_sums, int* flags, bool push, hipStream_t st,
+                       int phase);
+hipError_t launch_push(const Geo& g, void* m, const double* E, const RowShift* rows, double dtk, float bk,
+                       int* flags, hipStream_t st);
+hipError_t launch_recon(const Geo& g, void* m, const int* offsets, void* fgrid, void* Dgrid, double* rho_part,
+                        hipStream_t st);
+hipError_t launch_recon3(const Geo& g, void* m, const int* offsets, void* fgrid, void* Dgrid, double* rho_part,
+                         void* scratch, hipStream_t st);
+hipError_t launch_field(const Geo& g, const double* rho_part, const double* rho_in, double* rho_out, double* E_out,
+                        const double2* tw, const double* green, double* diag_ring, long long* step_ctr,
+                        int write_diag, double* W_out, int* flags, int solve, hipStream_t st);
+hipError_t launch_validate(const Geo& g, const double* x, const double* v, const double* f, int* bad,
+                           hipStream_t st);
+hipError_t launch_to32(const Geo& g, const double* x, const double* v, const double* f, M32 m, int* flags,
+                       hipStream_t st);
+hipError_t launch_to64(const Geo& g, M32 m, double* x, double* v, double* f, hipStream_t st);
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
+size_t recon3_scratch_bytes(const Geo& g);
+}  // namespace avl
+
+using namespace avl;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+struct Layout {
+    size_t markers[2], counts, offsets, tile_sums, fgrid, rho_part, rho, E, tw, green, rows, diag, ctr, flags, bad,
+        scratch3, total;
+};
+
+int ilog2(int v)
+{
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Validate a configuration and derive the kernel constants.
+int make_geo(const avl_config* c, Geo* g)
+{
+    if (!c) return AVL_EINVAL;
+    std::memset(g, 0, sizeof(Geo));
+    if (c->vdim != 1 && c->vdim != 3) return AVL_EINVAL;
+    if (c->vdim == 3) return AVL_ENOTSUP;
+    if (c->nx < 8 || c->nx > kMaxNx || (c->nx & (c->nx - 1))) return AVL_EINVAL;
+    if (c->precision != AVL_FP64 && c->precision != AVL_FP32) return AVL_EINVAL;
+    if (c->first_kick != 0 && c->first_kick != 1) return AVL_EINVAL;
+    if (c->reserved != 0) return AVL_EINVAL;
+    if (c->n_markers < 0 || c->n_markers >= (int64_t)INT32_MAX) return AVL_ESIZE;
+    if (!finite_pos(c->L) || !finite_pos(c->dt) || !finite_pos(c->c_p)) return AVL_EINVAL;
+    if (!std::isfinite(c->q) || !std::isfinite(c->m) || c->m == 0.0) return AVL_EINVAL;
+    g->vdim = c->vdim;
+    g->prec = c->precision;
+    g->nx = c->nx;
+    g->lognx = ilog2(c->nx);
+    int64_t rows = 1, cells = c->nx;
+    double vol = 1.0;
+    for (int d = 0; d < c->vdim; ++d) {
+        if (c->nv[d] < 2 || c->nv[d] > (1 << 20)) return AVL_EINVAL;
+        if (!std::isfinite(c->vmin[d]) || !std::isfinite(c->vmax[d]) || !(c->vmax[d] > c->vmin[d]))
+            return AVL_EINVAL;
+        g->nv[d] = c->nv[d];
+        rows *= (c->nv[d] + 1);
+        cells *= c->nv[d];
+        g->vmin[d] = c->vmin[d];
+        g->dv[d] = (c->vmax[d] - c->vmin[d]) / c->nv[d];
+        g->inv_dv[d] = 1.0 / g->dv[d];
+        vol *= g->dv[d];
+    }
+    for (int d = c->vdim; d < 3; ++d) g->nv[d] = 1;
+    if (rows * c->nx + 2 >= (int64_t)INT32_MAX || cells >= (int64_t)INT32_MAX) return AVL_ESIZE;
+    g->nrow = (int)rows;
+    g->nb = (int)(rows * c->nx);
+    g->n = (int)c->n_markers;
+    g->L = c->L;
+    g->inv_L = 1.0 / c->L;
+    g->dx = c->L / c->nx;
+    g->inv_dx = 1.0 / g->dx;
+    g->dt = c->dt;
+    g->qm = c->q / c->m;
+    g->cp = c->c_p;
+    g->q_vol = c->q * vol;
+    g->bscale = (float)(g->qm * c->dt * g->inv_dv[0]);
+    g->gam = (float)(g->dv[0] * c->dt * g->inv_dx);
+    g->c0f = (float)(c->vmin[0] * g->inv_dv[0] + 0.5);
+    // sort window: at least three bucket rows
+    g->hist_bins = std::max(8192, 3 * c->nx);
+    // reconstruction decomposition
+    if (c->vdim == 1) {
+        g->nstrip = (c->nx + kReconCols - 1) / kReconCols;
+        int want_chunks = std::max(1, 2048 / g->nstrip);
+        int rc = std::max(2, std::min(32, c->nv[0] / want_chunks));
+        g->rc = rc;
+        g->nchunk = (c->nv[0] + rc - 1) / rc;
+        const size_t esz = c->precision ? 4 : 8;
+        const int budget = (int)((160 * 1024 - 1024) / (kReconWaves * 3 * esz));
+        double per_run = c->n_markers > 0 ? (double)c->n_markers / (double)g->nb : 0.0;
+        int expect = (int)(kWave * per_run);
+        int cap = std::max(512, 2 * expect + 256);
+        cap = std::min(budget, ((cap + 63) / 64) * 64);
+        g->cap = std::max(64, cap);
+    } else {
+        // 1D-3V FP32 encoding of the x-velocity dual index
+        int jr = 1;
+        while (jr < c->nv[0] + 1 + 64) jr <<= 1;
+        g->jrange = jr;
+        g->jpad = (jr - (c->nv[0] + 1)) / 2;
+        if ((int64_t)jr * (c->nv[1] + 1) * (c->nv[2] + 1) * c->nx >= (int64_t)INT32_MAX) {
+            if (c->precision == AVL_FP32) return AVL_ENOTSUP;
+        }
+        g->nstrip = 0;
+        g->rc = 1;
+        g->nchunk = (int)(rows / (c->nv[0] + 1));   // one partial per (vy, vz) plane of dual rows
+        g->cap = 0;
+    }
+    return AVL_OK;
+}
+
+void make_layout(const avl_config* c, const Geo& g, Layout* L)
+{
+    size_t n = (size_t)g.n;
+    size_t mbytes = c->precision == AVL_FP64 ? sizeof(double) * n * (2 + g.vdim) : 4 * n * (3 + g.vdim);
+    size_t esz = c->precision == AVL_FP64 ? 8 : 4;
+    size_t cells = (size_t)g.nx;
+    for (int d = 0; d < g.vdim; ++d) cells *= g.nv[d];
+    size_t nbt = (size_t)g.nb + 1;
+    size_t ntiles = (nbt + kScanTile - 1) / kScanTile;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+    L->markers[0] = take(mbytes + 64 * (3 + g.vdim));
+    L->markers[1] = take(mbytes + 64 * (3 + g.vdim));
+    L->counts = take(sizeof(int) * nbt);
+    L->offsets = take(sizeof(int) * (nbt + 1));
+    L->tile_sums = take(sizeof(int) * (ntiles + 1));
+    L->fgrid = take(esz * cells);
+    L->rho_part = take(sizeof(double) * (size_t)std::max(1, g.nchunk) * g.nx);
+    L->rho = take(sizeof(double) * g.nx);
+    L->E = take(sizeof(double) * g.nx);
+    L->tw = take(sizeof(double) * g.nx);
+    L->green = take(sizeof(double) * g.nx);
+    L->rows = take(sizeof(RowShift) * (g.nv[0] + 1));
+    L->diag = take(sizeof(double) * 2 * kDiagCap);
+    L->ctr = take(sizeof(long long));
+    L->flags = take(sizeof(int));
+    L->bad = take(sizeof(int));
+    L->scratch3 = take(g.vdim == 3 ? recon3_scratch_bytes(g) : 0);
+    L->total = off;
+}
+
+}  // namespace
+
+struct avl_handle {
+    avl_config cfg;
+    Geo g;
+    Layout lay;
+    hipStream_t st;
+    char* ws;
+    M64 m64[2];
+    M32 m32[2];
+    int cur;
+    int *counts, *offsets, *tile_sums, *flags, *bad;
+    void* fgrid;
+    double *rho_part, *rho, *E, *green, *diag;
+    double2* tw;
+    RowShift* rows;
+    long long* ctr;
+    void* scratch3;
+    bool sorted, have_f, have_rho, have_E;
+    bool kicked;        // a push has happened since loading (first-kick rule)
+    int64_t steps;      // steps enqueued since loading (mirrors the device counter)
+    hipGraphExec_t gexec[2];
+    bool graph_ok;
+    bool timing;
+    std::vector<hipEvent_t> ev[AVL_K_COUNT];
+    size_t ev_used[AVL_K_COUNT];
+};
+
+namespace {
+
+void* marker_view(avl_handle* h, int which)
+{
+    return h->g.prec == AVL_FP64 ? (void*)&h->m64[which] : (void*)&h->m32[which];
+}
+
+void set_views(avl_handle* h)
+{
+    const size_t n = (size_t)h->g.n;
+    for (int b = 0; b < 2; ++b) {
+        char* p = h->ws + h->lay.markers[b];
+        if (h->g.prec == AVL_FP64) {
+            double* d = reinterpret_cast<double*>(p);
+            h->m64[b].x = d;
+            h->m64[b].v = d + n;
+            h->m64[b].f = d + n * (1 + h->g.vdim);
+        } else {
+            int* c = reinterpret_cast<int*>(p);
+            h->m32[b].cell = c;
+            h->m32[b].a = reinterpret_cast<float*>(c + n);
+            h->m32[b].b = reinterpret_cast<float*>(c + 2 * n);
+            h->m32[b].f = reinterpret_cast<float*>(c + n * (2 + h->g.vdim));
+        }
+    }
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? AVL_OK : AVL_EDEVICE; }
+
+#define AVL_TRY(expr)                          \
+    do {                                       \
+        hipError_t e_ = (expr);                \
+        if (e_ != hipSuccess) return AVL_EDEVICE; \
+    } while (0)
+
+struct Timer {
+    avl_handle* h;
+    int k;
+    hipEvent_t stop;
+    Timer(avl_handle* hh, int kk) : h(hh), k(kk), stop(nullptr)
+    {
+        if (!h->timing) return;
+        std::vector<hipEvent_t>& v = h->ev[k];
+        if (h->ev_used[k] + 2 > v.size()) {
+            for (int i = 0; i < 64; ++i) {
+                hipEvent_t e;
+                if (hipEventCreate(&e) != hipSuccess) return;
+                v.push_back(e);
+            }
+        }
+        (void)hipEventRecord(v[h->ev_used[k]], h->st);
+        stop = v[h->ev_used[k] + 1];
+        h->ev_used[k] += 2;
+    }
+    ~Timer()
+    {
+        if (stop) (void)hipEventRecord(stop, h->st);
+    }
+};
+
+double kick_fraction(avl_handle* h) { return (!h->kicked && h->cfg.first_kick) ? 0.5 : 1.0; }
+
+// Host tables: FFT twiddles, the field solve's transfer function and the FP32
+// drift table; written into the workspace at load time.
+int upload_tables(avl_handle* h)
+{
+    const Geo& g = h->g;
+    const int nx = g.nx;
+    std::vector<double> tw(nx), green(nx);
+    for (int k = 0; k < nx / 2; ++k) {
+        const double ang = 2.0 * M_PI * (double)k / (double)nx;
+        tw[2 * k] = std::cos(ang);
+        tw[2 * k + 1] = -std::sin(ang);
+    }
+    // Eq. (kappasoftening): kappa = k sinc(k dx), K^2 = k^2 sinc^2(k dx / 2)
+    for (int m = 0; m < nx; ++m) {
+        if (m == 0 || 2 * m == nx) { green[m] = 0.0; continue; }
+        const int mp = (2 * m < nx) ? m : m - nx;
+        const double k = 2.0 * M_PI * mp / g.L;
+        const double y = k * g.dx;
+        const double kappa = k * (std::sin(y) / y);
+        const double s = std::sin(0.5 * y) / (0.5 * y);
+        const double K2 = k * k * s * s;
+        green[m] = g.cp * kappa / K2;
+    }
+    std::vector<RowShift> rows(g.nv[0] + 1);
+    for (int jp = 0; jp <= g.nv[0]; ++jp) {
+        const double vel = g.vmin[0] + ((double)(jp - 1) + 0.5) * g.dv[0];
+        const double P = vel * g.dt / g.dx;
+        double w = std::floor(P);
+        float fr = (float)(P - w);
+        if (fr >= 1.0f) { fr = 0.0f; w += 1.0; }
+        rows[jp].whole = (int)w;
+        rows[jp].frac = fr;
+    }
+    AVL_TRY(hipMemcpyAsync(h->tw, tw.data(), sizeof(double) * nx, hipMemcpyHostToDevice, h->st));
+    AVL_TRY(hipMemcpyAsync(h->green, green.data(), sizeof(double) * nx, hipMemcpyHostToDevice, h->st));
+    AVL_TRY(hipMemcpyAsync(h->rows, rows.data(), sizeof(RowShift) * rows.size(), hipMemcpyHostToDevice, h->st));
+    AVL_TRY(hipStreamSynchronize(h->st));
+    return AVL_OK;
+}
+
+int do_sort(avl_handle* h, bool push, double kick)
+{
+    const Geo& g = h->g;
+    void* src = marker_view(h, h->cur);
+    void* dst = marker_view(h, 1 - h->cur);
+    const double dtk = g.dt * kick;
+    const float bk = g.bscale * (float)kick;
+    {
+        Timer t(h, AVL_K_PUSH_COUNT);
+        AVL_TRY(launch_sort(g, src, dst, h->E, h->rows, dtk, bk, h->counts, h->offsets, h->tile_sums, h->flags,
+                            push, h->st, 0));
+    }
+    {
+        Timer t(h, AVL_K_SCAN);
+        AVL_TRY(launch_sort(g, src, dst, h->E, h->rows, dtk, bk, h->counts, h->offsets, h->tile_sums, h->flags,
+                            push, h->st, 1));
+    }
+    {
+        Timer t(h, AVL_K_SCATTER);
+        AVL_TRY(launch_sort(g, src, dst, h->E, h->rows, dtk, bk, h->counts, h->offsets, h->tile_sums, h->flags,
+                            push, h->st, 2));
+    }
+    h->cur = 1 - h->cur;
+    h->sorted = true;
+    if (push) h->kicked = true;
+    return AVL_OK;
+}
+
+int do_recon(avl_handle* h, void* Dgrid)
+{
+    Timer t(h, AVL_K_RECONSTRUCT);
+    if (h->g.vdim == 1)
+        AVL_TRY(launch_recon(h->g, marker_view(h, h->cur), h->offsets, h->fgrid, Dgrid, h->rho_part, h->st));
+    else
+        AVL_TRY(launch_recon3(h->g, marker_view(h, h->cur), h->offsets, h->fgrid, Dgrid, h->rho_part, h->scratch3,
+                              h->st));
+    h->have_f = true;
+    h->have_rho = false;
+    return AVL_OK;
+}
+
+int do_field(avl_handle* h, const double* rho_in, bool diag, double* W_out, bool solve = true)
+{
+    Timer t(h, AVL_K_FIELD);
+    AVL_TRY(launch_field(h->g, h->rho_part, rho_in, h->rho, h->E, h->tw, h->green, h->diag, h->ctr, diag ? 1 : 0,
+                         W_out, h->flags, solve ? 1 : 0, h->st));
+    h->have_rho = true;
+    if (solve) h->have_E = true;
+    return AVL_OK;
+}
+
+int one_step(avl_handle* h)
+{
+    Timer t(h, AVL_K_STEP);
+    int rc = do_sort(h, true, kick_fraction(h));
+    if (rc) return rc;
+    if ((rc = do_recon(h, nullptr))) return rc;
+    if ((rc = do_field(h, nullptr, true, nullptr))) return rc;
+    h->steps += 1;
+    return AVL_OK;
+}
+
+// Load FP64 markers into buffer `cur` (converting to the FP32 form if needed),
+// validate them, and rebuild f, rho, E.
+int load_markers(avl_handle* h, const double* x, const double* v, const double* f)
+{
+    const Geo& g = h->g;
+    const size_t n = (size_t)g.n;
+    if (n > 0 && (!x || !v || !f)) return AVL_EINVAL;
+    if (((uintptr_t)x | (uintptr_t)v | (uintptr_t)f) & 7) return AVL_EALIGN;
+    AVL_TRY(hipMemsetAsync(h->bad, 0, sizeof(int), h->st));
+    AVL_TRY(launch_validate(g, x, v, f, h->bad, h->st));
+    int bad = 0;
+    AVL_TRY(hipMemcpyAsync(&bad, h->bad, sizeof(int), hipMemcpyDeviceToHost, h->st));
+    AVL_TRY(hipStreamSynchronize(h->st));
+    if (bad) return AVL_EINVAL;
+    h->cur = 0;
+    if (n == 0) {
+        // nothing to copy
+    } else if (g.prec == AVL_FP64) {
+        AVL_TRY(hipMemcpyAsync(h->m64[0].x, x, sizeof(double) * n, hipMemcpyDeviceToDevice, h->st));
+        AVL_TRY(hipMemcpyAsync(h->m64[0].v, v, sizeof(double) * n * g.vdim, hipMemcpyDeviceToDevice, h->st));
+        AVL_TRY(hipMemcpyAsync(h->m64[0].f, f, sizeof(double) * n, hipMemcpyDeviceToDevice, h->st));
+    } else {
+        AVL_TRY(launch_to32(g, x, v, f, h->m32[0], h->flags, h->st));
+    }
+    const int total = g.n;
+    const size_t nbt = (size_t)g.nb + 1;
+    AVL_TRY(hipMemsetAsync(h->counts, 0, sizeof(int) * nbt, h->st));
+    AVL_TRY(hipMemcpyAsync(h->offsets + nbt, &total, sizeof(int), hipMemcpyHostToDevice, h->st));
+    AVL_TRY(hipMemsetAsync(h->ctr, 0, sizeof(long long), h->st));
+    AVL_TRY(hipStreamSynchronize(h->st));
+    h->steps = 0;
+    h->kicked = false;
+    h->sorted = false;
+    int rc;
+    if ((rc = do_sort(h, false, 1.0))) return rc;
+    if ((rc = do_recon(h, nullptr))) return rc;
+    if ((rc = do_field(h, nullptr, false, nullptr))) return rc;
+    return AVL_OK;
+}
+
+void drop_graphs(avl_handle* h)
+{
+    for (int b = 0; b < 2; ++b)
+        if (h->gexec[b]) {
+            (void)hipGraphExecDestroy(h->gexec[b]);
+            h->gexec[b] = nullptr;
+        }
+    h->graph_ok = false;
+}
+
+int copy_diag(avl_handle* h, int64_t first, int32_t count, double* out)
+{
+    int64_t done = 0;
+    while (done < count) {
+        int64_t pos = (first + done) % kDiagCap;
+        int64_t len = std::min<int64_t>(count - done, kDiagCap - pos);
+        AVL_TRY(hipMemcpyAsync(out + 2 * done, h->diag + 2 * pos, sizeof(double) * 2 * len, hipMemcpyDeviceToDevice,
+                               h->st));
+        done += len;
+    }
+    return AVL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t avl_workspace_bytes(const avl_config* cfg)
+{
+    Geo g;
+    if (make_geo(cfg, &g) != AVL_OK) return 0;
+    Layout L;
+    make_layout(cfg, g, &L);
+    return L.total;
+}
+
+int avl_init(const avl_config* cfg, void* workspace, size_t ws_bytes, void* stream, const double* x,
+             const double* v, const double* f, avl_handle** out)
+{
+    if (!out) return AVL_EINVAL;
+    *out = nullptr;
+    Geo g;
+    int rc = make_geo(cfg, &g);
+    if (rc) return rc;
+    Layout lay;
+    make_layout(cfg, g, &lay);
+    if (!workspace) return AVL_EINVAL;
+    if ((uintptr_t)workspace % kAlign) return AVL_EALIGN;
+    if (ws_bytes < lay.total) return AVL_ESIZE;
+    avl_handle* h = new (std::nothrow) avl_handle();
+    if (!h) return AVL_EINVAL;
+    h->cfg = *cfg;
+    h->g = g;
+    h->lay = lay;
+    h->st = (hipStream_t)stream;
+    h->ws = (char*)workspace;
+    set_views(h);
+    h->counts = (int*)(h->ws + lay.counts);
+    h->offsets = (int*)(h->ws + lay.offsets);
+    h->tile_sums = (int*)(h->ws + lay.tile_sums);
+    h->fgrid = h->ws + lay.fgrid;
+    h->rho_part = (double*)(h->ws + lay.rho_part);
+    h->rho = (double*)(h->ws + lay.rho);
+    h->E = (double*)(h->ws + lay.E);
+    h->tw = (double2*)(h->ws + lay.tw);
+    h->green = (double*)(h->ws + lay.green);
+    h->rows = (RowShift*)(h->ws + lay.rows);
+    h->diag = (double*)(h->ws + lay.diag);
+    h->ctr = (long long*)(h->ws + lay.ctr);
+    h->flags = (int*)(h->ws + lay.flags);
+    h->bad = (int*)(h->ws + lay.bad);
+    h->scratch3 = h->ws + lay.scratch3;
+    h->gexec[0] = h->gexec[1] = nullptr;
+    if (hipMemsetAsync(h->flags, 0, sizeof(int), h->st) != hipSuccess || (rc = upload_tables(h)) != AVL_OK) {
+        delete h;
+        return rc ? rc : AVL_EDEVICE;
+    }
+    rc = load_markers(h, x, v, f);
+    if (rc) {
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return AVL_OK;
+}
+
+int avl_push(avl_handle* h, const double* E)
+{
+    if (!h) return AVL_EINVAL;
+    if (!E && !h->have_E) return AVL_ESTATE;
+    const double kick = kick_fraction(h);
+    {
+        Timer t(h, AVL_K_PUSH_COUNT);
+        AVL_TRY(launch_push(h->g, marker_view(h, h->cur), E ? E : h->E, h->rows, h->g.dt * kick,
+                            h->g.bscale * (float)kick, h->flags, h->st));
+    }
+    h->kicked = true;
+    h->sorted = false;
+    h->have_f = h->have_rho = h->have_E = false;
+    return AVL_OK;
+}
+
+int avl_sort(avl_handle* h)
+{
+    if (!h) return AVL_EINVAL;
+    return do_sort(h, false, 1.0);
+}
+
+int avl_reconstruct(avl_handle* h, void* f_out, void* D_out)
+{
+    if (!h) return AVL_EINVAL;
+    int rc;
+    if (!h->sorted && (rc = do_sort(h, false, 1.0))) return rc;
+    if ((rc = do_recon(h, D_out))) return rc;
+    if (f_out) {
+        size_t cells = (size_t)h->g.nx;
+        for (int d = 0; d < h->g.vdim; ++d) cells *= h->g.nv[d];
+        AVL_TRY(hipMemcpyAsync(f_out, h->fgrid, cells * (h->g.prec ? 4 : 8), hipMemcpyDeviceToDevice, h->st));
+    }
+    return AVL_OK;
+}
+
+int avl_moments(avl_handle* h, double* rho_out)
+{
+    if (!h) return AVL_EINVAL;
+    if (!h->have_f) return AVL_ESTATE;
+    int rc = do_field(h, nullptr, false, nullptr, false);
+    if (rc) return rc;
+    if (rho_out) AVL_TRY(hipMemcpyAsync(rho_out, h->rho, sizeof(double) * h->g.nx, hipMemcpyDeviceToDevice, h->st));
+    return AVL_OK;
+}
+
+int avl_poisson(avl_handle* h, const double* rho, double* E_out, double* W_out)
+{
+    if (!h) return AVL_EINVAL;
+    if (!rho && !h->have_rho) return AVL_ESTATE;
+    int rc = do_field(h, rho ? rho : h->rho, false, W_out);
+    if (rc) return rc;
+    if (E_out) AVL_TRY(hipMemcpyAsync(E_out, h->E, sizeof(double) * h->g.nx, hipMemcpyDeviceToDevice, h->st));
+    return AVL_OK;
+}
+
+int avl_step(avl_handle* h, int32_t nsteps, double* diag_out)
+{
+    if (!h) return AVL_EINVAL;
+    if (nsteps < 0) return AVL_EINVAL;
+    if (!h->have_E || !h->sorted) return AVL_ESTATE;
+    int64_t first = h->steps;
+    for (int32_t s = 0; s < nsteps; ++s) {
+        int rc = one_step(h);
+        if (rc) return rc;
+        if (diag_out && ((s + 1) % kDiagCap == 0)) {
+            if ((rc = copy_diag(h, first + s + 1 - kDiagCap, kDiagCap, diag_out + 2 * (s + 1 - kDiagCap)))) return rc;
+        }
+    }
+    if (diag_out) {
+        int32_t tail = nsteps % kDiagCap;
+        if (tail) return copy_diag(h, first + nsteps - tail, tail, diag_out + 2 * (nsteps - tail));
+    }
+    return AVL_OK;
+}
+
+int avl_step_graph(avl_handle* h, int32_t nsteps, double* diag_out)
+{
+    if (!h) return AVL_EINVAL;
+    if (nsteps < 0) return AVL_EINVAL;
+    if (!h->have_E || !h->sorted) return AVL_ESTATE;
+    if (h->timing) return avl_step(h, nsteps, diag_out);
+    int64_t first = h->steps;
+    int32_t s = 0;
+    // a half first kick is a different launch argument: run it directly
+    if (nsteps > 0 && kick_fraction(h) != 1.0) {
+        int rc = one_step(h);
+        if (rc) return rc;
+        s = 1;
+    }
+    if (!h->graph_ok && s < nsteps) {
+        // capture one step from each buffer parity
+        for (int b = 0; b < 2; ++b) {
+            hipGraph_t graph;
+            const int saved_cur = h->cur;
+            const int64_t saved_steps = h->steps;
+            h->cur = b;
+            if (hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal) != hipSuccess) return AVL_EDEVICE;
+            int rc = one_step(h);
+            hipError_t e = hipStreamEndCapture(h->st, &graph);
+            h->cur = saved_cur;
+            h->steps = saved_steps;
+            if (rc || e != hipSuccess) return AVL_EDEVICE;
+            e = hipGraphInstantiate(&h->gexec[b], graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                drop_graphs(h);
+                return AVL_EDEVICE;
+            }
+        }
+        h->graph_ok = true;
+    }
+    for (; s < nsteps; ++s) {
+        AVL_TRY(hipGraphLaunch(h->gexec[h->cur], h->st));
+        h->cur = 1 - h->cur;
+        h->steps += 1;
+        if (diag_out && ((s + 1) % kDiagCap == 0)) {
+            int rc = copy_diag(h, first + s + 1 - kDiagCap, kDiagCap, diag_out + 2 * (s + 1 - kDiagCap));
+            if (rc) return rc;
+        }
+    }
+    h->sorted = true;
+    h->have_f = h->have_rho = h->have_E = true;
+    h->kicked = true;
+    if (diag_out) {
+        int32_t tail = nsteps % kDiagCap;
+        if (tail) return copy_diag(h, first + nsteps - tail, tail, diag_out + 2 * (nsteps - tail));
+    }
+    return AVL_OK;
+}
+
+int avl_get_markers(avl_handle* h, double* x, double* v, double* f)
+{
+    if (!h) return AVL_EINVAL;
+    const Geo& g = h->g;
+    const size_t n = (size_t)g.n;
+    if (n == 0) return AVL_OK;
+    if (!x || !v || !f) return AVL_EINVAL;
+    if (((uintptr_t)x | (uintptr_t)v | (uintptr_t)f) & 7) return AVL_EALIGN;
+    if (g.prec == AVL_FP64) {
+        const M64& m = h->m64[h->cur];
+        AVL_TRY(hipMemcpyAsync(x, m.x, sizeof(double) * n, hipMemcpyDeviceToDevice, h->st));
+        AVL_TRY(hipMemcpyAsync(v, m.v, sizeof(double) * n * g.vdim, hipMemcpyDeviceToDevice, h->st));
+        AVL_TRY(hipMemcpyAsync(f, m.f, sizeof(double) * n, hipMemcpyDeviceToDevice, h->st));
+        return AVL_OK;
+    }
+    return hip_status(launch_to64(g, h->m32[h->cur], x, v, f, h->st));
+}
+
+int avl_set_markers(avl_handle* h, const double* x, const double* v, const double* f)
+{
+    if (!h) return AVL_EINVAL;
+    drop_graphs(h);
+    return load_markers(h, x, v, f);
+}
+
+int avl_get_field(avl_handle* h, double* E_out, double* rho_out)
+{
+    if (!h) return AVL_EINVAL;
+    if (E_out) {
+        if (!h->have_E) return AVL_ESTATE;
+        AVL_TRY(hipMemcpyAsync(E_out, h->E, sizeof(double) * h->g.nx, hipMemcpyDeviceToDevice, h->st));
+    }
+    if (rho_out) {
+        if (!h->have_rho) return AVL_ESTATE;
+        AVL_TRY(hipMemcpyAsync(rho_out, h->rho, sizeof(double) * h->g.nx, hipMemcpyDeviceToDevice, h->st));
+    }
+    return AVL_OK;
+}
+
+int64_t avl_step_count(const avl_handle* h) { return h ? h->steps : -1; }
+
+int avl_check(avl_handle* h)
+{
+    if (!h) return AVL_EINVAL;
+    int fl = 0;
+    AVL_TRY(hipMemcpyAsync(&fl, h->flags, sizeof(int), hipMemcpyDeviceToHost, h->st));
+    AVL_TRY(hipStreamSynchronize(h->st));
+    if (fl & FLAG_NONFINITE) return AVL_ENONFINITE;
+    if (fl & (FLAG_SLOT | FLAG_RANGE)) return AVL_EINTERNAL;
+    return AVL_OK;
+}
+
+int avl_set_stream(avl_handle* h, void* stream)
+{
+    if (!h) return AVL_EINVAL;
+    h->st = (hipStream_t)stream;
+    return AVL_OK;
+}
+
+int avl_timing(avl_handle* h, int enable)
+{
+    if (!h) return AVL_EINVAL;
+    h->timing = enable != 0;
+    for (int k = 0; k < AVL_K_COUNT; ++k) h->ev_used[k] = 0;
+    return AVL_OK;
+}
+
+int avl_kernel_time(avl_handle* h, int kernel, double* ms_total, int64_t* launches)
+{
+    if (!h || kernel < 0 || kernel >= AVL_K_COUNT) return AVL_EINVAL;
+    AVL_TRY(hipStreamSynchronize(h->st));
+    double tot = 0.0;
+    const size_t used = h->ev_used[kernel];
+    for (size_t i = 0; i + 1 < used; i += 2) {
+        float ms = 0.0f;
+        AVL_TRY(hipEventElapsedTime(&ms, h->ev[kernel][i], h->ev[kernel][i + 1]));
+        tot += ms;
+    }
+    if (ms_total) *ms_total = tot;
+    if (launches) *launches = (int64_t)(used / 2);
+    return AVL_OK;
+}
+
+double avl_kernel_bytes(const avl_handle* h, int kernel)
+{
+    if (!h) return 0.0;
+    const Geo& g = h->g;
+    const double n = g.n;
+    double cells = g.nx;
+    for (int d = 0; d < g.vdim; ++d) cells *= g.nv[d];
+    const double mk = g.prec == AVL_FP64 ? 8.0 * (2 + g.vdim) : 4.0 * (3 + g.vdim);   // bytes per marker
+    const double pos = g.prec == AVL_FP64 ? 8.0 * (1 + g.vdim) : 4.0 * (2 + g.vdim);  // without f
+    const double esz = g.prec == AVL_FP64 ? 8.0 : 4.0;
+    switch (kernel) {
+    case AVL_K_PUSH_COUNT: return n * pos;                      // read positions and velocities
+    case AVL_K_SCAN: return 3.0 * 4.0 * (g.nb + 1.0);           // counts read twice, offsets written
+    case AVL_K_SCATTER: return 2.0 * n * mk;                    // read and write every marker
+    case AVL_K_RECONSTRUCT: return n * mk + cells * esz;        // read markers, write f
+    case AVL_K_FIELD: return 8.0 * g.nx * (g.nchunk + 2.0);
+    case AVL_K_STEP: return n * (pos + 3.0 * mk) + cells * esz;
+    default: return 0.0;
+    }
+}
+
+int avl_copy_probe(void* dst, const void* src, size_t bytes, void* stream)
+{
+    if (!dst || !src || (bytes % 16)) return AVL_EINVAL;
+    if (((uintptr_t)dst | (uintptr_t)src) & 15) return AVL_EALIGN;
+    return hip_status(launch_copy(src, dst, bytes, (hipStream_t)stream));
+}
+
+const char* avl_strerror(int status)
+{
+    switch (status) {
+    case AVL_OK: return "ok";
+    case AVL_EINVAL: return "invalid argument or configuration";
+    case AVL_ESIZE: return "size out of range or workspace too small";
+    case AVL_EALIGN: return "misaligned pointer";
+    case AVL_ESTATE: return "call not valid in the current state";
+    case AVL_EDEVICE: return "HIP runtime error";
+    case AVL_ENOTSUP: return "configuration not supported";
+    case AVL_ENONFINITE: return "non-finite value seen on the device";
+    case AVL_EINTERNAL: return "device consistency check failed";
+    default: return "unknown status";
+    }
+}
+
+int avl_destroy(avl_handle* h)
+{
+    if (!h) return AVL_EINVAL;
+    drop_graphs(h);
+    for (int k = 0; k < AVL_K_COUNT; ++k)
+        for (hipEvent_t e : h->ev[k]) (void)hipEventDestroy(e);
+    delete h;
+    return AVL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,190 @@
+// Device-side definitions shared by the libavl kernels (gfx950).
+//
+// Phase-space bookkeeping used throughout:
+//  * A marker at x has the dual coordinate s = x/dx - 1/2: the integer part
+//    i0 = floor(s) is the x cell whose centre is the marker's left cloud
+//    neighbour and a = s - i0 in [0,1) is the cloud-in-cell weight of the right
+//    neighbour (Sec. 2, Fig. "interpolation"; centres as in Fig. "phasespace").
+//    The same holds per velocity component with t = (v - vmin)/dv - 1/2,
+//    j0 = floor(t), b = t - j0.
+//  * Markers are sorted by "bucket": the dual cell (i0 mod nx, j0+1 per velocity
+//    component), flattened velocity-major with nv[d]+1 dual rows per component
+//    (j0 ranges over -1..nv-1 for clouds that still touch the grid).  Clouds
+//    that miss the velocity grid entirely go to one overflow bucket (index nb),
+//    which the reconstruction ignores.  Bucket rows therefore have nx entries.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace avl {
+
+enum : int { FLAG_NONFINITE = 1, FLAG_SLOT = 2, FLAG_RANGE = 4 };
+
+constexpr int kWave = 64;
+constexpr int kSortThreads = 256;
+constexpr int kSortMPT = 8;                               // markers per thread in sort passes
+constexpr int kSortTile = kSortThreads * kSortMPT;
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+constexpr int kReconCols = kWave - 1;                     // target columns per reconstruct wave
+constexpr int kReconWaves = 4;                            // waves per reconstruct block
+constexpr int kDiagCap = 4096;                            // per-step diagnostics ring
+constexpr int kFieldThreads = 512;
+constexpr int kMaxNx = 4096;
+
+struct Geo {
+    int vdim, prec;
+    int nx, lognx;
+    int nv[3];
+    int nrow;            // number of bucket rows: prod(nv[d] + 1)
+    int nb;              // in-range buckets nrow*nx; bucket nb collects the rest
+    int n;               // markers
+    int rc;              // target velocity rows per reconstruct chunk (1D-1V)
+    int nchunk, nstrip;  // reconstruct chunks along v and column strips along x
+    int hist_bins;       // LDS histogram bins per sort block
+    int cap;             // markers staged in LDS per reconstruct wave
+    int jpad, jrange;    // FP32 1D-3V: x-velocity dual index stored with offset jpad, range jrange
+    double L, inv_L, dx, inv_dx;
+    double vmin[3], dv[3], inv_dv[3];
+    double dt, qm, cp;
+    double q_vol;        // q * prod(dv): scale from sum_j f to rho
+    float bscale;        // FP32 form: q/m * dt / dv[0] (times the kick fraction)
+    float gam;           // FP32 form: dv[0] * dt / dx (drift in x cells per unit b)
+    float c0f;           // FP32 form: vmin[0]/dv[0] + 1/2
+};
+
+struct M64 {             // plain FP64 marker arrays
+    double* x;
+    double* v;           // component d of marker l at v[d*n + l]
+    double* f;
+};
+
+struct M32 {             // FP32 form: dual cell index + offsets
+    int* cell;
+    float* a;
+    float* b;            // component d of marker l at b[d*n + l]
+    float* f;
+};
+
+// Drift table for the FP32 form, one entry per dual row j' = j0+1 in [0, nv]:
+// the x shift in cells of a marker at b = 0, split into an integer and a
+// fractional part computed once in FP64 on the host.
+struct RowShift {
+    int whole;
+    float frac;
+};
+
+__device__ __forceinline__ int wrap_pow2(int i, int nx) { return i & (nx - 1); }
+
+// Bucket of an FP64 marker and its in-cell offsets.  Returns g.nb when the
+// cloud misses the velocity grid (or a coordinate is not finite).
+template <int VD>
+__device__ __forceinline__ int locate64(const Geo& g, double x, const double* vv,
+                                        int& ix, int* jp, double& a, double* b)
+{
+    double s = x * g.inv_dx - 0.5;
+    bool ok = (s >= -1.0) && (s < (double)g.nx);
+    double sc = ok ? s : 0.0;
+    double fs = floor(sc);
+    a = sc - fs;
+    ix = wrap_pow2((int)fs, g.nx);
+    int row = 0;
+#pragma unroll
+    for (int d = VD - 1; d >= 0; --d) {
+        double t = (vv[d] - g.vmin[d]) * g.inv_dv[d] - 0.5;
+        bool okd = (t >= -1.0) && (t < (double)g.nv[d]);
+        double tc = okd ? t : 0.0;
+        double ft = floor(tc);
+        b[d] = tc - ft;
+        jp[d] = (int)ft + 1;
+        ok = ok && okd;
+        row = row * (g.nv[d] + 1) + jp[d];
+    }
+    return ok ? row * g.nx + ix : g.nb;
+}
+
+// Gather + kick + drift of one FP64 marker (x velocity only).
+__device__ __forceinline__ void push64(const Geo& g, const double* sE, double dtk,
+                                       double& x, double& vx)
+{
+    double s = x * g.inv_dx - 0.5;
+    double fs = floor(s);
+    double a = s - fs;
+    int ia = wrap_pow2((int)fs, g.nx);
+    int ib = wrap_pow2(ia + 1, g.nx);
+    double El = (1.0 - a) * sE[ia] + a * sE[ib];
+    vx = vx + g.qm * El * dtk;
+    double xn = x + vx * g.dt;
+    xn = xn - g.L * floor(xn * g.inv_L);
+    if (xn >= g.L) xn -= g.L;
+    if (xn < 0.0) xn += g.L;
+    x = xn;
+}
+
+// FP32 form: bucket of a stored cell index.  1D-1V stores cell = j'*nx + i0
+// with j' = j0+1 unbounded; 1D-3V stores ((jz'*(nvy+1) + jy')*jrange + jx' +
+// jpad)*nx + i0 so that x-velocity rows beyond the grid stay representable.
+template <int VD>
+__device__ __forceinline__ int bucket32(const Geo& g, int cell)
+{
+    if (VD == 1) return (cell >= 0 && cell < g.nb) ? cell : g.nb;
+    int ix = cell & (g.nx - 1);
+    int r = cell >> g.lognx;
+    int jx = (r % g.jrange) - g.jpad;
+    int yz = r / g.jrange;
+    if (cell < 0 || jx < 0 || jx > g.nv[0]) return g.nb;
+    return (yz * (g.nv[0] + 1) + jx) * g.nx + ix;
+}
+
+// Gather + kick + drift of one FP32-form marker.  Velocity moves in units of
+// dv (b carries into the dual row), position in units of dx (a carries into
+// the column, with periodic wrap); the large per-row part of the x shift comes
+// from the FP64-built table so no absolute coordinate is ever held in FP32.
+template <int VD>
+__device__ __forceinline__ void push32(const Geo& g, const float* sE, const RowShift* rows,
+                                       float bk, int& cell, float& a, float& b, int& flags)
+{
+    int ix = cell & (g.nx - 1);
+    int r = cell >> g.lognx;
+    int jx, rest;
+    if (VD == 1) { jx = r; rest = 0; }
+    else { jx = (r % g.jrange) - g.jpad; rest = r / g.jrange; }
+    int ib = (ix + 1) & (g.nx - 1);
+    float El = (1.0f - a) * sE[ix] + a * sE[ib];
+    float bn = b + El * bk;
+    float fl = floorf(bn);
+    jx += (int)fl;
+    bn -= fl;
+    if (bn >= 1.0f) { bn -= 1.0f; jx += 1; }
+    int whole;
+    float frac;
+    if (jx >= 0 && jx <= g.nv[0]) {
+        whole = rows[jx].whole;
+        frac = rows[jx].frac;
+    } else {
+        float P = ((float)(jx - 1) + g.c0f) * g.gam;
+        float Pf = floorf(P);
+        whole = (int)Pf;
+        frac = P - Pf;
+    }
+    float an = a + frac + bn * g.gam;
+    float ca = floorf(an);
+    an -= ca;
+    if (an >= 1.0f) { an -= 1.0f; ca += 1.0f; }
+    ix = (ix + whole + (int)ca) & (g.nx - 1);
+    if (VD == 1) {
+        const int lim = (1 << (30 - g.lognx));
+        if (jx < -lim || jx > lim) { flags |= FLAG_RANGE; jx = jx < 0 ? -lim : lim; }
+        cell = jx * g.nx + ix;
+    } else {
+        int jj = jx + g.jpad;
+        if (jj < 0 || jj >= g.jrange) { flags |= FLAG_RANGE; jj = jj < 0 ? 0 : g.jrange - 1; }
+        cell = (rest * g.jrange + jj) * g.nx + ix;
+    }
+    if (!(an == an) || !(bn == bn)) flags |= FLAG_NONFINITE;
+    a = an;
+    b = bn;
+}
+
+}  // namespace avl
