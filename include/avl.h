@@ -159,8 +159,10 @@ int avl_step_graph(avl_handle* h, int32_t nsteps, double* diag_out);
  * 1/2 + b) dv with (i, j) the stored cell. */
 int avl_get_markers(avl_handle* h, double* x, double* v, double* f);
 
-/* Replace the markers (FP64 SoA, same count, x in [0, L)); the order becomes
- * stale and f, rho, E are recomputed as in avl_init.  Synchronises. */
+/* Replace the markers (FP64 SoA, same count, x in [0, L)), e.g. to resume
+ * from a checkpoint taken with avl_get_markers: they are re-sorted and f, rho
+ * and E recomputed as in avl_init, while the step count and the first-kick
+ * state carry on.  Synchronises. */
 int avl_set_markers(avl_handle* h, const double* x, const double* v, const double* f);
 
 /* Copy the handle's current field (nx doubles) and charge density. */

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -32,6 +33,7 @@ hipError_t launch_to32(const Geo& g, const double* x, const double* v, const dou
 hipError_t launch_to64(const Geo& g, M32 m, double* x, double* v, double* f, hipStream_t st);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
 size_t recon3_scratch_bytes(const Geo& g);
+void set_lds_limit(int bytes);
 }  // namespace avl
 
 using namespace avl;
@@ -168,6 +170,21 @@ void make_layout(const avl_config* c, const Geo& g, Layout* L)
     L->total = off;
 }
 
+// Shrink LDS-sized parameters to what one block may use on this device.
+void fit_lds(Geo* g, int lds)
+{
+    const int esz = g->prec ? 4 : 8;
+    if (g->vdim == 1) {
+        int budget = (lds - 256) / (kReconWaves * 3 * esz);
+        budget = (budget / 64) * 64;
+        if (g->cap > budget) g->cap = budget;
+    }
+    const int fixed = esz * g->nx + (g->prec ? (int)sizeof(RowShift) * (g->nv[0] + 1) : 0) + 64;
+    int bins = (lds - fixed) / 4;
+    bins = (bins >> g->lognx) << g->lognx;
+    if (g->hist_bins > bins) g->hist_bins = bins;
+}
+
 }  // namespace
 
 struct avl_handle {
@@ -190,6 +207,7 @@ struct avl_handle {
     bool kicked;        // a push has happened since loading (first-kick rule)
     int64_t steps;      // steps enqueued since loading (mirrors the device counter)
     hipGraphExec_t gexec[2];
+    hipStream_t cap_st;   // capture stream (the legacy default stream cannot be captured)
     bool graph_ok;
     bool timing;
     std::vector<hipEvent_t> ev[AVL_K_COUNT];
@@ -225,10 +243,23 @@ void set_views(avl_handle* h)
 
 int hip_status(hipError_t e) { return e == hipSuccess ? AVL_OK : AVL_EDEVICE; }
 
-#define AVL_TRY(expr)                          \
-    do {                                       \
-        hipError_t e_ = (expr);                \
-        if (e_ != hipSuccess) return AVL_EDEVICE; \
+bool debug_on()
+{
+    static int on = -1;
+    if (on < 0) on = std::getenv("AVL_DEBUG") ? 1 : 0;
+    return on == 1;
+}
+
+int report(hipError_t e, const char* what, int line)
+{
+    if (debug_on()) std::fprintf(stderr, "[avl] %s failed at line %d: %s\n", what, line, hipGetErrorString(e));
+    return AVL_EDEVICE;
+}
+
+#define AVL_TRY(expr)                                    \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) return report(e_, #expr, __LINE__); \
     } while (0)
 
 struct Timer {
@@ -322,7 +353,10 @@ int do_sort(avl_handle* h, bool push, double kick)
     }
     h->cur = 1 - h->cur;
     h->sorted = true;
-    if (push) h->kicked = true;
+    if (push) {
+        h->kicked = true;
+        h->have_f = h->have_rho = h->have_E = false;
+    }
     return AVL_OK;
 }
 
@@ -334,8 +368,9 @@ int do_recon(avl_handle* h, void* Dgrid)
     else
         AVL_TRY(launch_recon3(h->g, marker_view(h, h->cur), h->offsets, h->fgrid, Dgrid, h->rho_part, h->scratch3,
                               h->st));
+    // rho stays valid when the markers have not moved since it was formed
+    if (!h->have_f) h->have_rho = false;
     h->have_f = true;
-    h->have_rho = false;
     return AVL_OK;
 }
 
@@ -362,7 +397,7 @@ int one_step(avl_handle* h)
 
 // Load FP64 markers into buffer `cur` (converting to the FP32 form if needed),
 // validate them, and rebuild f, rho, E.
-int load_markers(avl_handle* h, const double* x, const double* v, const double* f)
+int load_markers(avl_handle* h, const double* x, const double* v, const double* f, bool fresh)
 {
     const Geo& g = h->g;
     const size_t n = (size_t)g.n;
@@ -388,11 +423,14 @@ int load_markers(avl_handle* h, const double* x, const double* v, const double* 
     const size_t nbt = (size_t)g.nb + 1;
     AVL_TRY(hipMemsetAsync(h->counts, 0, sizeof(int) * nbt, h->st));
     AVL_TRY(hipMemcpyAsync(h->offsets + nbt, &total, sizeof(int), hipMemcpyHostToDevice, h->st));
-    AVL_TRY(hipMemsetAsync(h->ctr, 0, sizeof(long long), h->st));
+    if (fresh) AVL_TRY(hipMemsetAsync(h->ctr, 0, sizeof(long long), h->st));
     AVL_TRY(hipStreamSynchronize(h->st));
-    h->steps = 0;
-    h->kicked = false;
+    if (fresh) {
+        h->steps = 0;
+        h->kicked = false;
+    }
     h->sorted = false;
+    h->have_f = h->have_rho = h->have_E = false;
     int rc;
     if ((rc = do_sort(h, false, 1.0))) return rc;
     if ((rc = do_recon(h, nullptr))) return rc;
@@ -473,11 +511,24 @@ int avl_init(const avl_config* cfg, void* workspace, size_t ws_bytes, void* stre
     h->bad = (int*)(h->ws + lay.bad);
     h->scratch3 = h->ws + lay.scratch3;
     h->gexec[0] = h->gexec[1] = nullptr;
+    h->cap_st = nullptr;
+    {
+        // size LDS use from what the device lets one block opt into
+        int dev = 0, lds = 0;
+        if (hipGetDevice(&dev) != hipSuccess) { delete h; return AVL_EDEVICE; }
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess || lds <= 0)
+            if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) lds = 65536;
+        set_lds_limit(lds);
+        fit_lds(&h->g, lds);
+        if (debug_on())
+            std::fprintf(stderr, "[avl] lds limit %d B, recon cap %d, hist bins %d, rc %d, chunks %d, strips %d\n", lds,
+                         h->g.cap, h->g.hist_bins, h->g.rc, h->g.nchunk, h->g.nstrip);
+    }
     if (hipMemsetAsync(h->flags, 0, sizeof(int), h->st) != hipSuccess || (rc = upload_tables(h)) != AVL_OK) {
         delete h;
         return rc ? rc : AVL_EDEVICE;
     }
-    rc = load_markers(h, x, v, f);
+    rc = load_markers(h, x, v, f, true);
     if (rc) {
         delete h;
         return rc;
@@ -577,23 +628,31 @@ int avl_step_graph(avl_handle* h, int32_t nsteps, double* diag_out)
         s = 1;
     }
     if (!h->graph_ok && s < nsteps) {
-        // capture one step from each buffer parity
+        // capture one step from each buffer parity on a side stream; the graph
+        // is then launched on the handle's stream
+        if (!h->cap_st) AVL_TRY(hipStreamCreateWithFlags(&h->cap_st, hipStreamNonBlocking));
+        AVL_TRY(hipStreamSynchronize(h->st));
+        const hipStream_t user_st = h->st;
         for (int b = 0; b < 2; ++b) {
-            hipGraph_t graph;
+            hipGraph_t graph = nullptr;
             const int saved_cur = h->cur;
             const int64_t saved_steps = h->steps;
             h->cur = b;
-            if (hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal) != hipSuccess) return AVL_EDEVICE;
-            int rc = one_step(h);
-            hipError_t e = hipStreamEndCapture(h->st, &graph);
+            h->st = h->cap_st;
+            hipError_t e = hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal);
+            int rc = e == hipSuccess ? one_step(h) : AVL_EDEVICE;
+            hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(h->st, &graph) : e;
+            h->st = user_st;
             h->cur = saved_cur;
             h->steps = saved_steps;
-            if (rc || e != hipSuccess) return AVL_EDEVICE;
+            if (e != hipSuccess) return report(e, "hipStreamBeginCapture", __LINE__);
+            if (e2 != hipSuccess) return report(e2, "hipStreamEndCapture", __LINE__);
+            if (rc) return rc;
             e = hipGraphInstantiate(&h->gexec[b], graph, nullptr, nullptr, 0);
             (void)hipGraphDestroy(graph);
             if (e != hipSuccess) {
                 drop_graphs(h);
-                return AVL_EDEVICE;
+                return report(e, "hipGraphInstantiate", __LINE__);
             }
         }
         h->graph_ok = true;
@@ -639,7 +698,7 @@ int avl_set_markers(avl_handle* h, const double* x, const double* v, const doubl
 {
     if (!h) return AVL_EINVAL;
     drop_graphs(h);
-    return load_markers(h, x, v, f);
+    return load_markers(h, x, v, f, false);
 }
 
 int avl_get_field(avl_handle* h, double* E_out, double* rho_out)
@@ -748,6 +807,7 @@ int avl_destroy(avl_handle* h)
 {
     if (!h) return AVL_EINVAL;
     drop_graphs(h);
+    if (h->cap_st) (void)hipStreamDestroy(h->cap_st);
     for (int k = 0; k < AVL_K_COUNT; ++k)
         for (hipEvent_t e : h->ev[k]) (void)hipEventDestroy(e);
     delete h;

@@ -75,6 +75,19 @@ struct RowShift {
     float frac;
 };
 
+// Dynamic LDS a block may opt into on the current device (set at load time).
+int lds_limit();
+
+// Raise a kernel's dynamic-LDS allowance to `bytes` if it is not already that
+// high (`granted` caches what was set for this kernel).
+inline hipError_t ensure_lds(const void* fn, size_t bytes, int& granted)
+{
+    if ((int)bytes <= granted || bytes <= 65536) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) granted = (int)bytes;
+    return e;
+}
+
 __device__ __forceinline__ int wrap_pow2(int i, int nx) { return i & (nx - 1); }
 
 // Bucket of an FP64 marker and its in-cell offsets.  Returns g.nb when the

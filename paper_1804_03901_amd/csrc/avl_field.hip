@@ -13,6 +13,10 @@
 
 namespace avl {
 
+static int g_lds_limit = 65536;
+void set_lds_limit(int bytes) { g_lds_limit = bytes; }
+int lds_limit() { return g_lds_limit; }
+
 __device__ __forceinline__ int bitrev(int i, int lg) { return (int)(__brev((unsigned)i) >> (32 - lg)); }
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b)
@@ -135,11 +139,9 @@ hipError_t launch_field(const Geo& g, const double* rho_part, const double* rho_
                         long long* step_ctr, int write_diag, double* W_out, int* flags, int solve, hipStream_t st)
 {
     const size_t smem = sizeof(double2) * g.nx;
-    static bool attr = false;
-    if (!attr) {
-        (void)hipFuncSetAttribute((const void*)k_field, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
-        attr = true;
-    }
+    static int granted = 0;
+    hipError_t e = ensure_lds((const void*)k_field, smem, granted);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_field, dim3(1), dim3(kFieldThreads), smem, st, g, rho_part, rho_in, rho_out, E_out,
                        tw, green, diag_ring, step_ctr, write_diag, W_out, flags, solve);
     return hipGetLastError();

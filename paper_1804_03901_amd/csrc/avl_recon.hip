@@ -202,13 +202,11 @@ hipError_t launch_recon(const Geo& g, void* m, const int* offsets, void* fgrid, 
     const size_t esz = g.prec ? sizeof(float) : sizeof(double);
     const size_t smem = (size_t)kReconWaves * 3 * g.cap * esz;
     if (g.vdim != 1) return hipErrorNotSupported;
-    static bool attr[2] = {false, false};
-    if (!attr[g.prec]) {
-        if (g.prec == 0)
-            (void)hipFuncSetAttribute((const void*)k_recon_1v<0>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        else
-            (void)hipFuncSetAttribute((const void*)k_recon_1v<1>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        attr[g.prec] = true;
+    static int granted[2] = {0, 0};
+    {
+        const void* fn = g.prec == 0 ? (const void*)k_recon_1v<0> : (const void*)k_recon_1v<1>;
+        hipError_t e = ensure_lds(fn, smem, granted[g.prec]);
+        if (e != hipSuccess) return e;
     }
     if (g.prec == 0)
         hipLaunchKernelGGL(k_recon_1v<0>, dim3(blocks), dim3(kWave * kReconWaves), smem, st, g,

@@ -386,14 +386,14 @@ static hipError_t launch_sort_t(const Geo& g, void* src, void* dst, const double
     const int blocks = (g.n + kSortTile - 1) / kSortTile;
     const size_t smem = sort_smem<PREC>(g, push);
     if (g.n == 0 && phase != 1) return hipSuccess;   // the scan still runs: offsets become zero
-    static bool attr = false;
-    if (!attr) {
-        const int lim = 160 * 1024;
-        (void)hipFuncSetAttribute((const void*)k_count<PREC, VD, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-        (void)hipFuncSetAttribute((const void*)k_count<PREC, VD, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-        (void)hipFuncSetAttribute((const void*)k_scatter<PREC, VD, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-        (void)hipFuncSetAttribute((const void*)k_scatter<PREC, VD, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-        attr = true;
+    static int granted[4] = {0, 0, 0, 0};
+    {
+        const void* fns[4] = {(const void*)k_count<PREC, VD, true>, (const void*)k_count<PREC, VD, false>,
+                              (const void*)k_scatter<PREC, VD, true>, (const void*)k_scatter<PREC, VD, false>};
+        for (int i = 0; i < 4; ++i) {
+            hipError_t e = ensure_lds(fns[i], smem, granted[i]);
+            if (e != hipSuccess) return e;
+        }
     }
     if (phase == 0) {
         if (push) hipLaunchKernelGGL((k_count<PREC, VD, true>), dim3(blocks), dim3(kSortThreads), smem, st, g, s, E, rows, dtk, bk, counts, flags);
