@@ -29,9 +29,35 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_form(avl, inputs, w, x, v, f, precision, steps, warmup):
+FORMS = {"fp32": ("AVL_FP32", 0), "fp32_kahan": ("AVL_FP32", "AVL_OPT_KAHAN32"), "fp64": ("AVL_FP64", 0)}
+
+
+def copy_probe(avl, nbytes=1 << 30, reps=10):
+    """Achievable HBM bandwidth of a plain streaming copy (read + write bytes / time)."""
     import torch
-    sim = avl.Simulation(w, x, v, f, precision=precision)
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    avl.avl_copy_probe(dst, src, nbytes)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        avl.avl_copy_probe(dst, src, nbytes)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    ok = bool(torch.equal(dst[:1024], src[:1024]))
+    del src, dst
+    return 2 * nbytes / (ms * 1e-3) / 1e9, ms, ok
+
+
+def run_form(avl, inputs, w, x, v, f, form, steps, warmup):
+    import torch
+    prec_name, opt = FORMS[form]
+    precision = getattr(avl, prec_name)
+    options = getattr(avl, opt) if isinstance(opt, str) else opt
+    sim = avl.Simulation(w, x, v, f, precision=precision, options=options)
     torch.cuda.synchronize()
     sim.step(warmup, graph=True, diag=False)
     torch.cuda.synchronize()
@@ -94,7 +120,8 @@ def main():
     ap.add_argument("--ppc", type=int, default=16)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--forms", default="fp32,fp64")
+    ap.add_argument("--forms", default="fp32,fp32_kahan,fp64")
+    ap.add_argument("--no-probe", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
@@ -108,10 +135,13 @@ def main():
     x, v, f = inputs.markers(w)
     v = v.reshape(-1)
     results = {}
+    probe = None
+    if not args.no_probe:
+        probe = copy_probe(avl)
+        log(f"copy probe: {probe[0]:.0f} GB/s")
     for form in args.forms.split(","):
-        prec = avl.AVL_FP32 if form == "fp32" else avl.AVL_FP64
         log(f"form {form}: warmup {args.warmup}, timed {args.steps}")
-        results[form] = run_form(avl, inputs, w, x, v, f, prec, args.steps, args.warmup)
+        results[form] = run_form(avl, inputs, w, x, v, f, form, args.steps, args.warmup)
         log(f"form {form}: {results[form][0]:.4f} ms/step (graph {results[form][1]:.4f})")
     main_form = "fp32" if "fp32" in results else next(iter(results))
     ms, ms_graph, kt = results[main_form]
@@ -129,7 +159,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if main_form == "fp32" else "f64",
+        "dtype": "f64" if main_form == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "markers": w.n_markers, "nx": w.nx, "nv": w.nv[0], "ppc": w.ppc,
                    "form": main_form, "parallelism": "single GPU"},
@@ -142,6 +172,10 @@ def main():
     }
     if "fp32" in results and "fp64" in results:
         out["fp32_speedup_over_fp64"] = results["fp64"][0] / results["fp32"][0]
+    if probe is not None:
+        out["roofline"]["copy_probe_GBs"] = probe[0]
+        out["roofline"]["frac_of_copy"] = achieved / probe[0]
+        out["copy_probe"] = {"GB_per_s": probe[0], "ms": probe[1], "bytes_moved": 2 * (1 << 30), "checked": probe[2]}
     if not args.no_cpu:
         log(f"cpu baseline: oracle, {args.cpu_steps} steps on the full marker set, 1 thread")
         rate, secs = cpu_baseline(inputs, w, x, v.reshape(1, -1), f, args.cpu_steps)

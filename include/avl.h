@@ -68,9 +68,17 @@ typedef enum {
  *  AVL_FP32: each marker stores the integer index of the cell whose centre is
  *            its lower-left cloud neighbour plus FP32 offsets in [0,1) from that
  *            centre (a along x, b along each velocity component) and an FP32 f;
- *            reconstruction sums N and D in FP32 with compensated (Kahan)
- *            summation; rho and the field solve stay FP64. */
+ *            the push works in cell units, the f grid is FP32; rho and the field
+ *            solve stay FP64. */
 typedef enum { AVL_FP64 = 0, AVL_FP32 = 1 } avl_precision;
+
+/* Options.  The reconstruction sums, per run of markers sharing a cell, the
+ * moments S_f, S_af, S_bf, S_abf, S_a, S_b, S_ab of the offsets (from which
+ * the four cloud-in-cell corner sums follow exactly); by default these
+ * accumulate in FP64 in both forms.
+ *  AVL_OPT_KAHAN32: FP32 form only: accumulate them in FP32 with compensated
+ *                   (Kahan) summation instead. */
+typedef enum { AVL_OPT_KAHAN32 = 1 } avl_option;
 
 typedef struct avl_config {
     int32_t vdim;        /* 1 (1D-1V) or 3 (1D-3V) */
@@ -78,7 +86,7 @@ typedef struct avl_config {
     int32_t nv[3];       /* velocity cells per component, each >= 2 (only [0, vdim) used) */
     int32_t precision;   /* avl_precision */
     int32_t first_kick;  /* 0: first velocity update is a full dt from v^0; 1: half dt */
-    int32_t reserved;    /* must be 0 */
+    int32_t options;     /* bit set of avl_option, 0 for the defaults */
     int64_t n_markers;   /* number of markers n, 0 <= n < 2^31 */
     double L;            /* domain length, finite > 0 */
     double vmin[3];      /* lower velocity bound per component */
@@ -183,7 +191,7 @@ int avl_set_stream(avl_handle* h, void* stream);
  * avl_kernel_time synchronises and returns the summed milliseconds and the
  * number of launches since timing was enabled. */
 enum { AVL_K_PUSH_COUNT = 0, AVL_K_SCAN = 1, AVL_K_SCATTER = 2, AVL_K_RECONSTRUCT = 3,
-       AVL_K_FIELD = 4, AVL_K_STEP = 5, AVL_K_COUNT = 6 };
+       AVL_K_MOMENTS = 4, AVL_K_FIELD = 5, AVL_K_STEP = 6, AVL_K_COUNT = 7 };
 int avl_timing(avl_handle* h, int enable);
 int avl_kernel_time(avl_handle* h, int kernel, double* ms_total, int64_t* launches);
 

@@ -20,8 +20,9 @@ LIB_PATH = os.path.join(_HERE, "_build", "libavl.so")
 
 AVL_FP64 = 0
 AVL_FP32 = 1
-K_PUSH_COUNT, K_SCAN, K_SCATTER, K_RECONSTRUCT, K_FIELD, K_STEP = range(6)
-KERNEL_NAMES = ["push_count", "scan", "scatter", "reconstruct", "field", "step"]
+AVL_OPT_KAHAN32 = 1
+K_PUSH_COUNT, K_SCAN, K_SCATTER, K_RECONSTRUCT, K_MOMENTS, K_FIELD, K_STEP = range(7)
+KERNEL_NAMES = ["push_count", "scan", "scatter", "reconstruct", "moments", "field", "step"]
 
 STATUS = {0: "AVL_OK", -1: "AVL_EINVAL", -2: "AVL_ESIZE", -3: "AVL_EALIGN", -4: "AVL_ESTATE",
           -5: "AVL_EDEVICE", -6: "AVL_ENOTSUP", -7: "AVL_ENONFINITE", -8: "AVL_EINTERNAL"}
@@ -36,7 +37,7 @@ class AvlError(RuntimeError):
 class AvlConfig(ctypes.Structure):
     _fields_ = [
         ("vdim", ctypes.c_int32), ("nx", ctypes.c_int32), ("nv", ctypes.c_int32 * 3),
-        ("precision", ctypes.c_int32), ("first_kick", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("first_kick", ctypes.c_int32), ("options", ctypes.c_int32),
         ("n_markers", ctypes.c_int64), ("L", ctypes.c_double),
         ("vmin", ctypes.c_double * 3), ("vmax", ctypes.c_double * 3),
         ("dt", ctypes.c_double), ("q", ctypes.c_double), ("m", ctypes.c_double), ("c_p", ctypes.c_double),
@@ -116,7 +117,8 @@ def _stream_ptr(stream) -> Optional[int]:
     return stream.cuda_stream
 
 
-def make_config(w: "inputs.Workload", precision: int = AVL_FP64, n_markers: Optional[int] = None) -> AvlConfig:
+def make_config(w: "inputs.Workload", precision: int = AVL_FP64, n_markers: Optional[int] = None,
+                options: int = 0) -> AvlConfig:
     c = AvlConfig()
     c.vdim = w.vdim
     c.nx = w.nx
@@ -126,7 +128,7 @@ def make_config(w: "inputs.Workload", precision: int = AVL_FP64, n_markers: Opti
         c.vmax[d] = w.vmax[d] if d < w.vdim else 1.0
     c.precision = precision
     c.first_kick = w.first_kick
-    c.reserved = 0
+    c.options = options
     c.n_markers = w.n_markers if n_markers is None else n_markers
     c.L = w.L
     c.dt, c.q, c.m, c.c_p = w.dt, w.q, w.m, w.c_p
@@ -231,7 +233,7 @@ class Simulation:
     """One VHS species on one GPU: owns a torch workspace and a libavl handle."""
 
     def __init__(self, w: "inputs.Workload", x, v, f, precision: int = AVL_FP64, device: str = "cuda:0",
-                 stream=None):
+                 stream=None, options: int = 0):
         import torch
         self.w = w
         self.device = torch.device(device)
@@ -240,7 +242,7 @@ class Simulation:
         v = torch.as_tensor(v, dtype=torch.float64, device=self.device).reshape(-1).contiguous()
         f = torch.as_tensor(f, dtype=torch.float64, device=self.device).contiguous()
         self.n = x.numel()
-        self.cfg = make_config(w, precision, self.n)
+        self.cfg = make_config(w, precision, self.n, options)
         nbytes = avl_workspace_bytes(self.cfg)
         if nbytes == 0:
             raise AvlError(-1, "avl_workspace_bytes")

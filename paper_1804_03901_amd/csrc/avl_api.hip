@@ -21,11 +21,13 @@ hipError_t launch_push(const Geo& g, void* m, const double* E, const RowShift* r
                        int* flags, hipStream_t st);
 hipError_t launch_recon(const Geo& g, void* m, const int* offsets, void* fgrid, void* Dgrid, double* rho_part,
                         hipStream_t st);
+hipError_t launch_moments(const Geo& g, const double* rho_part, double* rho, hipStream_t st);
+int recon_capacity(int prec);
 hipError_t launch_recon3(const Geo& g, void* m, const int* offsets, void* fgrid, void* Dgrid, double* rho_part,
                          void* scratch, hipStream_t st);
-hipError_t launch_field(const Geo& g, const double* rho_part, const double* rho_in, double* rho_out, double* E_out,
-                        const double2* tw, const double* green, double* diag_ring, long long* step_ctr,
-                        int write_diag, double* W_out, int* flags, int solve, hipStream_t st);
+hipError_t launch_field(const Geo& g, const double* rho_src, double* rho_copy, double* E_out, const double2* tw,
+                        const double* green, double* diag_ring, long long* step_ctr, int write_diag, double* W_out,
+                        int* flags, hipStream_t st);
 hipError_t launch_validate(const Geo& g, const double* x, const double* v, const double* f, int* bad,
                            hipStream_t st);
 hipError_t launch_to32(const Geo& g, const double* x, const double* v, const double* f, M32 m, int* flags,
@@ -68,12 +70,14 @@ int make_geo(const avl_config* c, Geo* g)
     if (c->nx < 8 || c->nx > kMaxNx || (c->nx & (c->nx - 1))) return AVL_EINVAL;
     if (c->precision != AVL_FP64 && c->precision != AVL_FP32) return AVL_EINVAL;
     if (c->first_kick != 0 && c->first_kick != 1) return AVL_EINVAL;
-    if (c->reserved != 0) return AVL_EINVAL;
+    if (c->options & ~AVL_OPT_KAHAN32) return AVL_EINVAL;
+    if ((c->options & AVL_OPT_KAHAN32) && c->precision != AVL_FP32) return AVL_EINVAL;
     if (c->n_markers < 0 || c->n_markers >= (int64_t)INT32_MAX) return AVL_ESIZE;
     if (!finite_pos(c->L) || !finite_pos(c->dt) || !finite_pos(c->c_p)) return AVL_EINVAL;
     if (!std::isfinite(c->q) || !std::isfinite(c->m) || c->m == 0.0) return AVL_EINVAL;
     g->vdim = c->vdim;
     g->prec = c->precision;
+    g->kahan = (c->options & AVL_OPT_KAHAN32) ? 1 : 0;
     g->nx = c->nx;
     g->lognx = ilog2(c->nx);
     int64_t rows = 1, cells = c->nx;
@@ -106,22 +110,26 @@ int make_geo(const avl_config* c, Geo* g)
     g->bscale = (float)(g->qm * c->dt * g->inv_dv[0]);
     g->gam = (float)(g->dv[0] * c->dt * g->inv_dx);
     g->c0f = (float)(c->vmin[0] * g->inv_dv[0] + 0.5);
-    // sort window: at least three bucket rows
-    g->hist_bins = std::max(8192, 3 * c->nx);
+    // sort window: the bucket rows one count tile spans, plus one each side
+    {
+        const double per_row = rows > 0 ? (double)c->n_markers / (double)rows : 0.0;
+        const double span = per_row > 0 ? (double)kCountTile / per_row : 1.0;
+        int64_t want = (int64_t)(std::ceil(span) + 3) * c->nx;
+        want = std::max<int64_t>(want, 4 * (int64_t)c->nx);
+        want = std::min<int64_t>(want, std::max<int64_t>(8192, 4 * (int64_t)c->nx));
+        g->hist_bins = (int)want;
+    }
     // reconstruction decomposition
     if (c->vdim == 1) {
+        // about 2048 wave tasks (each a 63-column strip by rc velocity rows)
+        // so that every CU runs several; AVL_RECON_ROWS overrides rc
         g->nstrip = (c->nx + kReconCols - 1) / kReconCols;
         int want_chunks = std::max(1, 2048 / g->nstrip);
         int rc = std::max(2, std::min(32, c->nv[0] / want_chunks));
+        if (const char* env = std::getenv("AVL_RECON_ROWS")) rc = std::max(1, std::min(256, std::atoi(env)));
         g->rc = rc;
         g->nchunk = (c->nv[0] + rc - 1) / rc;
-        const size_t esz = c->precision ? 4 : 8;
-        const int budget = (int)((160 * 1024 - 1024) / (kReconWaves * 3 * esz));
-        double per_run = c->n_markers > 0 ? (double)c->n_markers / (double)g->nb : 0.0;
-        int expect = (int)(kWave * per_run);
-        int cap = std::max(512, 2 * expect + 256);
-        cap = std::min(budget, ((cap + 63) / 64) * 64);
-        g->cap = std::max(64, cap);
+        g->cap = recon_capacity(c->precision);
     } else {
         // 1D-3V FP32 encoding of the x-velocity dual index
         int jr = 1;
@@ -174,11 +182,8 @@ void make_layout(const avl_config* c, const Geo& g, Layout* L)
 void fit_lds(Geo* g, int lds)
 {
     const int esz = g->prec ? 4 : 8;
-    if (g->vdim == 1) {
-        int budget = (lds - 256) / (kReconWaves * 3 * esz);
-        budget = (budget / 64) * 64;
-        if (g->cap > budget) g->cap = budget;
-    }
+    (void)esz;
+    if (g->vdim == 1) g->cap = recon_capacity(g->prec);
     const int fixed = esz * g->nx + (g->prec ? (int)sizeof(RowShift) * (g->nv[0] + 1) : 0) + 64;
     int bins = (lds - fixed) / 4;
     bins = (bins >> g->lognx) << g->lognx;
@@ -360,27 +365,34 @@ int do_sort(avl_handle* h, bool push, double kick)
     return AVL_OK;
 }
 
+// Reconstruction of f and the rho moment (the reconstruction kernel writes
+// per-chunk column partials; a second kernel adds them in chunk order).
 int do_recon(avl_handle* h, void* Dgrid)
 {
-    Timer t(h, AVL_K_RECONSTRUCT);
-    if (h->g.vdim == 1)
-        AVL_TRY(launch_recon(h->g, marker_view(h, h->cur), h->offsets, h->fgrid, Dgrid, h->rho_part, h->st));
-    else
-        AVL_TRY(launch_recon3(h->g, marker_view(h, h->cur), h->offsets, h->fgrid, Dgrid, h->rho_part, h->scratch3,
-                              h->st));
-    // rho stays valid when the markers have not moved since it was formed
-    if (!h->have_f) h->have_rho = false;
+    {
+        Timer t(h, AVL_K_RECONSTRUCT);
+        if (h->g.vdim == 1)
+            AVL_TRY(launch_recon(h->g, marker_view(h, h->cur), h->offsets, h->fgrid, Dgrid, h->rho_part, h->st));
+        else
+            AVL_TRY(launch_recon3(h->g, marker_view(h, h->cur), h->offsets, h->fgrid, Dgrid, h->rho_part,
+                                  h->scratch3, h->st));
+    }
+    {
+        Timer t(h, AVL_K_MOMENTS);
+        AVL_TRY(launch_moments(h->g, h->rho_part, h->rho, h->st));
+    }
     h->have_f = true;
+    h->have_rho = true;
     return AVL_OK;
 }
 
-int do_field(avl_handle* h, const double* rho_in, bool diag, double* W_out, bool solve = true)
+int do_field(avl_handle* h, const double* rho_src, bool diag, double* W_out)
 {
     Timer t(h, AVL_K_FIELD);
-    AVL_TRY(launch_field(h->g, h->rho_part, rho_in, h->rho, h->E, h->tw, h->green, h->diag, h->ctr, diag ? 1 : 0,
-                         W_out, h->flags, solve ? 1 : 0, h->st));
+    AVL_TRY(launch_field(h->g, rho_src, nullptr, h->E, h->tw, h->green, h->diag,
+                         h->ctr, diag ? 1 : 0, W_out, h->flags, h->st));
     h->have_rho = true;
-    if (solve) h->have_E = true;
+    h->have_E = true;
     return AVL_OK;
 }
 
@@ -390,7 +402,7 @@ int one_step(avl_handle* h)
     int rc = do_sort(h, true, kick_fraction(h));
     if (rc) return rc;
     if ((rc = do_recon(h, nullptr))) return rc;
-    if ((rc = do_field(h, nullptr, true, nullptr))) return rc;
+    if ((rc = do_field(h, h->rho, true, nullptr))) return rc;
     h->steps += 1;
     return AVL_OK;
 }
@@ -434,7 +446,7 @@ int load_markers(avl_handle* h, const double* x, const double* v, const double* 
     int rc;
     if ((rc = do_sort(h, false, 1.0))) return rc;
     if ((rc = do_recon(h, nullptr))) return rc;
-    if ((rc = do_field(h, nullptr, false, nullptr))) return rc;
+    if ((rc = do_field(h, h->rho, false, nullptr))) return rc;
     return AVL_OK;
 }
 
@@ -576,9 +588,7 @@ int avl_reconstruct(avl_handle* h, void* f_out, void* D_out)
 int avl_moments(avl_handle* h, double* rho_out)
 {
     if (!h) return AVL_EINVAL;
-    if (!h->have_f) return AVL_ESTATE;
-    int rc = do_field(h, nullptr, false, nullptr, false);
-    if (rc) return rc;
+    if (!h->have_f || !h->have_rho) return AVL_ESTATE;
     if (rho_out) AVL_TRY(hipMemcpyAsync(rho_out, h->rho, sizeof(double) * h->g.nx, hipMemcpyDeviceToDevice, h->st));
     return AVL_OK;
 }
@@ -774,7 +784,8 @@ double avl_kernel_bytes(const avl_handle* h, int kernel)
     case AVL_K_SCAN: return 3.0 * 4.0 * (g.nb + 1.0);           // counts read twice, offsets written
     case AVL_K_SCATTER: return 2.0 * n * mk;                    // read and write every marker
     case AVL_K_RECONSTRUCT: return n * mk + cells * esz;        // read markers, write f
-    case AVL_K_FIELD: return 8.0 * g.nx * (g.nchunk + 2.0);
+    case AVL_K_MOMENTS: return 8.0 * g.nx * (g.nchunk + 1.0);       // chunk partials in, rho out
+    case AVL_K_FIELD: return 8.0 * g.nx * 2.0;
     case AVL_K_STEP: return n * (pos + 3.0 * mk) + cells * esz;
     default: return 0.0;
     }

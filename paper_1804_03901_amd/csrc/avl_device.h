@@ -22,13 +22,14 @@ enum : int { FLAG_NONFINITE = 1, FLAG_SLOT = 2, FLAG_RANGE = 4 };
 
 constexpr int kWave = 64;
 constexpr int kSortThreads = 256;
-constexpr int kSortMPT = 8;                               // markers per thread in sort passes
+constexpr int kSortMPT = 8;                               // markers per thread, scatter pass
 constexpr int kSortTile = kSortThreads * kSortMPT;
+constexpr int kCountMPT = 16;                             // markers per thread, count pass
+constexpr int kCountTile = kSortThreads * kCountMPT;
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
 constexpr int kReconCols = kWave - 1;                     // target columns per reconstruct wave
-constexpr int kReconWaves = 4;                            // waves per reconstruct block
 constexpr int kDiagCap = 4096;                            // per-step diagnostics ring
 constexpr int kFieldThreads = 512;
 constexpr int kMaxNx = 4096;
@@ -45,6 +46,7 @@ struct Geo {
     int hist_bins;       // LDS histogram bins per sort block
     int cap;             // markers staged in LDS per reconstruct wave
     int jpad, jrange;    // FP32 1D-3V: x-velocity dual index stored with offset jpad, range jrange
+    int kahan;           // FP32 form: compensated FP32 accumulation instead of FP64 accumulators
     double L, inv_L, dx, inv_dx;
     double vmin[3], dv[3], inv_dv[3];
     double dt, qm, cp;

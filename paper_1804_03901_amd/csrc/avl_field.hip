@@ -44,35 +44,29 @@ __device__ void block_sum3(double& a, double& b, double& c, double* s)
     c = s[2 * NT];
 }
 
-__global__ __launch_bounds__(kFieldThreads) void k_field(Geo g, const double* __restrict__ rho_part,
-                                                         const double* __restrict__ rho_in,
-                                                         double* __restrict__ rho_out, double* __restrict__ E_out,
+__global__ __launch_bounds__(kFieldThreads) void k_field(Geo g, const double* __restrict__ rho_src,
+                                                         double* __restrict__ rho_copy, double* __restrict__ E_out,
                                                          const double2* __restrict__ tw,
                                                          const double* __restrict__ green,
                                                          double* __restrict__ diag_ring,
                                                          long long* __restrict__ step_ctr, int write_diag,
-                                                         double* __restrict__ W_out, int* __restrict__ flags,
-                                                         int solve)
+                                                         double* __restrict__ W_out, int* __restrict__ flags)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    double2* z = reinterpret_cast<double2*>(smem);
-    __shared__ double red[3 * kFieldThreads];
     const int nx = g.nx, lg = g.lognx;
     const int half_n = nx >> 1;
+    double2* z = reinterpret_cast<double2*>(smem);
+    double2* stw = z + nx;
+    double* sgr = reinterpret_cast<double*>(stw + half_n);
+    __shared__ double red[3 * kFieldThreads];
 
     for (int i = threadIdx.x; i < nx; i += blockDim.x) {
-        double r;
-        if (rho_in) {
-            r = rho_in[i];
-        } else {
-            double s = 0.0;
-            for (int c = 0; c < g.nchunk; ++c) s += rho_part[(size_t)c * nx + i];
-            r = s * g.q_vol;
-        }
-        if (rho_out) rho_out[i] = r;
+        const double r = rho_src[i];
+        if (rho_copy) rho_copy[i] = r;
         z[bitrev(i, lg)] = make_double2(r, 0.0);
+        sgr[i] = green[i];
+        if (i < half_n) stw[i] = tw[i];
     }
-    if (!solve) return;
     __syncthreads();
     // forward transform, rho_hat_m = sum_i rho_i exp(-2 pi i m i / nx)
     for (int lh = 0; (1 << lh) < nx; ++lh) {
@@ -80,7 +74,7 @@ __global__ __launch_bounds__(kFieldThreads) void k_field(Geo g, const double* __
         for (int b = threadIdx.x; b < half_n; b += blockDim.x) {
             const int grp = b >> lh, p = b & (half - 1);
             const int i0 = grp * len + p, i1 = i0 + half;
-            const double2 t = cmul(tw[p * stride], z[i1]);
+            const double2 t = cmul(stw[p * stride], z[i1]);
             const double2 u = z[i0];
             z[i0] = make_double2(u.x + t.x, u.y + t.y);
             z[i1] = make_double2(u.x - t.x, u.y - t.y);
@@ -90,7 +84,7 @@ __global__ __launch_bounds__(kFieldThreads) void k_field(Geo g, const double* __
     // E_hat_m = -i * (c_p kappa_m / K_m^2) * rho_hat_m
     for (int m = threadIdx.x; m < nx; m += blockDim.x) {
         const double2 r = z[m];
-        const double c = green[m];
+        const double c = sgr[m];
         z[m] = make_double2(c * r.y, -c * r.x);
     }
     __syncthreads();
@@ -101,7 +95,7 @@ __global__ __launch_bounds__(kFieldThreads) void k_field(Geo g, const double* __
             const int grp = b >> lh, p = b & (half - 1);
             const int i0 = grp * len + p, i1 = i0 + half;
             const double2 u = z[i0], v = z[i1];
-            const double2 w = tw[p * stride];
+            const double2 w = stw[p * stride];
             z[i0] = make_double2(u.x + v.x, u.y + v.y);
             z[i1] = cmul(make_double2(u.x - v.x, u.y - v.y), make_double2(w.x, -w.y));
         }
@@ -115,7 +109,7 @@ __global__ __launch_bounds__(kFieldThreads) void k_field(Geo g, const double* __
         E_out[i] = E;
         if (!isfinite(E)) bad = 1;
         sw += E * E;
-        const double2 w = i < half_n ? tw[i] : make_double2(-tw[i - half_n].x, -tw[i - half_n].y);
+        const double2 w = i < half_n ? stw[i] : make_double2(-stw[i - half_n].x, -stw[i - half_n].y);
         sre += E * w.x;
         sim += E * w.y;
     }
@@ -134,16 +128,16 @@ __global__ __launch_bounds__(kFieldThreads) void k_field(Geo g, const double* __
     }
 }
 
-hipError_t launch_field(const Geo& g, const double* rho_part, const double* rho_in, double* rho_out,
-                        double* E_out, const double2* tw, const double* green, double* diag_ring,
-                        long long* step_ctr, int write_diag, double* W_out, int* flags, int solve, hipStream_t st)
+hipError_t launch_field(const Geo& g, const double* rho_src, double* rho_copy, double* E_out, const double2* tw,
+                        const double* green, double* diag_ring, long long* step_ctr, int write_diag, double* W_out,
+                        int* flags, hipStream_t st)
 {
-    const size_t smem = sizeof(double2) * g.nx;
+    const size_t smem = (sizeof(double2) + sizeof(double2) / 2 + sizeof(double)) * g.nx;
     static int granted = 0;
     hipError_t e = ensure_lds((const void*)k_field, smem, granted);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_field, dim3(1), dim3(kFieldThreads), smem, st, g, rho_part, rho_in, rho_out, E_out,
-                       tw, green, diag_ring, step_ctr, write_diag, W_out, flags, solve);
+    hipLaunchKernelGGL(k_field, dim3(1), dim3(kFieldThreads), smem, st, g, rho_src, rho_copy, E_out, tw, green,
+                       diag_ring, step_ctr, write_diag, W_out, flags);
     return hipGetLastError();
 }
 

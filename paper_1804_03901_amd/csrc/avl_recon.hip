@@ -9,7 +9,13 @@
 // dual rows of its chunk bottom to top: it stages the row segment's markers
 // (one contiguous range of the sorted arrays, plus the wrapped run at x = L
 // for the first strip) into LDS with coalesced loads, then every lane sums its
-// own run into four (N, D) corner partials.  Target cell (i, j) is then
+// own run into four (N, D) corner partials.  Staging is software-pipelined:
+// the next row's markers are loaded into registers while the current row is
+// summed, so each wave keeps a full row segment (16-24 KB) of loads in
+// flight.  Row segments larger than the LDS capacity are summed straight from
+// global memory (same order, slower).  Tasks are dealt to blocks so that each
+// XCD gets consecutive chunks of the same strip, whose shared halo rows then
+// hit that XCD's L2.  Target cell (i, j) is then
 //   ((up01(i, j-1) + up11(i-1, j-1)) + S00(i, j)) + S10(i-1, j)
 // where the (i-1) terms come from the neighbouring lane by a shuffle and the
 // "up" terms are carried in registers from the previous dual row.  Every sum
@@ -18,6 +24,8 @@
 // rho: each lane also sums f over the rows of its chunk for its column and
 // writes one partial per (chunk, column); the field kernel adds the chunk
 // partials in chunk order, in FP64.
+#include <type_traits>
+
 #include "avl_device.h"
 
 namespace avl {
@@ -42,9 +50,39 @@ struct Plain {
     __device__ double value() const { return s; }
 };
 
-template <int PREC> struct ReconTypes;
-template <> struct ReconTypes<0> { using T = double; using Acc = Plain; using M = M64; };
-template <> struct ReconTypes<1> { using T = float; using Acc = Kahan<float>; using M = M32; };
+// Per-run moments of the marker offsets: with them the four cloud-in-cell
+// corner sums of a run are
+//   N11 = S_abf, N10 = S_af - S_abf, N01 = S_bf - S_abf, N00 = S_f - S_af - S_bf + S_abf
+//   D11 = S_ab,  D10 = S_a - S_ab,   D01 = S_b - S_ab,   D00 = n - S_a - S_b + S_ab
+// (expanding (1-a)(1-b) etc.), so a marker costs four products and seven
+// accumulations instead of eight weighted sums.  The accumulators are FP64
+// (A = Plain) or compensated FP32 (A = Kahan<float>).
+template <typename A> struct Moments {
+    A f, af, bf, abf, a, b, ab;
+    __device__ void zero() { f.zero(); af.zero(); bf.zero(); abf.zero(); a.zero(); b.zero(); ab.zero(); }
+    template <typename T> __device__ void add(T a_, T b_, T f_) {
+        const T af_ = a_ * f_, bf_ = b_ * f_, ab_ = a_ * b_, abf_ = ab_ * f_;
+        f.add(f_); af.add(af_); bf.add(bf_); abf.add(abf_);
+        a.add(a_); b.add(b_); ab.add(ab_);
+    }
+};
+
+struct Corners {
+    double n00, n10, n01, n11, d00, d10, d01, d11;
+    template <typename A> __device__ void from(const Moments<A>& M, int len) {
+        const double Sf = M.f.value(), Saf = M.af.value(), Sbf = M.bf.value(), Sabf = M.abf.value();
+        const double Sa = M.a.value(), Sb = M.b.value(), Sab = M.ab.value();
+        n11 = Sabf;
+        n10 = Saf - Sabf;
+        n01 = Sbf - Sabf;
+        n00 = (Sf - Saf) - n01;
+        d11 = Sab;
+        d10 = Sa - Sab;
+        d01 = Sb - Sab;
+        d00 = ((double)len - Sa) - d01;
+    }
+};
+
 
 __device__ __forceinline__ void wave_sync_lds()
 {
@@ -52,52 +90,147 @@ __device__ __forceinline__ void wave_sync_lds()
     __builtin_amdgcn_wave_barrier();
 }
 
-template <int PREC>
-__device__ __forceinline__ void load_ab(const Geo& g, const typename ReconTypes<PREC>::M& m, int q,
-                                        typename ReconTypes<PREC>::T& a, typename ReconTypes<PREC>::T& b,
-                                        typename ReconTypes<PREC>::T& f);
+template <int PREC> struct RT;
+template <> struct RT<0> {
+    using T = double;
+    using M = M64;
+    static constexpr int KU = 20;    // register prefetch depth per lane (markers)
+};
+template <> struct RT<1> {
+    using T = float;
+    using M = M32;
+    static constexpr int KU = 24;
+};
 
-template <>
-__device__ __forceinline__ void load_ab<0>(const Geo& g, const M64& m, int q, double& a, double& b, double& f)
+template <int PREC> constexpr int recon_cap() { return kWave * RT<PREC>::KU; }
+
+// bytes of LDS per wave
+template <int PREC> constexpr size_t recon_lds()
 {
-    int ix, jp[1];
-    double bb[1];
-    double vv[1] = {m.v[q]};
-    locate64<1>(g, m.x[q], vv, ix, jp, a, bb);
-    b = bb[0];
-    f = m.f[q];
+    return PREC ? sizeof(float4) * recon_cap<PREC>() : (sizeof(double2) + sizeof(double)) * recon_cap<PREC>();
 }
 
-template <>
-__device__ __forceinline__ void load_ab<1>(const Geo& g, const M32& m, int q, float& a, float& b, float& f)
+// Raw marker fields held in registers between the load and the LDS store.
+template <int PREC> struct Raw;
+template <> struct Raw<0> {
+    double x, v, f;
+    __device__ void load(const M64& m, int q) { x = m.x[q]; v = m.v[q]; f = m.f[q]; }
+};
+template <> struct Raw<1> {
+    float a, b, f;
+    __device__ void load(const M32& m, int q) { a = m.a[q]; b = m.b[q]; f = m.f[q]; }
+};
+
+template <int PREC> struct Lds;
+template <> struct Lds<0> {
+    double2* ab;
+    double* f;
+    __device__ void init(unsigned char* base) {
+        ab = reinterpret_cast<double2*>(base);
+        f = reinterpret_cast<double*>(base + sizeof(double2) * recon_cap<0>());
+    }
+    __device__ void put(const Geo& g, int p, const Raw<0>& r) {
+        int ix, jp[1];
+        double a, b[1];
+        double vv[1] = {r.v};
+        locate64<1>(g, r.x, vv, ix, jp, a, b);
+        ab[p] = make_double2(a, b[0]);
+        f[p] = r.f;
+    }
+    __device__ void get(int p, double& a, double& b, double& ff) const {
+        double2 t = ab[p];
+        a = t.x;
+        b = t.y;
+        ff = f[p];
+    }
+};
+template <> struct Lds<1> {
+    float4* abf;
+    __device__ void init(unsigned char* base) { abf = reinterpret_cast<float4*>(base); }
+    __device__ void put(const Geo&, int p, const Raw<1>& r) { abf[p] = make_float4(r.a, r.b, r.f, 0.0f); }
+    __device__ void get(int p, float& a, float& b, float& ff) const {
+        float4 t = abf[p];
+        a = t.x;
+        b = t.y;
+        ff = t.z;
+    }
+};
+
+template <int PREC>
+__device__ __forceinline__ void load_global(const Geo& g, const typename RT<PREC>::M& m, int q,
+                                            typename RT<PREC>::T& a, typename RT<PREC>::T& b,
+                                            typename RT<PREC>::T& f)
 {
-    a = m.a[q];
-    b = m.b[q];
-    f = m.f[q];
+    Raw<PREC> r;
+    r.load(m, q);
+    if constexpr (PREC == 0) {
+        int ix, jp[1];
+        double bb[1];
+        double vv[1] = {r.v};
+        locate64<1>(g, r.x, vv, ix, jp, a, bb);
+        b = bb[0];
+        f = r.f;
+    } else {
+        a = r.a;
+        b = r.b;
+        f = r.f;
+    }
+}
+
+// Marker range of one dual-row segment: the contiguous runs of lanes
+// first..last plus (first strip only) the wrapped run of lane 0.
+struct Seg {
+    int lo, nmain, wbeg, total;
+    __device__ int index(int p) const { return p < nmain ? lo + p : wbeg + (p - nmain); }
+};
+
+__device__ __forceinline__ Seg make_seg(int beg, int end, int first_lane, int last_lane, bool wrapped)
+{
+    Seg s;
+    s.lo = __shfl(beg, first_lane, kWave);
+    const int hi = __shfl(end, last_lane, kWave);
+    s.wbeg = __shfl(beg, 0, kWave);
+    const int wend = __shfl(end, 0, kWave);
+    s.nmain = hi - s.lo;
+    s.total = s.nmain + (wrapped ? wend - s.wbeg : 0);
+    return s;
 }
 
 template <int PREC>
-__global__ __launch_bounds__(kWave * kReconWaves) void k_recon_1v(Geo g, typename ReconTypes<PREC>::M m,
-                                                                  const int* __restrict__ offsets,
-                                                                  typename ReconTypes<PREC>::T* __restrict__ fgrid,
-                                                                  typename ReconTypes<PREC>::T* __restrict__ Dgrid,
-                                                                  double* __restrict__ rho_part)
+__device__ __forceinline__ void prefetch(const typename RT<PREC>::M& m, const Seg& s, int lane, Raw<PREC>* r)
 {
-    using T = typename ReconTypes<PREC>::T;
-    using Acc = typename ReconTypes<PREC>::Acc;
+    constexpr int KU = RT<PREC>::KU;
+    if (s.total > recon_cap<PREC>()) return;   // summed from global memory instead
+#pragma unroll
+    for (int k = 0; k < KU; ++k) {
+        const int p = lane + k * kWave;
+        if (p < s.total) r[k].load(m, s.index(p));
+    }
+}
+
+template <int PREC, bool KAHAN>
+__global__ __launch_bounds__(kWave) void k_recon_1v(Geo g, typename RT<PREC>::M m, const int* __restrict__ offsets,
+                                                    typename RT<PREC>::T* __restrict__ fgrid,
+                                                    typename RT<PREC>::T* __restrict__ Dgrid,
+                                                    double* __restrict__ rho_part, int tasks_per_xcd)
+{
+    using T = typename RT<PREC>::T;
+    using A = typename std::conditional<KAHAN, Kahan<float>, Plain>::type;
+    constexpr int KU = RT<PREC>::KU;
+    constexpr int CAP = recon_cap<PREC>();
     extern __shared__ __align__(16) unsigned char smem[];
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wv = threadIdx.x / kWave;
-    const int task = blockIdx.x * kReconWaves + wv;
-    if (task >= g.nstrip * g.nchunk) return;
-    T* sA = reinterpret_cast<T*>(smem) + (size_t)wv * 3 * g.cap;
-    T* sB = sA + g.cap;
-    T* sF = sB + g.cap;
+    const int lane = threadIdx.x;
+    // XCD-aware dealing: blocks go round-robin over the 8 XCDs; give each XCD
+    // a contiguous range of (strip-major) tasks
+    const int task = (blockIdx.x & 7) * tasks_per_xcd + (blockIdx.x >> 3);
+    if ((blockIdx.x >> 3) >= tasks_per_xcd || task >= g.nstrip * g.nchunk) return;
+    Lds<PREC> lds;
+    lds.init(smem);
 
-    const int strip = task % g.nstrip;
-    const int chunk = task / g.nstrip;
+    const int strip = task / g.nchunk;
+    const int chunk = task - strip * g.nchunk;
     const int nx = g.nx;
-    const int col = strip * kReconCols - 1 + lane;        // -1 .. ; -1 is the wrapped column nx-1
+    const int col = strip * kReconCols - 1 + lane;        // -1 is the wrapped column nx-1
     const bool run_ok = col < nx;
     const int colw = col < 0 ? nx - 1 : col;
     const bool tgt_ok = lane >= 1 && col < nx;
@@ -108,113 +241,143 @@ __global__ __launch_bounds__(kWave * kReconWaves) void k_recon_1v(Geo g, typenam
     const int j_begin = chunk * g.rc;
     const int j_end = min(j_begin + g.rc, g.nv[0]);
 
-    Acc upN, upD;
-    upN.zero();
-    upD.zero();
+    auto row_offsets = [&](int jd, int& beg, int& end) {
+        beg = 0;
+        end = 0;
+        if (run_ok && jd < j_end) {
+            const int bk = (jd + 1) * nx + colw;
+            beg = offsets[bk];
+            end = offsets[bk + 1];
+        }
+    };
+
+    Raw<PREC> regs[KU];
+    int beg, end, nbeg, nend;
+    row_offsets(j_begin - 1, beg, end);
+    Seg seg = make_seg(beg, end, first_lane, last_lane, wrapped);
+    prefetch<PREC>(m, seg, lane, regs);
+    row_offsets(j_begin, nbeg, nend);
+
+    double upN = 0.0, upD = 0.0;
     double rp = 0.0;
 
     for (int jd = j_begin - 1; jd < j_end; ++jd) {
-        const int rowbase = (jd + 1) * nx;
-        int beg = 0, end = 0;
-        if (run_ok) {
-            beg = offsets[rowbase + colw];
-            end = offsets[rowbase + colw + 1];
-        }
-        const int lo = __shfl(beg, first_lane, kWave);
-        const int hi = __shfl(end, last_lane, kWave);
-        const int wbeg = __shfl(beg, 0, kWave);
-        const int wend = __shfl(end, 0, kWave);
-        const int nmain = hi - lo;
-        const int total = nmain + (wrapped ? wend - wbeg : 0);
-        const bool staged = total <= g.cap;
-        int p0;
+        const bool staged = seg.total <= CAP;
         if (staged) {
-            for (int p = lane; p < total; p += kWave) {
-                int q = p < nmain ? lo + p : wbeg + (p - nmain);
-                T a, b, f;
-                load_ab<PREC>(g, m, q, a, b, f);
-                sA[p] = a;
-                sB[p] = b;
-                sF[p] = f;
+#pragma unroll
+            for (int k = 0; k < KU; ++k) {
+                const int p = lane + k * kWave;
+                if (p < seg.total) lds.put(g, p, regs[k]);
             }
-            wave_sync_lds();
-            p0 = (wrapped && lane == 0) ? nmain : beg - lo;
-        } else {
-            p0 = beg;
-        }
-        const int len = end - beg;
-
-        Acc n00, n10, n01, n11, d00, d10, d01, d11;
-        n00.zero(); n10.zero(); n01.zero(); n11.zero();
-        d00.zero(); d10.zero(); d01.zero(); d11.zero();
-        for (int k = 0; k < len; ++k) {
-            T a, b, f;
-            if (staged) {
-                a = sA[p0 + k];
-                b = sB[p0 + k];
-                f = sF[p0 + k];
-            } else {
-                load_ab<PREC>(g, m, p0 + k, a, b, f);
-            }
-            const T ua = T(1) - a, ub = T(1) - b;
-            const T w00 = ua * ub, w10 = a * ub, w01 = ua * b, w11 = a * b;
-            n00.add(w00 * f); d00.add(w00);
-            n10.add(w10 * f); d10.add(w10);
-            n01.add(w01 * f); d01.add(w01);
-            n11.add(w11 * f); d11.add(w11);
         }
         wave_sync_lds();
+        const int p0 = staged ? ((wrapped && lane == 0) ? seg.nmain : beg - seg.lo) : beg;
+        const int len = end - beg;
+        // start the next row's loads before summing this one
+        Seg nseg = make_seg(nbeg, nend, first_lane, last_lane, wrapped);
+        if (jd + 1 < j_end) prefetch<PREC>(m, nseg, lane, regs);
+        int nnbeg, nnend;
+        row_offsets(jd + 2, nnbeg, nnend);
+
+        Moments<A> M;
+        M.zero();
+        for (int k = 0; k < len; ++k) {
+            T a, b, f;
+            if (staged) lds.get(p0 + k, a, b, f);
+            else load_global<PREC>(g, m, p0 + k, a, b, f);
+            M.add(a, b, f);
+        }
+        wave_sync_lds();
+        Corners c;
+        c.from(M, len);
 
         // corner partials of the left neighbour run (lane - 1)
-        const T n10l = __shfl_up(n10.value(), 1, kWave);
-        const T d10l = __shfl_up(d10.value(), 1, kWave);
-        const T n11l = __shfl_up(n11.value(), 1, kWave);
-        const T d11l = __shfl_up(d11.value(), 1, kWave);
+        const double n10l = __shfl_up(c.n10, 1, kWave);
+        const double d10l = __shfl_up(c.d10, 1, kWave);
+        const double n11l = __shfl_up(c.n11, 1, kWave);
+        const double d11l = __shfl_up(c.d11, 1, kWave);
 
         if (jd >= j_begin && tgt_ok) {
-            Acc N = upN, D = upD;
-            N.add(n00.value());
-            N.add(n10l);
-            D.add(d00.value());
-            D.add(d10l);
-            const T Nv = N.value(), Dv = D.value();
-            const T fv = Dv > T(0) ? Nv / Dv : T(0);
+            const double Nv = (upN + c.n00) + n10l;
+            const double Dv = (upD + c.d00) + d10l;
+            const double fv = Dv > 0.0 ? Nv / Dv : 0.0;
             const size_t gi = (size_t)jd * nx + col;
-            fgrid[gi] = fv;
-            if (Dgrid) Dgrid[gi] = Dv;
-            rp += (double)fv;
+            fgrid[gi] = (T)fv;
+            if (Dgrid) Dgrid[gi] = (T)Dv;
+            rp += (double)(T)fv;
         }
-        upN.zero();
-        upD.zero();
-        upN.add(n01.value());
-        upN.add(n11l);
-        upD.add(d01.value());
-        upD.add(d11l);
+        upN = c.n01 + n11l;
+        upD = c.d01 + d11l;
+
+        beg = nbeg;
+        end = nend;
+        nbeg = nnbeg;
+        nend = nnend;
+        seg = nseg;
     }
     if (tgt_ok) rho_part[(size_t)chunk * nx + col] = rp;
+}
+
+// rho_i = q prod(dv) sum_c part[c][i]: 64 columns per block, 4 groups of
+// chunks per column summed with independent loads, then combined in a fixed
+// order (deterministic).
+__global__ __launch_bounds__(256) void k_rho(Geo g, const double* __restrict__ part, double* __restrict__ rho)
+{
+    __shared__ double red[4][64];
+    const int c = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + c;
+    double s = 0.0;
+    if (i < g.nx) {
+        int ch = grp;
+        for (; ch + 12 < g.nchunk; ch += 16) {
+            const double a0 = part[(size_t)ch * g.nx + i];
+            const double a1 = part[(size_t)(ch + 4) * g.nx + i];
+            const double a2 = part[(size_t)(ch + 8) * g.nx + i];
+            const double a3 = part[(size_t)(ch + 12) * g.nx + i];
+            s += a0;
+            s += a1;
+            s += a2;
+            s += a3;
+        }
+        for (; ch < g.nchunk; ch += 4) s += part[(size_t)ch * g.nx + i];
+    }
+    red[grp][c] = s;
+    __syncthreads();
+    if (grp == 0 && i < g.nx) rho[i] = (((red[0][c] + red[1][c]) + red[2][c]) + red[3][c]) * g.q_vol;
 }
 
 hipError_t launch_recon(const Geo& g, void* m, const int* offsets, void* fgrid, void* Dgrid,
                         double* rho_part, hipStream_t st)
 {
-    const int tasks = g.nstrip * g.nchunk;
-    const int blocks = (tasks + kReconWaves - 1) / kReconWaves;
-    const size_t esz = g.prec ? sizeof(float) : sizeof(double);
-    const size_t smem = (size_t)kReconWaves * 3 * g.cap * esz;
     if (g.vdim != 1) return hipErrorNotSupported;
-    static int granted[2] = {0, 0};
-    {
-        const void* fn = g.prec == 0 ? (const void*)k_recon_1v<0> : (const void*)k_recon_1v<1>;
-        hipError_t e = ensure_lds(fn, smem, granted[g.prec]);
-        if (e != hipSuccess) return e;
-    }
-    if (g.prec == 0)
-        hipLaunchKernelGGL(k_recon_1v<0>, dim3(blocks), dim3(kWave * kReconWaves), smem, st, g,
-                           *reinterpret_cast<M64*>(m), offsets, (double*)fgrid, (double*)Dgrid, rho_part);
+    const int tasks = g.nstrip * g.nchunk;
+    const int per_xcd = (tasks + 7) / 8;
+    const int blocks = per_xcd * 8;
+    const size_t smem = g.prec ? recon_lds<1>() : recon_lds<0>();
+    static int granted[3] = {0, 0, 0};
+    const int var = g.prec == 0 ? 0 : (g.kahan ? 2 : 1);
+    const void* fns[3] = {(const void*)k_recon_1v<0, false>, (const void*)k_recon_1v<1, false>,
+                          (const void*)k_recon_1v<1, true>};
+    hipError_t e = ensure_lds(fns[var], smem, granted[var]);
+    if (e != hipSuccess) return e;
+    if (var == 0)
+        hipLaunchKernelGGL((k_recon_1v<0, false>), dim3(blocks), dim3(kWave), smem, st, g, *reinterpret_cast<M64*>(m),
+                           offsets, (double*)fgrid, (double*)Dgrid, rho_part, per_xcd);
+    else if (var == 1)
+        hipLaunchKernelGGL((k_recon_1v<1, false>), dim3(blocks), dim3(kWave), smem, st, g, *reinterpret_cast<M32*>(m),
+                           offsets, (float*)fgrid, (float*)Dgrid, rho_part, per_xcd);
     else
-        hipLaunchKernelGGL(k_recon_1v<1>, dim3(blocks), dim3(kWave * kReconWaves), smem, st, g,
-                           *reinterpret_cast<M32*>(m), offsets, (float*)fgrid, (float*)Dgrid, rho_part);
+        hipLaunchKernelGGL((k_recon_1v<1, true>), dim3(blocks), dim3(kWave), smem, st, g, *reinterpret_cast<M32*>(m),
+                           offsets, (float*)fgrid, (float*)Dgrid, rho_part, per_xcd);
     return hipGetLastError();
 }
+
+hipError_t launch_moments(const Geo& g, const double* rho_part, double* rho, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rho, dim3((g.nx + 63) / 64), dim3(256), 0, st, g, rho_part, rho);
+    return hipGetLastError();
+}
+
+int recon_capacity(int prec) { return prec ? recon_cap<1>() : recon_cap<0>(); }
 
 }  // namespace avl

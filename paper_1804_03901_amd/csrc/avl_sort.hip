@@ -77,17 +77,11 @@ template <int PREC> struct MarkersOf;
 template <> struct MarkersOf<0> { using T = M64; using E = double; };
 template <> struct MarkersOf<1> { using T = M32; using E = float; };
 
-// The LDS window of a sort block: bucket rows [r_lo, r_lo + nrows) around the
-// rows of the block's first and last marker (which bound the block's rows,
-// the input being sorted), widened by one row each way.
-template <int PREC, int VD>
-__device__ void sort_window(const Geo& g, const typename MarkersOf<PREC>::T& m, int first, int last,
-                            int* s_lo, int* s_nb)
+// The LDS window of a sort block: bucket rows around the rows of the block's
+// first and last marker (which bound the block's rows, the input being
+// sorted), widened by one row each way, at most hist_bins buckets.
+__device__ __forceinline__ void set_window(const Geo& g, int b0, int b1, int* s_lo, int* s_nb)
 {
-    Pay<PREC, VD> p0, p1;
-    p0.load(m, g.n, first, false);
-    p1.load(m, g.n, last, false);
-    int b0 = p0.bucket(g), b1 = p1.bucket(g);
     int r0 = (b0 >= g.nb ? g.nrow - 1 : b0 >> g.lognx);
     int r1 = (b1 >= g.nb ? g.nrow - 1 : b1 >> g.lognx);
     int lo = min(r0, r1) - 1, hi = max(r0, r1) + 1;
@@ -99,10 +93,86 @@ __device__ void sort_window(const Geo& g, const typename MarkersOf<PREC>::T& m, 
     *s_nb = (hi - lo + 1) << g.lognx;
 }
 
+// Wavefront-aggregated LDS histogram update.  A wave holds 64 consecutive
+// markers of the previous order, which land in only a handful of new buckets:
+// lanes with equal bins are grouped with ballots, the first lane of each group
+// adds the group size, and every lane gets its rank among all markers of its
+// bin in this block (RANK) -- one conflict-free LDS atomic per distinct bin
+// instead of one per marker.  `win` marks lanes with an in-window bin; all
+// lanes of the wave must call this.
+template <bool RANK>
+__device__ __forceinline__ int wave_hist_add(int* hist, int rel, bool win)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    unsigned long long pending = __ballot(win);
+    int leader = 0, wrank = 0, cnt = 0;
+    while (pending) {
+        const int l = __ffsll((unsigned long long)pending) - 1;
+        const int key = __shfl(rel, l, kWave);
+        const unsigned long long same = __ballot(win && rel == key) & pending;
+        if ((same >> lane) & 1ull) {
+            leader = l;
+            wrank = __popcll(same & below);
+        }
+        if (lane == l) cnt = __popcll(same);
+        pending &= ~same;
+    }
+    int base = 0;
+    if (cnt) {
+        if (RANK) base = atomicAdd(&hist[rel], cnt);
+        else atomicAdd(&hist[rel], cnt);
+    }
+    if (!RANK) return -1;
+    base = __shfl(base, leader, kWave);
+    return win ? base + wrank : -1;
+}
+
 template <int PREC>
 __device__ void stage_field(const Geo& g, const double* E, typename MarkersOf<PREC>::E* sE)
 {
     for (int i = threadIdx.x; i < g.nx; i += blockDim.x) sE[i] = (typename MarkersOf<PREC>::E)E[i];
+}
+
+template <int PREC>
+struct SortSmem {
+    typename MarkersOf<PREC>::E* sE;
+    RowShift* sRow;
+    int* hist;
+    __device__ SortSmem(unsigned char* smem, const Geo& g) {
+        using ET = typename MarkersOf<PREC>::E;
+        sE = reinterpret_cast<ET*>(smem);
+        sRow = reinterpret_cast<RowShift*>(smem + sizeof(ET) * g.nx);
+        hist = reinterpret_cast<int*>(smem + sizeof(ET) * g.nx + (PREC ? sizeof(RowShift) * (g.nv[0] + 1) : 0));
+    }
+};
+
+// Block prologue shared by count and scatter: stage the field (and drift
+// table), find the histogram window from the already-loaded first and last
+// markers, clear the window.  Marker loads are issued before this runs, so
+// their latency overlaps the window set-up.
+template <int PREC, int VD, int MPT, bool PUSH>
+__device__ __forceinline__ void sort_prologue(const Geo& g, const SortSmem<PREC>& sm, const Pay<PREC, VD>* p,
+                                              int base, int last, const double* E, const RowShift* rows_g,
+                                              int* s_b, int* s_lo, int* s_nb)
+{
+    if (PUSH) {
+        stage_field<PREC>(g, E, sm.sE);
+        if (PREC)
+            for (int i = threadIdx.x; i <= g.nv[0]; i += blockDim.x) sm.sRow[i] = rows_g[i];
+    }
+#pragma unroll
+    for (int k = 0; k < MPT; ++k) {
+        const int i = base + k * kSortThreads + threadIdx.x;
+        if (i == base) s_b[0] = p[k].bucket(g);
+        if (i == last) s_b[1] = p[k].bucket(g);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) set_window(g, s_b[0], s_b[1], s_lo, s_nb);
+    __syncthreads();
+    const int nbw = *s_nb;
+    for (int i = threadIdx.x; i < nbw; i += blockDim.x) sm.hist[i] = 0;
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -115,45 +185,40 @@ __global__ __launch_bounds__(kSortThreads) void k_count(Geo g, typename MarkersO
                                                         double dtk, float bk,
                                                         int* __restrict__ counts, int* __restrict__ flags)
 {
-    using ET = typename MarkersOf<PREC>::E;
+    constexpr int MPT = kCountMPT;
     extern __shared__ __align__(16) unsigned char smem[];
-    ET* sE = reinterpret_cast<ET*>(smem);
-    RowShift* sRow = reinterpret_cast<RowShift*>(smem + sizeof(ET) * g.nx);
-    int* hist = reinterpret_cast<int*>(smem + sizeof(ET) * g.nx + (PREC ? sizeof(RowShift) * (g.nv[0] + 1) : 0));
-    __shared__ int s_lo, s_nb, s_flags;
-    const int base = blockIdx.x * kSortTile;
-    const int last = min(base + kSortTile, g.n) - 1;
-    if (threadIdx.x == 0) {
-        sort_window<PREC, VD>(g, m, base, last, &s_lo, &s_nb);
-        s_flags = 0;
+    SortSmem<PREC> sm(smem, g);
+    __shared__ int s_b[2], s_lo, s_nb, s_flags;
+    const int base = blockIdx.x * kCountTile;
+    const int last = min(base + kCountTile, g.n) - 1;
+    Pay<PREC, VD> p[MPT];
+#pragma unroll
+    for (int k = 0; k < MPT; ++k) {
+        const int i = base + k * kSortThreads + threadIdx.x;
+        if (i <= last) p[k].load(m, g.n, i, false);
     }
-    if (PUSH) {
-        stage_field<PREC>(g, E, sE);
-        if (PREC)
-            for (int i = threadIdx.x; i <= g.nv[0]; i += blockDim.x) sRow[i] = rows_g[i];
-    }
-    __syncthreads();
+    if (threadIdx.x == 0) s_flags = 0;
+    sort_prologue<PREC, VD, MPT, PUSH>(g, sm, p, base, last, E, rows_g, s_b, &s_lo, &s_nb);
     const int lo = s_lo, nbw = s_nb;
-    for (int i = threadIdx.x; i < nbw; i += blockDim.x) hist[i] = 0;
-    __syncthreads();
     int fl = 0;
-#pragma unroll 4
-    for (int k = 0; k < kSortMPT; ++k) {
-        int i = base + k * kSortThreads + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < MPT; ++k) {
+        const int i = base + k * kSortThreads + threadIdx.x;
+        int rel = -1;
+        bool win = false;
         if (i <= last) {
-            Pay<PREC, VD> p;
-            p.load(m, g.n, i, false);
-            if (PUSH) p.push(g, sE, sRow, dtk, bk, fl);
-            int bkt = p.bucket(g);
-            int rel = bkt - lo;
-            if (rel >= 0 && rel < nbw) atomicAdd(&hist[rel], 1);
-            else atomicAdd(&counts[bkt], 1);
+            if (PUSH) p[k].push(g, sm.sE, sm.sRow, dtk, bk, fl);
+            const int bkt = p[k].bucket(g);
+            rel = bkt - lo;
+            win = rel >= 0 && rel < nbw;
+            if (!win) atomicAdd(&counts[bkt], 1);
         }
+        wave_hist_add<false>(sm.hist, rel, win);
     }
     if (fl) atomicOr(&s_flags, fl);
     __syncthreads();
     for (int i = threadIdx.x; i < nbw; i += blockDim.x) {
-        int c = hist[i];
+        const int c = sm.hist[i];
         if (c) atomicAdd(&counts[lo + i], c);
     }
     if (threadIdx.x == 0 && s_flags) atomicOr(flags, s_flags);
@@ -171,67 +236,62 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(Geo g, typename Marker
                                                           const int* __restrict__ offsets,
                                                           int* __restrict__ counts, int* __restrict__ flags)
 {
-    using ET = typename MarkersOf<PREC>::E;
+    constexpr int MPT = kSortMPT;
     extern __shared__ __align__(16) unsigned char smem[];
-    ET* sE = reinterpret_cast<ET*>(smem);
-    RowShift* sRow = reinterpret_cast<RowShift*>(smem + sizeof(ET) * g.nx);
-    int* hist = reinterpret_cast<int*>(smem + sizeof(ET) * g.nx + (PREC ? sizeof(RowShift) * (g.nv[0] + 1) : 0));
-    __shared__ int s_lo, s_nb, s_flags;
+    SortSmem<PREC> sm(smem, g);
+    __shared__ int s_b[2], s_lo, s_nb, s_flags;
     const int base = blockIdx.x * kSortTile;
     const int last = min(base + kSortTile, g.n) - 1;
-    if (threadIdx.x == 0) {
-        sort_window<PREC, VD>(g, src, base, last, &s_lo, &s_nb);
-        s_flags = 0;
+    Pay<PREC, VD> p[MPT];
+#pragma unroll
+    for (int k = 0; k < MPT; ++k) {
+        const int i = base + k * kSortThreads + threadIdx.x;
+        if (i <= last) p[k].load(src, g.n, i, true);
     }
-    if (PUSH) {
-        stage_field<PREC>(g, E, sE);
-        if (PREC)
-            for (int i = threadIdx.x; i <= g.nv[0]; i += blockDim.x) sRow[i] = rows_g[i];
-    }
-    __syncthreads();
+    if (threadIdx.x == 0) s_flags = 0;
+    sort_prologue<PREC, VD, MPT, PUSH>(g, sm, p, base, last, E, rows_g, s_b, &s_lo, &s_nb);
     const int lo = s_lo, nbw = s_nb;
-    for (int i = threadIdx.x; i < nbw; i += blockDim.x) hist[i] = 0;
-    __syncthreads();
-    Pay<PREC, VD> p[kSortMPT];
-    int bkt[kSortMPT], rank[kSortMPT];
+    int bkt[MPT], rank[MPT];
     int fl = 0;
 #pragma unroll
-    for (int k = 0; k < kSortMPT; ++k) {
-        int i = base + k * kSortThreads + threadIdx.x;
+    for (int k = 0; k < MPT; ++k) {
+        const int i = base + k * kSortThreads + threadIdx.x;
         bkt[k] = -1;
+        int rel = -1;
+        bool win = false;
         if (i <= last) {
-            p[k].load(src, g.n, i, true);
-            if (PUSH) p[k].push(g, sE, sRow, dtk, bk, fl);
+            if (PUSH) p[k].push(g, sm.sE, sm.sRow, dtk, bk, fl);
             bkt[k] = p[k].bucket(g);
-            int rel = bkt[k] - lo;
-            rank[k] = (rel >= 0 && rel < nbw) ? atomicAdd(&hist[rel], 1) : -1;
+            rel = bkt[k] - lo;
+            win = rel >= 0 && rel < nbw;
         }
+        rank[k] = wave_hist_add<true>(sm.hist, rel, win);
     }
     __syncthreads();
     // claim each touched bucket's slots: counts[] holds the slots still free,
     // counting down from the run length
     for (int i = threadIdx.x; i < nbw; i += blockDim.x) {
-        int c = hist[i];
+        const int c = sm.hist[i];
         if (c) {
-            int old = atomicSub(&counts[lo + i], c);
+            const int old = atomicSub(&counts[lo + i], c);
             int start = old - c;
             if (start < 0) { fl |= FLAG_SLOT; start = -1; }
-            hist[i] = start;
+            sm.hist[i] = start;
         }
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < kSortMPT; ++k) {
+    for (int k = 0; k < MPT; ++k) {
         if (bkt[k] < 0) continue;
         int slot;
         if (rank[k] >= 0) {
-            int start = hist[bkt[k] - lo];
+            const int start = sm.hist[bkt[k] - lo];
             slot = start < 0 ? -1 : start + rank[k];
         } else {
             slot = atomicSub(&counts[bkt[k]], 1) - 1;
         }
-        int beg = offsets[bkt[k]], end = offsets[bkt[k] + 1];
-        int dest = beg + slot;
+        const int beg = offsets[bkt[k]], end = offsets[bkt[k] + 1];
+        const int dest = beg + slot;
         if (slot < 0 || dest >= end) { fl |= FLAG_SLOT; continue; }
         p[k].store(dst, g.n, dest);
     }
@@ -383,7 +443,8 @@ static hipError_t launch_sort_t(const Geo& g, void* src, void* dst, const double
     using MT = typename MarkersOf<PREC>::T;
     MT s = *reinterpret_cast<MT*>(src);
     MT d = dst ? *reinterpret_cast<MT*>(dst) : s;
-    const int blocks = (g.n + kSortTile - 1) / kSortTile;
+    const int cblocks = (g.n + kCountTile - 1) / kCountTile;
+    const int sblocks = (g.n + kSortTile - 1) / kSortTile;
     const size_t smem = sort_smem<PREC>(g, push);
     if (g.n == 0 && phase != 1) return hipSuccess;   // the scan still runs: offsets become zero
     static int granted[4] = {0, 0, 0, 0};
@@ -396,8 +457,8 @@ static hipError_t launch_sort_t(const Geo& g, void* src, void* dst, const double
         }
     }
     if (phase == 0) {
-        if (push) hipLaunchKernelGGL((k_count<PREC, VD, true>), dim3(blocks), dim3(kSortThreads), smem, st, g, s, E, rows, dtk, bk, counts, flags);
-        else hipLaunchKernelGGL((k_count<PREC, VD, false>), dim3(blocks), dim3(kSortThreads), smem, st, g, s, E, rows, dtk, bk, counts, flags);
+        if (push) hipLaunchKernelGGL((k_count<PREC, VD, true>), dim3(cblocks), dim3(kSortThreads), smem, st, g, s, E, rows, dtk, bk, counts, flags);
+        else hipLaunchKernelGGL((k_count<PREC, VD, false>), dim3(cblocks), dim3(kSortThreads), smem, st, g, s, E, rows, dtk, bk, counts, flags);
     } else if (phase == 1) {
         const int nbt = g.nb + 1;
         const int ntiles = (nbt + kScanTile - 1) / kScanTile;
@@ -405,8 +466,8 @@ static hipError_t launch_sort_t(const Geo& g, void* src, void* dst, const double
         hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, tile_sums, ntiles);
         hipLaunchKernelGGL(k_scan_apply, dim3(ntiles), dim3(kScanThreads), 0, st, counts, nbt, tile_sums, offsets);
     } else {
-        if (push) hipLaunchKernelGGL((k_scatter<PREC, VD, true>), dim3(blocks), dim3(kSortThreads), smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags);
-        else hipLaunchKernelGGL((k_scatter<PREC, VD, false>), dim3(blocks), dim3(kSortThreads), smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags);
+        if (push) hipLaunchKernelGGL((k_scatter<PREC, VD, true>), dim3(sblocks), dim3(kSortThreads), smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags);
+        else hipLaunchKernelGGL((k_scatter<PREC, VD, false>), dim3(sblocks), dim3(kSortThreads), smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags);
     }
     return hipGetLastError();
 }

@@ -50,7 +50,7 @@ def test_workspace_bytes_valid_config():
 
 @pytest.mark.parametrize("bad", [
     dict(nx=48), dict(nx=4), dict(nx=8192), dict(vdim=2), dict(precision=7), dict(first_kick=2),
-    dict(reserved=1), dict(L=0.0), dict(L=float("nan")), dict(dt=-0.1), dict(c_p=0.0), dict(m=0.0),
+    dict(options=2), dict(options=1), dict(L=0.0), dict(L=float("nan")), dict(dt=-0.1), dict(c_p=0.0), dict(m=0.0),
     dict(nv=(1, 1, 1)), dict(vmin=(6.0, 0, 0)), dict(n_markers=-1), dict(n_markers=2 ** 31),
 ])
 def test_invalid_configs_rejected_on_host(bad):
