@@ -99,6 +99,7 @@ int make_geo(const avl_config* c, Geo* g)
     g->nrow = (int)rows;
     g->nb = (int)(rows * c->nx);
     g->n = (int)c->n_markers;
+    g->np = (int)((c->n_markers + 63) / 64 * 64);
     g->L = c->L;
     g->inv_L = 1.0 / c->L;
     g->dx = c->L / c->nx;
@@ -149,7 +150,7 @@ int make_geo(const avl_config* c, Geo* g)
 
 void make_layout(const avl_config* c, const Geo& g, Layout* L)
 {
-    size_t n = (size_t)g.n;
+    size_t n = (size_t)g.np;
     size_t mbytes = c->precision == AVL_FP64 ? sizeof(double) * n * (2 + g.vdim) : 4 * n * (3 + g.vdim);
     size_t esz = c->precision == AVL_FP64 ? 8 : 4;
     size_t cells = (size_t)g.nx;
@@ -228,7 +229,7 @@ void* marker_view(avl_handle* h, int which)
 
 void set_views(avl_handle* h)
 {
-    const size_t n = (size_t)h->g.n;
+    const size_t n = (size_t)h->g.np;
     for (int b = 0; b < 2; ++b) {
         char* p = h->ws + h->lay.markers[b];
         if (h->g.prec == AVL_FP64) {
@@ -426,7 +427,9 @@ int load_markers(avl_handle* h, const double* x, const double* v, const double* 
         // nothing to copy
     } else if (g.prec == AVL_FP64) {
         AVL_TRY(hipMemcpyAsync(h->m64[0].x, x, sizeof(double) * n, hipMemcpyDeviceToDevice, h->st));
-        AVL_TRY(hipMemcpyAsync(h->m64[0].v, v, sizeof(double) * n * g.vdim, hipMemcpyDeviceToDevice, h->st));
+        for (int d = 0; d < g.vdim; ++d)
+            AVL_TRY(hipMemcpyAsync(h->m64[0].v + (size_t)d * g.np, v + (size_t)d * n, sizeof(double) * n,
+                                   hipMemcpyDeviceToDevice, h->st));
         AVL_TRY(hipMemcpyAsync(h->m64[0].f, f, sizeof(double) * n, hipMemcpyDeviceToDevice, h->st));
     } else {
         AVL_TRY(launch_to32(g, x, v, f, h->m32[0], h->flags, h->st));
@@ -697,7 +700,9 @@ int avl_get_markers(avl_handle* h, double* x, double* v, double* f)
     if (g.prec == AVL_FP64) {
         const M64& m = h->m64[h->cur];
         AVL_TRY(hipMemcpyAsync(x, m.x, sizeof(double) * n, hipMemcpyDeviceToDevice, h->st));
-        AVL_TRY(hipMemcpyAsync(v, m.v, sizeof(double) * n * g.vdim, hipMemcpyDeviceToDevice, h->st));
+        for (int d = 0; d < g.vdim; ++d)
+            AVL_TRY(hipMemcpyAsync(v + (size_t)d * n, m.v + (size_t)d * g.np, sizeof(double) * n,
+                                   hipMemcpyDeviceToDevice, h->st));
         AVL_TRY(hipMemcpyAsync(f, m.f, sizeof(double) * n, hipMemcpyDeviceToDevice, h->st));
         return AVL_OK;
     }
@@ -783,7 +788,12 @@ double avl_kernel_bytes(const avl_handle* h, int kernel)
     case AVL_K_PUSH_COUNT: return n * pos;                      // read positions and velocities
     case AVL_K_SCAN: return 3.0 * 4.0 * (g.nb + 1.0);           // counts read twice, offsets written
     case AVL_K_SCATTER: return 2.0 * n * mk;                    // read and write every marker
-    case AVL_K_RECONSTRUCT: return n * mk + cells * esz;        // read markers, write f
+    case AVL_K_RECONSTRUCT: {
+        // every marker's offsets and f (the FP32 form's cell index is implied by
+        // the sorted order), the run offsets, and the f grid written
+        const double rd = g.prec == AVL_FP64 ? mk : 4.0 * (2 + g.vdim);
+        return n * rd + 4.0 * (g.nb + 1.0) + cells * esz;
+    }
     case AVL_K_MOMENTS: return 8.0 * g.nx * (g.nchunk + 1.0);       // chunk partials in, rho out
     case AVL_K_FIELD: return 8.0 * g.nx * 2.0;
     case AVL_K_STEP: return n * (pos + 3.0 * mk) + cells * esz;

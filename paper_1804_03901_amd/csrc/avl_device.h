@@ -41,6 +41,7 @@ struct Geo {
     int nrow;            // number of bucket rows: prod(nv[d] + 1)
     int nb;              // in-range buckets nrow*nx; bucket nb collects the rest
     int n;               // markers
+    int np;              // stride between velocity components in marker storage (n padded to 64)
     int rc;              // target velocity rows per reconstruct chunk (1D-1V)
     int nchunk, nstrip;  // reconstruct chunks along v and column strips along x
     int hist_bins;       // LDS histogram bins per sort block
@@ -58,14 +59,14 @@ struct Geo {
 
 struct M64 {             // plain FP64 marker arrays
     double* x;
-    double* v;           // component d of marker l at v[d*n + l]
+    double* v;           // component d of marker l at v[d*np + l]
     double* f;
 };
 
 struct M32 {             // FP32 form: dual cell index + offsets
     int* cell;
     float* a;
-    float* b;            // component d of marker l at b[d*n + l]
+    float* b;            // component d of marker l at b[d*np + l]
     float* f;
 };
 

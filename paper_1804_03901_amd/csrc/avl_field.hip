@@ -178,7 +178,7 @@ __global__ void k_to32(Geo g, const double* __restrict__ x, const double* __rest
             float b = (float)(t - ft);
             int j0 = (int)ft;
             if (b >= 1.0f) { b = 0.0f; j0 += 1; }
-            m.b[(size_t)d * g.n + i] = b;
+            m.b[(size_t)d * g.np + i] = b;
             jp[d] = j0 + 1;
         }
         int cell;
@@ -218,15 +218,27 @@ __global__ void k_to64(Geo g, M32 m, double* __restrict__ x, double* __restrict_
         if (xx >= g.L) xx -= g.L;
         x[i] = xx;
         for (int d = 0; d < g.vdim; ++d)
-            v[(size_t)d * g.n + i] = g.vmin[d] + ((double)(jp[d] - 1) + 0.5 + (double)m.b[(size_t)d * g.n + i]) * g.dv[d];
+            v[(size_t)d * g.n + i] = g.vmin[d] + ((double)(jp[d] - 1) + 0.5 + (double)m.b[(size_t)d * g.np + i]) * g.dv[d];
         f[i] = (double)m.f[i];
     }
 }
 
-__global__ void k_copy(const float4* __restrict__ src, float4* __restrict__ dst, size_t n16)
+// Streaming copy: each thread moves four 16-byte vectors, all four loads
+// issued before the stores.
+__global__ __launch_bounds__(256) void k_copy(const float4* __restrict__ src, float4* __restrict__ dst, size_t n16)
 {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+    const size_t base = (size_t)blockIdx.x * 1024 + threadIdx.x;
+    float4 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const size_t i = base + (size_t)k * 256;
+        if (i < n16) v[k] = src[i];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const size_t i = base + (size_t)k * 256;
+        if (i < n16) dst[i] = v[k];
+    }
 }
 
 hipError_t launch_validate(const Geo& g, const double* x, const double* v, const double* f, int* bad, hipStream_t st)
@@ -258,8 +270,8 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t st)
 {
     size_t n16 = bytes / 16;
     if (n16 == 0) return hipSuccess;
-    size_t blocks = (n16 + 255) / 256;
-    if (blocks > 16384) blocks = 16384;
+    size_t blocks = (n16 + 1023) / 1024;
+    if (blocks > 0x7fffffffu) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, st, (const float4*)src, (float4*)dst, n16);
     return hipGetLastError();
 }

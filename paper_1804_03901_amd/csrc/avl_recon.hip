@@ -279,13 +279,23 @@ __global__ __launch_bounds__(kWave) void k_recon_1v(Geo g, typename RT<PREC>::M 
         int nnbeg, nnend;
         row_offsets(jd + 2, nnbeg, nnend);
 
+        // Two separate loops: a single loop with a per-iteration choice makes
+        // the compiler fall back to generic (flat) loads, whose waits would also
+        // stall on the prefetch of the next row.
         Moments<A> M;
         M.zero();
-        for (int k = 0; k < len; ++k) {
-            T a, b, f;
-            if (staged) lds.get(p0 + k, a, b, f);
-            else load_global<PREC>(g, m, p0 + k, a, b, f);
-            M.add(a, b, f);
+        if (staged) {
+            for (int k = 0; k < len; ++k) {
+                T a, b, f;
+                lds.get(p0 + k, a, b, f);
+                M.add(a, b, f);
+            }
+        } else {
+            for (int k = 0; k < len; ++k) {
+                T a, b, f;
+                load_global<PREC>(g, m, p0 + k, a, b, f);
+                M.add(a, b, f);
+            }
         }
         wave_sync_lds();
         Corners c;

@@ -21,22 +21,24 @@
 namespace avl {
 
 // ---------------------------------------------------------------------------
-// Marker payloads and their bucket computation, per storage form.
+// Marker payloads and their bucket computation, per storage form.  Component
+// arrays are laid out with the padded stride g.np (a multiple of 64 markers),
+// so a thread's group of consecutive markers can be read with 16-byte loads.
 // ---------------------------------------------------------------------------
 template <int PREC, int VD> struct Pay;
 
 template <int VD> struct Pay<0, VD> {
     double x, v[VD], f;
-    __device__ void load(const M64& m, int n, int i, bool with_f) {
+    __device__ void load(const M64& m, const Geo& g, int i, bool with_f) {
         x = m.x[i];
 #pragma unroll
-        for (int d = 0; d < VD; ++d) v[d] = m.v[(size_t)d * n + i];
+        for (int d = 0; d < VD; ++d) v[d] = m.v[(size_t)d * g.np + i];
         f = with_f ? m.f[i] : 0.0;
     }
-    __device__ void store(const M64& m, int n, int i) const {
+    __device__ void store(const M64& m, const Geo& g, int i) const {
         m.x[i] = x;
 #pragma unroll
-        for (int d = 0; d < VD; ++d) m.v[(size_t)d * n + i] = v[d];
+        for (int d = 0; d < VD; ++d) m.v[(size_t)d * g.np + i] = v[d];
         m.f[i] = f;
     }
     __device__ void push(const Geo& g, const double* sE, const RowShift*, double dtk, float, int& flags) {
@@ -53,18 +55,18 @@ template <int VD> struct Pay<0, VD> {
 template <int VD> struct Pay<1, VD> {
     int cell;
     float a, b[VD], f;
-    __device__ void load(const M32& m, int n, int i, bool with_f) {
+    __device__ void load(const M32& m, const Geo& g, int i, bool with_f) {
         cell = m.cell[i];
         a = m.a[i];
 #pragma unroll
-        for (int d = 0; d < VD; ++d) b[d] = m.b[(size_t)d * n + i];
+        for (int d = 0; d < VD; ++d) b[d] = m.b[(size_t)d * g.np + i];
         f = with_f ? m.f[i] : 0.0f;
     }
-    __device__ void store(const M32& m, int n, int i) const {
+    __device__ void store(const M32& m, const Geo& g, int i) const {
         m.cell[i] = cell;
         m.a[i] = a;
 #pragma unroll
-        for (int d = 0; d < VD; ++d) m.b[(size_t)d * n + i] = b[d];
+        for (int d = 0; d < VD; ++d) m.b[(size_t)d * g.np + i] = b[d];
         m.f[i] = f;
     }
     __device__ void push(const Geo& g, const float* sE, const RowShift* rows, double, float bk, int& flags) {
@@ -76,6 +78,79 @@ template <int VD> struct Pay<1, VD> {
 template <int PREC> struct MarkersOf;
 template <> struct MarkersOf<0> { using T = M64; using E = double; };
 template <> struct MarkersOf<1> { using T = M32; using E = float; };
+
+// K consecutive elements starting at a 16-byte aligned address, as 16-byte loads.
+template <typename T, int K>
+__device__ __forceinline__ void vload(const T* __restrict__ src, T* out)
+{
+    static_assert((K * sizeof(T)) % 16 == 0, "group must be a multiple of 16 bytes");
+    constexpr int V = 16 / sizeof(T);
+#pragma unroll
+    for (int j = 0; j < K / V; ++j) {
+        const int4 t = *reinterpret_cast<const int4*>(src + j * V);
+        __builtin_memcpy(out + j * V, &t, 16);
+    }
+}
+
+// A thread's group of K consecutive markers [first, first+K), all loads issued
+// together.  Past the last marker, indices are clamped (values masked later).
+template <int PREC, int VD, int K> struct Group;
+
+template <int VD, int K> struct Group<0, VD, K> {
+    Pay<0, VD> p[K];
+    __device__ void load(const M64& m, const Geo& g, int first, int last, bool with_f) {
+        if (first + K - 1 <= last) {
+            double t[K];
+            vload<double, K>(m.x + first, t);
+#pragma unroll
+            for (int k = 0; k < K; ++k) p[k].x = t[k];
+#pragma unroll
+            for (int d = 0; d < VD; ++d) {
+                vload<double, K>(m.v + (size_t)d * g.np + first, t);
+#pragma unroll
+                for (int k = 0; k < K; ++k) p[k].v[d] = t[k];
+            }
+            if (with_f) {
+                vload<double, K>(m.f + first, t);
+#pragma unroll
+                for (int k = 0; k < K; ++k) p[k].f = t[k];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; ++k) p[k].load(m, g, min(first + k, last), with_f);
+        }
+    }
+};
+
+template <int VD, int K> struct Group<1, VD, K> {
+    Pay<1, VD> p[K];
+    __device__ void load(const M32& m, const Geo& g, int first, int last, bool with_f) {
+        if (first + K - 1 <= last) {
+            int ti[K];
+            float t[K];
+            vload<int, K>(m.cell + first, ti);
+#pragma unroll
+            for (int k = 0; k < K; ++k) p[k].cell = ti[k];
+            vload<float, K>(m.a + first, t);
+#pragma unroll
+            for (int k = 0; k < K; ++k) p[k].a = t[k];
+#pragma unroll
+            for (int d = 0; d < VD; ++d) {
+                vload<float, K>(m.b + (size_t)d * g.np + first, t);
+#pragma unroll
+                for (int k = 0; k < K; ++k) p[k].b[d] = t[k];
+            }
+            if (with_f) {
+                vload<float, K>(m.f + first, t);
+#pragma unroll
+                for (int k = 0; k < K; ++k) p[k].f = t[k];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; ++k) p[k].load(m, g, min(first + k, last), with_f);
+        }
+    }
+};
 
 // The LDS window of a sort block: bucket rows around the rows of the block's
 // first and last marker (which bound the block's rows, the input being
@@ -91,41 +166,6 @@ __device__ __forceinline__ void set_window(const Geo& g, int b0, int b1, int* s_
     if (hi - lo + 1 > maxrows) hi = lo + maxrows - 1;
     *s_lo = lo << g.lognx;
     *s_nb = (hi - lo + 1) << g.lognx;
-}
-
-// Wavefront-aggregated LDS histogram update.  A wave holds 64 consecutive
-// markers of the previous order, which land in only a handful of new buckets:
-// lanes with equal bins are grouped with ballots, the first lane of each group
-// adds the group size, and every lane gets its rank among all markers of its
-// bin in this block (RANK) -- one conflict-free LDS atomic per distinct bin
-// instead of one per marker.  `win` marks lanes with an in-window bin; all
-// lanes of the wave must call this.
-template <bool RANK>
-__device__ __forceinline__ int wave_hist_add(int* hist, int rel, bool win)
-{
-    const int lane = threadIdx.x & (kWave - 1);
-    const unsigned long long below = (1ull << lane) - 1ull;
-    unsigned long long pending = __ballot(win);
-    int leader = 0, wrank = 0, cnt = 0;
-    while (pending) {
-        const int l = __ffsll((unsigned long long)pending) - 1;
-        const int key = __shfl(rel, l, kWave);
-        const unsigned long long same = __ballot(win && rel == key) & pending;
-        if ((same >> lane) & 1ull) {
-            leader = l;
-            wrank = __popcll(same & below);
-        }
-        if (lane == l) cnt = __popcll(same);
-        pending &= ~same;
-    }
-    int base = 0;
-    if (cnt) {
-        if (RANK) base = atomicAdd(&hist[rel], cnt);
-        else atomicAdd(&hist[rel], cnt);
-    }
-    if (!RANK) return -1;
-    base = __shfl(base, leader, kWave);
-    return win ? base + wrank : -1;
 }
 
 template <int PREC>
@@ -147,25 +187,24 @@ struct SortSmem {
     }
 };
 
-// Block prologue shared by count and scatter: stage the field (and drift
-// table), find the histogram window from the already-loaded first and last
-// markers, clear the window.  Marker loads are issued before this runs, so
-// their latency overlaps the window set-up.
-template <int PREC, int VD, int MPT, bool PUSH>
-__device__ __forceinline__ void sort_prologue(const Geo& g, const SortSmem<PREC>& sm, const Pay<PREC, VD>* p,
-                                              int base, int last, const double* E, const RowShift* rows_g,
-                                              int* s_b, int* s_lo, int* s_nb)
+// Block set-up shared by both passes: stage the field (and drift table), load
+// the thread's group, find the histogram window from the block's first and
+// last markers (before the push), clear the window.
+template <int PREC, int VD, int K, bool PUSH>
+__device__ __forceinline__ void sort_setup(const Geo& g, const SortSmem<PREC>& sm, const typename MarkersOf<PREC>::T& m,
+                                           Group<PREC, VD, K>& grp, int base, int first, int last, bool with_f,
+                                           const double* E, const RowShift* rows_g, int* s_b, int* s_lo, int* s_nb)
 {
     if (PUSH) {
         stage_field<PREC>(g, E, sm.sE);
         if (PREC)
             for (int i = threadIdx.x; i <= g.nv[0]; i += blockDim.x) sm.sRow[i] = rows_g[i];
     }
+    grp.load(m, g, first, last, with_f);
 #pragma unroll
-    for (int k = 0; k < MPT; ++k) {
-        const int i = base + k * kSortThreads + threadIdx.x;
-        if (i == base) s_b[0] = p[k].bucket(g);
-        if (i == last) s_b[1] = p[k].bucket(g);
+    for (int k = 0; k < K; ++k) {
+        if (first + k == base) s_b[0] = grp.p[k].bucket(g);
+        if (first + k == last) s_b[1] = grp.p[k].bucket(g);
     }
     __syncthreads();
     if (threadIdx.x == 0) set_window(g, s_b[0], s_b[1], s_lo, s_nb);
@@ -174,6 +213,30 @@ __device__ __forceinline__ void sort_prologue(const Geo& g, const SortSmem<PREC>
     for (int i = threadIdx.x; i < nbw; i += blockDim.x) sm.hist[i] = 0;
     __syncthreads();
 }
+
+// Per-thread aggregation of a group's buckets.  Consecutive markers of the
+// previous order come from one or two runs and land in a few new buckets, so a
+// thread keeps two "open" buckets with counts and gives each marker its rank
+// inside its open bucket (tag 0 or 1); any further bucket is an "extra"
+// (tag 2) handled one marker at a time.
+template <int K>
+struct Agg {
+    int b0, b1, c0, c1;
+    int tag[K], r[K];
+    __device__ void build(const int* bkt) {
+        b0 = -1; b1 = -1; c0 = 0; c1 = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int b = bkt[k];
+            tag[k] = -1;
+            r[k] = 0;
+            if (b < 0) continue;
+            if (b0 < 0 || b == b0) { b0 = b; tag[k] = 0; r[k] = c0++; }
+            else if (b1 < 0 || b == b1) { b1 = b; tag[k] = 1; r[k] = c1++; }
+            else tag[k] = 2;
+        }
+    }
+};
 
 // ---------------------------------------------------------------------------
 // count pass
@@ -185,36 +248,39 @@ __global__ __launch_bounds__(kSortThreads) void k_count(Geo g, typename MarkersO
                                                         double dtk, float bk,
                                                         int* __restrict__ counts, int* __restrict__ flags)
 {
-    constexpr int MPT = kCountMPT;
+    constexpr int K = kCountMPT;
     extern __shared__ __align__(16) unsigned char smem[];
     SortSmem<PREC> sm(smem, g);
     __shared__ int s_b[2], s_lo, s_nb, s_flags;
     const int base = blockIdx.x * kCountTile;
     const int last = min(base + kCountTile, g.n) - 1;
-    Pay<PREC, VD> p[MPT];
-#pragma unroll
-    for (int k = 0; k < MPT; ++k) {
-        const int i = base + k * kSortThreads + threadIdx.x;
-        if (i <= last) p[k].load(m, g.n, i, false);
-    }
+    const int first = base + threadIdx.x * K;
     if (threadIdx.x == 0) s_flags = 0;
-    sort_prologue<PREC, VD, MPT, PUSH>(g, sm, p, base, last, E, rows_g, s_b, &s_lo, &s_nb);
+    Group<PREC, VD, K> grp;
+    sort_setup<PREC, VD, K, PUSH>(g, sm, m, grp, base, first, last, false, E, rows_g, s_b, &s_lo, &s_nb);
     const int lo = s_lo, nbw = s_nb;
     int fl = 0;
+    int bkt[K];
 #pragma unroll
-    for (int k = 0; k < MPT; ++k) {
-        const int i = base + k * kSortThreads + threadIdx.x;
-        int rel = -1;
-        bool win = false;
-        if (i <= last) {
-            if (PUSH) p[k].push(g, sm.sE, sm.sRow, dtk, bk, fl);
-            const int bkt = p[k].bucket(g);
-            rel = bkt - lo;
-            win = rel >= 0 && rel < nbw;
-            if (!win) atomicAdd(&counts[bkt], 1);
+    for (int k = 0; k < K; ++k) {
+        bkt[k] = -1;
+        if (first + k <= last) {
+            if (PUSH) grp.p[k].push(g, sm.sE, sm.sRow, dtk, bk, fl);
+            bkt[k] = grp.p[k].bucket(g);
         }
-        wave_hist_add<false>(sm.hist, rel, win);
     }
+    Agg<K> ag;
+    ag.build(bkt);
+    auto add = [&](int b, int c) {
+        const int rel = b - lo;
+        if (rel >= 0 && rel < nbw) atomicAdd(&sm.hist[rel], c);
+        else atomicAdd(&counts[b], c);
+    };
+    if (ag.c0) add(ag.b0, ag.c0);
+    if (ag.c1) add(ag.b1, ag.c1);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (ag.tag[k] == 2) add(bkt[k], 1);
     if (fl) atomicOr(&s_flags, fl);
     __syncthreads();
     for (int i = threadIdx.x; i < nbw; i += blockDim.x) {
@@ -226,6 +292,11 @@ __global__ __launch_bounds__(kSortThreads) void k_count(Geo g, typename MarkersO
 
 // ---------------------------------------------------------------------------
 // scatter pass: src (sorted by the previous buckets) -> dst (sorted by new)
+//
+// Here consecutive lanes take consecutive markers (lane-strided), unlike the
+// count pass: markers of one previous run sit in neighbouring lanes and get
+// consecutive ranks in their new run from the LDS atomics, so each store
+// instruction writes a few contiguous stretches instead of 64 scattered words.
 // ---------------------------------------------------------------------------
 template <int PREC, int VD, bool PUSH>
 __global__ __launch_bounds__(kSortThreads) void k_scatter(Geo g, typename MarkersOf<PREC>::T src,
@@ -236,40 +307,58 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(Geo g, typename Marker
                                                           const int* __restrict__ offsets,
                                                           int* __restrict__ counts, int* __restrict__ flags)
 {
-    constexpr int MPT = kSortMPT;
+    constexpr int K = kSortMPT;
     extern __shared__ __align__(16) unsigned char smem[];
     SortSmem<PREC> sm(smem, g);
     __shared__ int s_b[2], s_lo, s_nb, s_flags;
     const int base = blockIdx.x * kSortTile;
     const int last = min(base + kSortTile, g.n) - 1;
-    Pay<PREC, VD> p[MPT];
-#pragma unroll
-    for (int k = 0; k < MPT; ++k) {
-        const int i = base + k * kSortThreads + threadIdx.x;
-        if (i <= last) p[k].load(src, g.n, i, true);
-    }
     if (threadIdx.x == 0) s_flags = 0;
-    sort_prologue<PREC, VD, MPT, PUSH>(g, sm, p, base, last, E, rows_g, s_b, &s_lo, &s_nb);
-    const int lo = s_lo, nbw = s_nb;
-    int bkt[MPT], rank[MPT];
-    int fl = 0;
+    if (PUSH) {
+        stage_field<PREC>(g, E, sm.sE);
+        if (PREC)
+            for (int i = threadIdx.x; i <= g.nv[0]; i += blockDim.x) sm.sRow[i] = rows_g[i];
+    }
+    Pay<PREC, VD> p[K];
 #pragma unroll
-    for (int k = 0; k < MPT; ++k) {
+    for (int k = 0; k < K; ++k) p[k].load(src, g, min(base + k * kSortThreads + (int)threadIdx.x, last), true);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = base + k * kSortThreads + threadIdx.x;
+        if (i == base) s_b[0] = p[k].bucket(g);
+        if (i == last) s_b[1] = p[k].bucket(g);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) set_window(g, s_b[0], s_b[1], &s_lo, &s_nb);
+    __syncthreads();
+    const int lo = s_lo, nbw = s_nb;
+    for (int i = threadIdx.x; i < nbw; i += blockDim.x) sm.hist[i] = 0;
+    __syncthreads();
+    int fl = 0;
+    int bkt[K], rank[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
         const int i = base + k * kSortThreads + threadIdx.x;
         bkt[k] = -1;
-        int rel = -1;
-        bool win = false;
+        rank[k] = -1;
         if (i <= last) {
             if (PUSH) p[k].push(g, sm.sE, sm.sRow, dtk, bk, fl);
             bkt[k] = p[k].bucket(g);
-            rel = bkt[k] - lo;
-            win = rel >= 0 && rel < nbw;
+            const int rel = bkt[k] - lo;
+            if (rel >= 0 && rel < nbw) rank[k] = atomicAdd(&sm.hist[rel], 1);
         }
-        rank[k] = wave_hist_add<true>(sm.hist, rel, win);
+    }
+    // run bounds of every marker's bucket, loaded while slots are claimed
+    int rb[K], re[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int bq = bkt[k] < 0 ? 0 : bkt[k];
+        rb[k] = offsets[bq];
+        re[k] = offsets[bq + 1];
     }
     __syncthreads();
-    // claim each touched bucket's slots: counts[] holds the slots still free,
-    // counting down from the run length
+    // claim each touched in-window bucket's slots: counts[] holds the slots
+    // still free, counting down from the run length
     for (int i = threadIdx.x; i < nbw; i += blockDim.x) {
         const int c = sm.hist[i];
         if (c) {
@@ -280,20 +369,25 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(Geo g, typename Marker
         }
     }
     __syncthreads();
+    int slot[K];
 #pragma unroll
-    for (int k = 0; k < MPT; ++k) {
-        if (bkt[k] < 0) continue;
-        int slot;
-        if (rank[k] >= 0) {
+    for (int k = 0; k < K; ++k) {
+        slot[k] = -1;
+        if (bkt[k] >= 0 && rank[k] >= 0) {
             const int start = sm.hist[bkt[k] - lo];
-            slot = start < 0 ? -1 : start + rank[k];
-        } else {
-            slot = atomicSub(&counts[bkt[k]], 1) - 1;
+            slot[k] = start < 0 ? -1 : start + rank[k];
         }
-        const int beg = offsets[bkt[k]], end = offsets[bkt[k] + 1];
-        const int dest = beg + slot;
-        if (slot < 0 || dest >= end) { fl |= FLAG_SLOT; continue; }
-        p[k].store(dst, g.n, dest);
+    }
+    // markers outside the window (large velocity jumps) claim one slot each
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (bkt[k] >= 0 && rank[k] < 0) slot[k] = atomicSub(&counts[bkt[k]], 1) - 1;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (bkt[k] < 0) continue;
+        const int dest = rb[k] + slot[k];
+        if (slot[k] < 0 || dest >= re[k]) { fl |= FLAG_SLOT; continue; }
+        p[k].store(dst, g, dest);
     }
     if (fl) atomicOr(&s_flags, fl);
     __syncthreads();
@@ -323,9 +417,9 @@ __global__ __launch_bounds__(kSortThreads) void k_push(Geo g, typename MarkersOf
         int i = base + k * kSortThreads + threadIdx.x;
         if (i < g.n) {
             Pay<PREC, VD> p;
-            p.load(m, g.n, i, true);
+            p.load(m, g, i, true);
             p.push(g, sE, sRow, dtk, bk, fl);
-            p.store(m, g.n, i);
+            p.store(m, g, i);
         }
     }
     if (fl) atomicOr(flags, fl);
