@@ -96,6 +96,9 @@ int make_geo(const avl_config* c, Geo* g)
     }
     for (int d = c->vdim; d < 3; ++d) g->nv[d] = 1;
     if (rows * c->nx + 2 >= (int64_t)INT32_MAX || cells >= (int64_t)INT32_MAX) return AVL_ESIZE;
+    // the 1D-1V reconstruction addresses each marker array with 32-bit byte offsets
+    if (c->vdim == 1 && (c->n_markers + 64) * (c->precision == AVL_FP64 ? 8 : 4) > (int64_t)0xffffffffLL)
+        return AVL_ESIZE;
     g->nrow = (int)rows;
     g->nb = (int)(rows * c->nx);
     g->n = (int)c->n_markers;

@@ -99,29 +99,87 @@ template <> struct RT<0> {
 template <> struct RT<1> {
     using T = float;
     using M = M32;
-    static constexpr int KU = 24;
+    static constexpr int KU = 20;
 };
 
-template <int PREC> constexpr int recon_cap() { return kWave * RT<PREC>::KU; }
+// LDS capacity per wave: KU markers per lane of the main range plus one
+// wrapped run of at most a wavefront.
+template <int PREC> constexpr int recon_cap() { return kWave * (RT<PREC>::KU + 1); }
 
-// bytes of LDS per wave
-template <int PREC> constexpr size_t recon_lds()
+// bytes of LDS per wave: a, b, f as three arrays of the storage type
+template <int PREC> constexpr size_t recon_lds() { return 3 * sizeof(typename RT<PREC>::T) * recon_cap<PREC>(); }
+
+// Raw buffer descriptors (gfx9 family, 32-bit raw data) for the marker
+// arrays the reconstruction reads; out-of-range buffer reads return zero, so
+// the prefetch needs no bounds branches.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* p, size_t bytes)
 {
-    return PREC ? sizeof(float4) * recon_cap<PREC>() : (sizeof(double2) + sizeof(double)) * recon_cap<PREC>();
+    // num_records is a 32-bit byte count: arrays up to 4 GiB (the host limits
+    // 1D-1V marker counts accordingly)
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0,
+                                             (int)(unsigned)min(bytes, (size_t)0xffffffffu), 0x00020000);
 }
 
-// Raw marker fields held in registers between the load and the LDS store.
-template <int PREC> struct Raw;
-template <> struct Raw<0> {
-    double x, v, f;
-    __device__ void load(const M64& m, int q) { x = m.x[q]; v = m.v[q]; f = m.f[q]; }
+// Descriptors cover exactly one range of markers [first, first+count): lanes
+// past the end read zero and cost no memory traffic.
+template <int PREC> struct Src;
+template <> struct Src<0> {           // x, v (first component), f
+    __amdgpu_buffer_rsrc_t rx, rv, rf;
+    __device__ void init(const M64& m, int first, int count) {
+        const size_t b = sizeof(double) * (size_t)count;
+        rx = rsrc(m.x + first, b);
+        rv = rsrc(m.v + first, b);
+        rf = rsrc(m.f + first, b);
+    }
+    struct Raw { double x, v, f; };
+    __device__ Raw load(int byte_off, int soff) const {
+        Raw r;
+        r.x = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rx, byte_off, soff, 0));
+        r.v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rv, byte_off, soff, 0));
+        r.f = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rf, byte_off, soff, 0));
+        return r;
+    }
 };
-template <> struct Raw<1> {
-    float a, b, f;
-    __device__ void load(const M32& m, int q) { a = m.a[q]; b = m.b[q]; f = m.f[q]; }
+template <> struct Src<1> {           // a, b (first component), f
+    __amdgpu_buffer_rsrc_t ra, rb, rf;
+    __device__ void init(const M32& m, int first, int count) {
+        const size_t b = sizeof(float) * (size_t)count;
+        ra = rsrc(m.a + first, b);
+        rb = rsrc(m.b + first, b);
+        rf = rsrc(m.f + first, b);
+    }
+    struct Raw { float a, b, f; };
+    __device__ Raw load(int byte_off, int soff) const {
+        Raw r;
+        r.a = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ra, byte_off, soff, 0));
+        r.b = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, byte_off, soff, 0));
+        r.f = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rf, byte_off, soff, 0));
+        return r;
+    }
 };
 
+// Staged row segment in LDS.  FP32 form: a, b, f as three float arrays
+// (12 bytes a marker, so more waves fit per CU).  FP64: (a, b) pairs and f,
+// read with one 16-byte and one 8-byte access.
 template <int PREC> struct Lds;
+template <> struct Lds<1> {
+    float *a, *b, *f;
+    __device__ void init(unsigned char* base) {
+        a = reinterpret_cast<float*>(base);
+        b = a + recon_cap<1>();
+        f = b + recon_cap<1>();
+    }
+    __device__ void put(const Geo&, int p, const Src<1>::Raw& r) {
+        a[p] = r.a;
+        b[p] = r.b;
+        f[p] = r.f;
+    }
+    __device__ void get(int p, float& aa, float& bb, float& ff) const {
+        aa = a[p];
+        bb = b[p];
+        ff = f[p];
+    }
+};
 template <> struct Lds<0> {
     double2* ab;
     double* f;
@@ -129,30 +187,19 @@ template <> struct Lds<0> {
         ab = reinterpret_cast<double2*>(base);
         f = reinterpret_cast<double*>(base + sizeof(double2) * recon_cap<0>());
     }
-    __device__ void put(const Geo& g, int p, const Raw<0>& r) {
+    __device__ void put(const Geo& g, int p, const Src<0>::Raw& r) {
         int ix, jp[1];
-        double a, b[1];
+        double aa, bb[1];
         double vv[1] = {r.v};
-        locate64<1>(g, r.x, vv, ix, jp, a, b);
-        ab[p] = make_double2(a, b[0]);
+        locate64<1>(g, r.x, vv, ix, jp, aa, bb);
+        ab[p] = make_double2(aa, bb[0]);
         f[p] = r.f;
     }
-    __device__ void get(int p, double& a, double& b, double& ff) const {
-        double2 t = ab[p];
-        a = t.x;
-        b = t.y;
+    __device__ void get(int p, double& aa, double& bb, double& ff) const {
+        const double2 t = ab[p];
+        aa = t.x;
+        bb = t.y;
         ff = f[p];
-    }
-};
-template <> struct Lds<1> {
-    float4* abf;
-    __device__ void init(unsigned char* base) { abf = reinterpret_cast<float4*>(base); }
-    __device__ void put(const Geo&, int p, const Raw<1>& r) { abf[p] = make_float4(r.a, r.b, r.f, 0.0f); }
-    __device__ void get(int p, float& a, float& b, float& ff) const {
-        float4 t = abf[p];
-        a = t.x;
-        b = t.y;
-        ff = t.z;
     }
 };
 
@@ -161,27 +208,25 @@ __device__ __forceinline__ void load_global(const Geo& g, const typename RT<PREC
                                             typename RT<PREC>::T& a, typename RT<PREC>::T& b,
                                             typename RT<PREC>::T& f)
 {
-    Raw<PREC> r;
-    r.load(m, q);
     if constexpr (PREC == 0) {
         int ix, jp[1];
         double bb[1];
-        double vv[1] = {r.v};
-        locate64<1>(g, r.x, vv, ix, jp, a, bb);
+        double vv[1] = {m.v[q]};
+        locate64<1>(g, m.x[q], vv, ix, jp, a, bb);
         b = bb[0];
-        f = r.f;
+        f = m.f[q];
     } else {
-        a = r.a;
-        b = r.b;
-        f = r.f;
+        a = m.a[q];
+        b = m.b[q];
+        f = m.f[q];
     }
 }
 
 // Marker range of one dual-row segment: the contiguous runs of lanes
 // first..last plus (first strip only) the wrapped run of lane 0.
 struct Seg {
-    int lo, nmain, wbeg, total;
-    __device__ int index(int p) const { return p < nmain ? lo + p : wbeg + (p - nmain); }
+    int lo, nmain, wbeg, wlen;
+    __device__ bool fits(int cap_main) const { return nmain <= cap_main && wlen <= kWave; }
 };
 
 __device__ __forceinline__ Seg make_seg(int beg, int end, int first_lane, int last_lane, bool wrapped)
@@ -192,19 +237,29 @@ __device__ __forceinline__ Seg make_seg(int beg, int end, int first_lane, int la
     s.wbeg = __shfl(beg, 0, kWave);
     const int wend = __shfl(end, 0, kWave);
     s.nmain = hi - s.lo;
-    s.total = s.nmain + (wrapped ? wend - s.wbeg : 0);
+    s.wlen = wrapped ? wend - s.wbeg : 0;
     return s;
 }
 
+// Issue the loads of one row segment into registers: KU markers per lane of
+// the main range and the lane's marker of the wrapped run.  The loads carry
+// no branches: each goes through a descriptor bounded to its range.
 template <int PREC>
-__device__ __forceinline__ void prefetch(const typename RT<PREC>::M& m, const Seg& s, int lane, Raw<PREC>* r)
+__device__ __forceinline__ void prefetch(const typename RT<PREC>::M& m, const Seg& s, int lane,
+                                         typename Src<PREC>::Raw* r, typename Src<PREC>::Raw& w)
 {
     constexpr int KU = RT<PREC>::KU;
-    if (s.total > recon_cap<PREC>()) return;   // summed from global memory instead
+    constexpr int esz = sizeof(typename RT<PREC>::T);
+    if (!s.fits(kWave * KU)) return;   // summed from global memory instead
+    Src<PREC> src;
+    src.init(m, __builtin_amdgcn_readfirstlane(s.lo), __builtin_amdgcn_readfirstlane(s.nmain));
+    const int off = lane * esz;
 #pragma unroll
-    for (int k = 0; k < KU; ++k) {
-        const int p = lane + k * kWave;
-        if (p < s.total) r[k].load(m, s.index(p));
+    for (int k = 0; k < KU; ++k) r[k] = src.load(off, k * kWave * esz);
+    if (s.wlen) {
+        Src<PREC> ws;
+        ws.init(m, __builtin_amdgcn_readfirstlane(s.wbeg), __builtin_amdgcn_readfirstlane(s.wlen));
+        w = ws.load(off, 0);
     }
 }
 
@@ -217,7 +272,7 @@ __global__ __launch_bounds__(kWave) void k_recon_1v(Geo g, typename RT<PREC>::M 
     using T = typename RT<PREC>::T;
     using A = typename std::conditional<KAHAN, Kahan<float>, Plain>::type;
     constexpr int KU = RT<PREC>::KU;
-    constexpr int CAP = recon_cap<PREC>();
+    constexpr int MAIN = kWave * KU;
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x;
     // XCD-aware dealing: blocks go round-robin over the 8 XCDs; give each XCD
@@ -251,31 +306,32 @@ __global__ __launch_bounds__(kWave) void k_recon_1v(Geo g, typename RT<PREC>::M 
         }
     };
 
-    Raw<PREC> regs[KU];
+    typename Src<PREC>::Raw regs[KU], wreg;
     int beg, end, nbeg, nend;
     row_offsets(j_begin - 1, beg, end);
     Seg seg = make_seg(beg, end, first_lane, last_lane, wrapped);
-    prefetch<PREC>(m, seg, lane, regs);
+    prefetch<PREC>(m, seg, lane, regs, wreg);
     row_offsets(j_begin, nbeg, nend);
 
     double upN = 0.0, upD = 0.0;
     double rp = 0.0;
 
     for (int jd = j_begin - 1; jd < j_end; ++jd) {
-        const bool staged = seg.total <= CAP;
+        const bool staged = seg.fits(MAIN);
         if (staged) {
 #pragma unroll
             for (int k = 0; k < KU; ++k) {
                 const int p = lane + k * kWave;
-                if (p < seg.total) lds.put(g, p, regs[k]);
+                if (p < seg.nmain) lds.put(g, p, regs[k]);
             }
+            if (lane < seg.wlen) lds.put(g, seg.nmain + lane, wreg);
         }
         wave_sync_lds();
         const int p0 = staged ? ((wrapped && lane == 0) ? seg.nmain : beg - seg.lo) : beg;
         const int len = end - beg;
         // start the next row's loads before summing this one
         Seg nseg = make_seg(nbeg, nend, first_lane, last_lane, wrapped);
-        if (jd + 1 < j_end) prefetch<PREC>(m, nseg, lane, regs);
+        if (jd + 1 < j_end) prefetch<PREC>(m, nseg, lane, regs, wreg);
         int nnbeg, nnend;
         row_offsets(jd + 2, nnbeg, nnend);
 
@@ -288,13 +344,15 @@ __global__ __launch_bounds__(kWave) void k_recon_1v(Geo g, typename RT<PREC>::M 
             for (int k = 0; k < len; ++k) {
                 T a, b, f;
                 lds.get(p0 + k, a, b, f);
-                M.add(a, b, f);
+                if constexpr (KAHAN) M.add(a, b, f);
+                else M.add((double)a, (double)b, (double)f);
             }
         } else {
             for (int k = 0; k < len; ++k) {
                 T a, b, f;
                 load_global<PREC>(g, m, p0 + k, a, b, f);
-                M.add(a, b, f);
+                if constexpr (KAHAN) M.add(a, b, f);
+                else M.add((double)a, (double)b, (double)f);
             }
         }
         wave_sync_lds();
