@@ -191,7 +191,8 @@ int avl_set_stream(avl_handle* h, void* stream);
  * avl_kernel_time synchronises and returns the summed milliseconds and the
  * number of launches since timing was enabled. */
 enum { AVL_K_PUSH_COUNT = 0, AVL_K_SCAN = 1, AVL_K_SCATTER = 2, AVL_K_RECONSTRUCT = 3,
-       AVL_K_MOMENTS = 4, AVL_K_FIELD = 5, AVL_K_STEP = 6, AVL_K_COUNT = 7 };
+       AVL_K_FIELD = 4 /* rho from the reconstruction's partials + field solve */, AVL_K_STEP = 5,
+       AVL_K_COUNT = 6 };
 int avl_timing(avl_handle* h, int enable);
 int avl_kernel_time(avl_handle* h, int kernel, double* ms_total, int64_t* launches);
 

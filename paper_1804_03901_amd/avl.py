@@ -21,8 +21,8 @@ LIB_PATH = os.path.join(_HERE, "_build", "libavl.so")
 AVL_FP64 = 0
 AVL_FP32 = 1
 AVL_OPT_KAHAN32 = 1
-K_PUSH_COUNT, K_SCAN, K_SCATTER, K_RECONSTRUCT, K_MOMENTS, K_FIELD, K_STEP = range(7)
-KERNEL_NAMES = ["push_count", "scan", "scatter", "reconstruct", "moments", "field", "step"]
+K_PUSH_COUNT, K_SCAN, K_SCATTER, K_RECONSTRUCT, K_FIELD, K_STEP = range(6)
+KERNEL_NAMES = ["push_count", "scan", "scatter", "reconstruct", "field", "step"]
 
 STATUS = {0: "AVL_OK", -1: "AVL_EINVAL", -2: "AVL_ESIZE", -3: "AVL_EALIGN", -4: "AVL_ESTATE",
           -5: "AVL_EDEVICE", -6: "AVL_ENOTSUP", -7: "AVL_ENONFINITE", -8: "AVL_EINTERNAL"}

@@ -15,19 +15,18 @@
 
 namespace avl {
 hipError_t launch_sort(const Geo& g, void* src, void* dst, const double* E, const RowShift* rows, double dtk,
-                       float bk, int* counts, int* offsets, int* tile_sums, int* flags, bool push, hipStream_t st,
-                       int phase);
+                       float bk, int* counts, int* offsets, int* tile_sums, int* tile_next, int* flags, bool push,
+                       hipStream_t st, int phase);
 hipError_t launch_push(const Geo& g, void* m, const double* E, const RowShift* rows, double dtk, float bk,
                        int* flags, hipStream_t st);
 hipError_t launch_recon(const Geo& g, void* m, const int* offsets, void* fgrid, void* Dgrid, double* rho_part,
                         hipStream_t st);
-hipError_t launch_moments(const Geo& g, const double* rho_part, double* rho, hipStream_t st);
 int recon_capacity(int prec);
 hipError_t launch_recon3(const Geo& g, void* m, const int* offsets, void* fgrid, void* Dgrid, double* rho_part,
                          void* scratch, hipStream_t st);
-hipError_t launch_field(const Geo& g, const double* rho_src, double* rho_copy, double* E_out, const double2* tw,
-                        const double* green, double* diag_ring, long long* step_ctr, int write_diag, double* W_out,
-                        int* flags, hipStream_t st);
+hipError_t launch_field(const Geo& g, const double* rho_part, const double* rho_in, double* rho, double* E_out,
+                        const double2* tw, const double* green, double* diag_ring, long long* step_ctr,
+                        int write_diag, double* W_out, int* flags, int* done, hipStream_t st);
 hipError_t launch_validate(const Geo& g, const double* x, const double* v, const double* f, int* bad,
                            hipStream_t st);
 hipError_t launch_to32(const Geo& g, const double* x, const double* v, const double* f, M32 m, int* flags,
@@ -48,7 +47,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
     size_t markers[2], counts, offsets, tile_sums, fgrid, rho_part, rho, E, tw, green, rows, diag, ctr, flags, bad,
-        scratch3, total;
+        done, scratch3, total;
 };
 
 int ilog2(int v)
@@ -166,7 +165,7 @@ void make_layout(const avl_config* c, const Geo& g, Layout* L)
     L->markers[1] = take(mbytes + 64 * (3 + g.vdim));
     L->counts = take(sizeof(int) * nbt);
     L->offsets = take(sizeof(int) * (nbt + 1));
-    L->tile_sums = take(sizeof(int) * (ntiles + 1));
+    L->tile_sums = take(sizeof(int) * 2 * (ntiles + 64));   // two parities of per-tile totals
     L->fgrid = take(esz * cells);
     L->rho_part = take(sizeof(double) * (size_t)std::max(1, g.nchunk) * g.nx);
     L->rho = take(sizeof(double) * g.nx);
@@ -178,6 +177,7 @@ void make_layout(const avl_config* c, const Geo& g, Layout* L)
     L->ctr = take(sizeof(long long));
     L->flags = take(sizeof(int));
     L->bad = take(sizeof(int));
+    L->done = take(sizeof(int));
     L->scratch3 = take(g.vdim == 3 ? recon3_scratch_bytes(g) : 0);
     L->total = off;
 }
@@ -205,7 +205,7 @@ struct avl_handle {
     M64 m64[2];
     M32 m32[2];
     int cur;
-    int *counts, *offsets, *tile_sums, *flags, *bad;
+    int *counts, *offsets, *tile_sums, *flags, *bad, *done;
     void* fgrid;
     double *rho_part, *rho, *E, *green, *diag;
     double2* tw;
@@ -213,6 +213,7 @@ struct avl_handle {
     long long* ctr;
     void* scratch3;
     bool sorted, have_f, have_rho, have_E;
+    bool partials;      // rho partials of the current markers are in the workspace
     bool kicked;        // a push has happened since loading (first-kick rule)
     int64_t steps;      // steps enqueued since loading (mirrors the device counter)
     hipGraphExec_t gexec[2];
@@ -345,32 +346,36 @@ int do_sort(avl_handle* h, bool push, double kick)
     void* dst = marker_view(h, 1 - h->cur);
     const double dtk = g.dt * kick;
     const float bk = g.bscale * (float)kick;
+    // per-scan-tile totals alternate between two halves with the buffer parity
+    const size_t tstride = ((size_t)g.nb + 1 + kScanTile - 1) / kScanTile + 64;
+    int* tcur = h->tile_sums + (size_t)h->cur * tstride;
+    int* tnext = h->tile_sums + (size_t)(1 - h->cur) * tstride;
     {
         Timer t(h, AVL_K_PUSH_COUNT);
-        AVL_TRY(launch_sort(g, src, dst, h->E, h->rows, dtk, bk, h->counts, h->offsets, h->tile_sums, h->flags,
+        AVL_TRY(launch_sort(g, src, dst, h->E, h->rows, dtk, bk, h->counts, h->offsets, tcur, tnext, h->flags,
                             push, h->st, 0));
     }
     {
         Timer t(h, AVL_K_SCAN);
-        AVL_TRY(launch_sort(g, src, dst, h->E, h->rows, dtk, bk, h->counts, h->offsets, h->tile_sums, h->flags,
+        AVL_TRY(launch_sort(g, src, dst, h->E, h->rows, dtk, bk, h->counts, h->offsets, tcur, tnext, h->flags,
                             push, h->st, 1));
     }
     {
         Timer t(h, AVL_K_SCATTER);
-        AVL_TRY(launch_sort(g, src, dst, h->E, h->rows, dtk, bk, h->counts, h->offsets, h->tile_sums, h->flags,
+        AVL_TRY(launch_sort(g, src, dst, h->E, h->rows, dtk, bk, h->counts, h->offsets, tcur, tnext, h->flags,
                             push, h->st, 2));
     }
     h->cur = 1 - h->cur;
     h->sorted = true;
     if (push) {
         h->kicked = true;
-        h->have_f = h->have_rho = h->have_E = false;
+        h->have_f = h->have_rho = h->have_E = h->partials = false;
     }
     return AVL_OK;
 }
 
-// Reconstruction of f and the rho moment (the reconstruction kernel writes
-// per-chunk column partials; a second kernel adds them in chunk order).
+// Reconstruction of f (the kernel also writes per-chunk column partials of
+// the rho moment, which the field kernel adds in chunk order).
 int do_recon(avl_handle* h, void* Dgrid)
 {
     {
@@ -381,21 +386,21 @@ int do_recon(avl_handle* h, void* Dgrid)
             AVL_TRY(launch_recon3(h->g, marker_view(h, h->cur), h->offsets, h->fgrid, Dgrid, h->rho_part,
                                   h->scratch3, h->st));
     }
-    {
-        Timer t(h, AVL_K_MOMENTS);
-        AVL_TRY(launch_moments(h->g, h->rho_part, h->rho, h->st));
-    }
+    // rho stays valid when the markers have not moved since it was formed
+    if (!h->have_f) h->have_rho = false;
     h->have_f = true;
-    h->have_rho = true;
+    h->partials = true;
     return AVL_OK;
 }
 
-int do_field(avl_handle* h, const double* rho_src, bool diag, double* W_out)
+// rho from the partials (or the caller's rho) and the field solve, one launch.
+int do_field(avl_handle* h, const double* rho_in, bool diag, double* W_out)
 {
     Timer t(h, AVL_K_FIELD);
-    AVL_TRY(launch_field(h->g, rho_src, nullptr, h->E, h->tw, h->green, h->diag,
-                         h->ctr, diag ? 1 : 0, W_out, h->flags, h->st));
-    h->have_rho = true;
+    if (!rho_in && !h->partials) return AVL_ESTATE;
+    AVL_TRY(launch_field(h->g, h->rho_part, rho_in, h->rho, h->E, h->tw, h->green, h->diag, h->ctr, diag ? 1 : 0,
+                         W_out, h->flags, h->done, h->st));
+    if (!rho_in) h->have_rho = true;
     h->have_E = true;
     return AVL_OK;
 }
@@ -406,7 +411,7 @@ int one_step(avl_handle* h)
     int rc = do_sort(h, true, kick_fraction(h));
     if (rc) return rc;
     if ((rc = do_recon(h, nullptr))) return rc;
-    if ((rc = do_field(h, h->rho, true, nullptr))) return rc;
+    if ((rc = do_field(h, nullptr, true, nullptr))) return rc;
     h->steps += 1;
     return AVL_OK;
 }
@@ -440,6 +445,10 @@ int load_markers(avl_handle* h, const double* x, const double* v, const double* 
     const int total = g.n;
     const size_t nbt = (size_t)g.nb + 1;
     AVL_TRY(hipMemsetAsync(h->counts, 0, sizeof(int) * nbt, h->st));
+    {
+        const size_t ntiles = (nbt + kScanTile - 1) / kScanTile;
+        AVL_TRY(hipMemsetAsync(h->tile_sums, 0, sizeof(int) * 2 * (ntiles + 64), h->st));
+    }
     AVL_TRY(hipMemcpyAsync(h->offsets + nbt, &total, sizeof(int), hipMemcpyHostToDevice, h->st));
     if (fresh) AVL_TRY(hipMemsetAsync(h->ctr, 0, sizeof(long long), h->st));
     AVL_TRY(hipStreamSynchronize(h->st));
@@ -448,11 +457,11 @@ int load_markers(avl_handle* h, const double* x, const double* v, const double* 
         h->kicked = false;
     }
     h->sorted = false;
-    h->have_f = h->have_rho = h->have_E = false;
+    h->have_f = h->have_rho = h->have_E = h->partials = false;
     int rc;
     if ((rc = do_sort(h, false, 1.0))) return rc;
     if ((rc = do_recon(h, nullptr))) return rc;
-    if ((rc = do_field(h, h->rho, false, nullptr))) return rc;
+    if ((rc = do_field(h, nullptr, false, nullptr))) return rc;
     return AVL_OK;
 }
 
@@ -527,6 +536,7 @@ int avl_init(const avl_config* cfg, void* workspace, size_t ws_bytes, void* stre
     h->ctr = (long long*)(h->ws + lay.ctr);
     h->flags = (int*)(h->ws + lay.flags);
     h->bad = (int*)(h->ws + lay.bad);
+    h->done = (int*)(h->ws + lay.done);
     h->scratch3 = h->ws + lay.scratch3;
     h->gexec[0] = h->gexec[1] = nullptr;
     h->cap_st = nullptr;
@@ -542,7 +552,8 @@ int avl_init(const avl_config* cfg, void* workspace, size_t ws_bytes, void* stre
             std::fprintf(stderr, "[avl] lds limit %d B, recon cap %d, hist bins %d, rc %d, chunks %d, strips %d\n", lds,
                          h->g.cap, h->g.hist_bins, h->g.rc, h->g.nchunk, h->g.nstrip);
     }
-    if (hipMemsetAsync(h->flags, 0, sizeof(int), h->st) != hipSuccess || (rc = upload_tables(h)) != AVL_OK) {
+    if (hipMemsetAsync(h->flags, 0, sizeof(int), h->st) != hipSuccess ||
+        hipMemsetAsync(h->done, 0, sizeof(int), h->st) != hipSuccess || (rc = upload_tables(h)) != AVL_OK) {
         delete h;
         return rc ? rc : AVL_EDEVICE;
     }
@@ -567,7 +578,7 @@ int avl_push(avl_handle* h, const double* E)
     }
     h->kicked = true;
     h->sorted = false;
-    h->have_f = h->have_rho = h->have_E = false;
+    h->have_f = h->have_rho = h->have_E = h->partials = false;
     return AVL_OK;
 }
 
@@ -594,7 +605,12 @@ int avl_reconstruct(avl_handle* h, void* f_out, void* D_out)
 int avl_moments(avl_handle* h, double* rho_out)
 {
     if (!h) return AVL_EINVAL;
-    if (!h->have_f || !h->have_rho) return AVL_ESTATE;
+    if (!h->have_f) return AVL_ESTATE;
+    if (!h->have_rho) {
+        // forming rho also solves the field from it (one fused launch)
+        int rc = do_field(h, nullptr, false, nullptr);
+        if (rc) return rc;
+    }
     if (rho_out) AVL_TRY(hipMemcpyAsync(rho_out, h->rho, sizeof(double) * h->g.nx, hipMemcpyDeviceToDevice, h->st));
     return AVL_OK;
 }
@@ -602,8 +618,8 @@ int avl_moments(avl_handle* h, double* rho_out)
 int avl_poisson(avl_handle* h, const double* rho, double* E_out, double* W_out)
 {
     if (!h) return AVL_EINVAL;
-    if (!rho && !h->have_rho) return AVL_ESTATE;
-    int rc = do_field(h, rho ? rho : h->rho, false, W_out);
+    if (!rho && !h->have_f && !h->have_rho) return AVL_ESTATE;
+    int rc = do_field(h, rho ? rho : (h->have_rho ? h->rho : nullptr), false, W_out);
     if (rc) return rc;
     if (E_out) AVL_TRY(hipMemcpyAsync(E_out, h->E, sizeof(double) * h->g.nx, hipMemcpyDeviceToDevice, h->st));
     return AVL_OK;
@@ -683,7 +699,7 @@ int avl_step_graph(avl_handle* h, int32_t nsteps, double* diag_out)
         }
     }
     h->sorted = true;
-    h->have_f = h->have_rho = h->have_E = true;
+    h->have_f = h->have_rho = h->have_E = h->partials = true;
     h->kicked = true;
     if (diag_out) {
         int32_t tail = nsteps % kDiagCap;
@@ -797,8 +813,7 @@ double avl_kernel_bytes(const avl_handle* h, int kernel)
         const double rd = g.prec == AVL_FP64 ? mk : 4.0 * (2 + g.vdim);
         return n * rd + 4.0 * (g.nb + 1.0) + cells * esz;
     }
-    case AVL_K_MOMENTS: return 8.0 * g.nx * (g.nchunk + 1.0);       // chunk partials in, rho out
-    case AVL_K_FIELD: return 8.0 * g.nx * 2.0;
+    case AVL_K_FIELD: return 8.0 * g.nx * (g.nchunk + 2.0);          // chunk partials in, rho and E out
     case AVL_K_STEP: return n * (pos + 3.0 * mk) + cells * esz;
     default: return 0.0;
     }

@@ -31,7 +31,7 @@ constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
 constexpr int kReconCols = kWave - 1;                     // target columns per reconstruct wave
 constexpr int kDiagCap = 4096;                            // per-step diagnostics ring
-constexpr int kFieldThreads = 512;
+constexpr int kFieldThreads = 256;
 constexpr int kMaxNx = 4096;
 
 struct Geo {

@@ -44,13 +44,20 @@ __device__ void block_sum3(double& a, double& b, double& c, double* s)
     c = s[2 * NT];
 }
 
-__global__ __launch_bounds__(kFieldThreads) void k_field(Geo g, const double* __restrict__ rho_src,
-                                                         double* __restrict__ rho_copy, double* __restrict__ E_out,
+// One launch for the charge density and the field.  Every block assembles rho
+// for 64 x cells from the reconstruction's chunk partials (four groups of
+// chunks per column, combined in a fixed order), then the last block to
+// finish -- found with a device-scope fence and a counter it resets -- runs
+// the FFT solve.  With rho given by the caller a single block does the solve.
+__global__ __launch_bounds__(kFieldThreads) void k_field(Geo g, const double* __restrict__ rho_part,
+                                                         const double* __restrict__ rho_in,
+                                                         double* __restrict__ rho, double* __restrict__ E_out,
                                                          const double2* __restrict__ tw,
                                                          const double* __restrict__ green,
                                                          double* __restrict__ diag_ring,
                                                          long long* __restrict__ step_ctr, int write_diag,
-                                                         double* __restrict__ W_out, int* __restrict__ flags)
+                                                         double* __restrict__ W_out, int* __restrict__ flags,
+                                                         int* __restrict__ done)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int nx = g.nx, lg = g.lognx;
@@ -59,11 +66,43 @@ __global__ __launch_bounds__(kFieldThreads) void k_field(Geo g, const double* __
     double2* stw = z + nx;
     double* sgr = reinterpret_cast<double*>(stw + half_n);
     __shared__ double red[3 * kFieldThreads];
+    __shared__ int s_last;
+    const double* src = rho_in;
+
+    if (!rho_in) {
+        // rho_i = q prod(dv) sum_c part[c][i]
+        double* colsum = red;   // [4][64]
+        const int c = threadIdx.x & 63, grp = threadIdx.x >> 6;
+        const int i = blockIdx.x * 64 + c;
+        double acc = 0.0;
+        if (i < nx) {
+            // batches of 16 independent loads (chunks grp, grp+4, ...), summed in order
+            for (int ch0 = grp; ch0 < g.nchunk; ch0 += 64) {
+                double v[16];
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    const int ch = ch0 + 4 * k;
+                    v[k] = ch < g.nchunk ? rho_part[(size_t)ch * nx + i] : 0.0;
+                }
+#pragma unroll
+                for (int k = 0; k < 16; ++k) acc += v[k];
+            }
+        }
+        colsum[grp * 64 + c] = acc;
+        __syncthreads();
+        if (grp == 0 && i < nx)
+            rho[i] = (((colsum[c] + colsum[64 + c]) + colsum[128 + c]) + colsum[192 + c]) * g.q_vol;
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) s_last = atomicAdd(done, 1) == (int)gridDim.x - 1;
+        __syncthreads();
+        if (!s_last) return;
+        __threadfence();
+        src = rho;
+    }
 
     for (int i = threadIdx.x; i < nx; i += blockDim.x) {
-        const double r = rho_src[i];
-        if (rho_copy) rho_copy[i] = r;
-        z[bitrev(i, lg)] = make_double2(r, 0.0);
+        z[bitrev(i, lg)] = make_double2(src[i], 0.0);
         sgr[i] = green[i];
         if (i < half_n) stw[i] = tw[i];
     }
@@ -114,6 +153,7 @@ __global__ __launch_bounds__(kFieldThreads) void k_field(Geo g, const double* __
         sim += E * w.y;
     }
     if (bad) atomicOr(flags, FLAG_NONFINITE);
+    __syncthreads();
     block_sum3<kFieldThreads>(sw, sre, sim, red);
     if (threadIdx.x == 0) {
         const double W = sw * g.dx / (2.0 * g.cp);
@@ -125,19 +165,21 @@ __global__ __launch_bounds__(kFieldThreads) void k_field(Geo g, const double* __
             diag_ring[2 * (c % kDiagCap) + 1] = m1;
             *step_ctr = c + 1;
         }
+        if (!rho_in) *done = 0;
     }
 }
 
-hipError_t launch_field(const Geo& g, const double* rho_src, double* rho_copy, double* E_out, const double2* tw,
-                        const double* green, double* diag_ring, long long* step_ctr, int write_diag, double* W_out,
-                        int* flags, hipStream_t st)
+hipError_t launch_field(const Geo& g, const double* rho_part, const double* rho_in, double* rho, double* E_out,
+                        const double2* tw, const double* green, double* diag_ring, long long* step_ctr,
+                        int write_diag, double* W_out, int* flags, int* done, hipStream_t st)
 {
     const size_t smem = (sizeof(double2) + sizeof(double2) / 2 + sizeof(double)) * g.nx;
     static int granted = 0;
     hipError_t e = ensure_lds((const void*)k_field, smem, granted);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_field, dim3(1), dim3(kFieldThreads), smem, st, g, rho_src, rho_copy, E_out, tw, green,
-                       diag_ring, step_ctr, write_diag, W_out, flags);
+    const int blocks = rho_in ? 1 : (g.nx + 63) / 64;
+    hipLaunchKernelGGL(k_field, dim3(blocks), dim3(kFieldThreads), smem, st, g, rho_part, rho_in, rho, E_out, tw,
+                       green, diag_ring, step_ctr, write_diag, W_out, flags, done);
     return hipGetLastError();
 }
 

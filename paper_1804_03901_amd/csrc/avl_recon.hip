@@ -386,34 +386,6 @@ __global__ __launch_bounds__(kWave) void k_recon_1v(Geo g, typename RT<PREC>::M 
     if (tgt_ok) rho_part[(size_t)chunk * nx + col] = rp;
 }
 
-// rho_i = q prod(dv) sum_c part[c][i]: 64 columns per block, 4 groups of
-// chunks per column summed with independent loads, then combined in a fixed
-// order (deterministic).
-__global__ __launch_bounds__(256) void k_rho(Geo g, const double* __restrict__ part, double* __restrict__ rho)
-{
-    __shared__ double red[4][64];
-    const int c = threadIdx.x & 63, grp = threadIdx.x >> 6;
-    const int i = blockIdx.x * 64 + c;
-    double s = 0.0;
-    if (i < g.nx) {
-        int ch = grp;
-        for (; ch + 12 < g.nchunk; ch += 16) {
-            const double a0 = part[(size_t)ch * g.nx + i];
-            const double a1 = part[(size_t)(ch + 4) * g.nx + i];
-            const double a2 = part[(size_t)(ch + 8) * g.nx + i];
-            const double a3 = part[(size_t)(ch + 12) * g.nx + i];
-            s += a0;
-            s += a1;
-            s += a2;
-            s += a3;
-        }
-        for (; ch < g.nchunk; ch += 4) s += part[(size_t)ch * g.nx + i];
-    }
-    red[grp][c] = s;
-    __syncthreads();
-    if (grp == 0 && i < g.nx) rho[i] = (((red[0][c] + red[1][c]) + red[2][c]) + red[3][c]) * g.q_vol;
-}
-
 hipError_t launch_recon(const Geo& g, void* m, const int* offsets, void* fgrid, void* Dgrid,
                         double* rho_part, hipStream_t st)
 {
@@ -437,12 +409,6 @@ hipError_t launch_recon(const Geo& g, void* m, const int* offsets, void* fgrid, 
     else
         hipLaunchKernelGGL((k_recon_1v<1, true>), dim3(blocks), dim3(kWave), smem, st, g, *reinterpret_cast<M32*>(m),
                            offsets, (float*)fgrid, (float*)Dgrid, rho_part, per_xcd);
-    return hipGetLastError();
-}
-
-hipError_t launch_moments(const Geo& g, const double* rho_part, double* rho, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_rho, dim3((g.nx + 63) / 64), dim3(256), 0, st, g, rho_part, rho);
     return hipGetLastError();
 }
 

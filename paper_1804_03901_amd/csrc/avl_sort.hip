@@ -246,12 +246,13 @@ __global__ __launch_bounds__(kSortThreads) void k_count(Geo g, typename MarkersO
                                                         const double* __restrict__ E,
                                                         const RowShift* __restrict__ rows_g,
                                                         double dtk, float bk,
-                                                        int* __restrict__ counts, int* __restrict__ flags)
+                                                        int* __restrict__ counts, int* __restrict__ tsum,
+                                                        int* __restrict__ flags)
 {
     constexpr int K = kCountMPT;
     extern __shared__ __align__(16) unsigned char smem[];
     SortSmem<PREC> sm(smem, g);
-    __shared__ int s_b[2], s_lo, s_nb, s_flags;
+    __shared__ int s_b[2], s_lo, s_nb, s_flags, s_tile[8];
     const int base = blockIdx.x * kCountTile;
     const int last = min(base + kCountTile, g.n) - 1;
     const int first = base + threadIdx.x * K;
@@ -273,8 +274,12 @@ __global__ __launch_bounds__(kSortThreads) void k_count(Geo g, typename MarkersO
     ag.build(bkt);
     auto add = [&](int b, int c) {
         const int rel = b - lo;
-        if (rel >= 0 && rel < nbw) atomicAdd(&sm.hist[rel], c);
-        else atomicAdd(&counts[b], c);
+        if (rel >= 0 && rel < nbw) {
+            atomicAdd(&sm.hist[rel], c);
+        } else {
+            atomicAdd(&counts[b], c);
+            atomicAdd(&tsum[b / kScanTile], c);
+        }
     };
     if (ag.c0) add(ag.b0, ag.c0);
     if (ag.c1) add(ag.b1, ag.c1);
@@ -282,11 +287,21 @@ __global__ __launch_bounds__(kSortThreads) void k_count(Geo g, typename MarkersO
     for (int k = 0; k < K; ++k)
         if (ag.tag[k] == 2) add(bkt[k], 1);
     if (fl) atomicOr(&s_flags, fl);
+    if (threadIdx.x < 8) s_tile[threadIdx.x] = 0;
     __syncthreads();
+    // flush the window; the same counts also go into per-scan-tile totals
+    // (kScanTile buckets each), so the scan needs no separate reduction pass
+    const int tlo = lo / kScanTile;
     for (int i = threadIdx.x; i < nbw; i += blockDim.x) {
         const int c = sm.hist[i];
-        if (c) atomicAdd(&counts[lo + i], c);
+        if (c) {
+            atomicAdd(&counts[lo + i], c);
+            atomicAdd(&s_tile[(lo + i) / kScanTile - tlo], c);
+        }
     }
+    __syncthreads();
+    const int ntile_win = (lo + nbw - 1) / kScanTile - tlo + 1;
+    if (threadIdx.x < ntile_win && s_tile[threadIdx.x]) atomicAdd(&tsum[tlo + threadIdx.x], s_tile[threadIdx.x]);
     if (threadIdx.x == 0 && s_flags) atomicOr(flags, s_flags);
 }
 
@@ -459,22 +474,8 @@ __device__ int block_excl_scan(int v, int* excl, int* s_w)
     return total;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int* __restrict__ counts, int nbt,
-                                                             int* __restrict__ tile_sums)
-{
-    __shared__ int s_w[kScanThreads / kWave + 1];
-    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-    int s = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        int i = base + k;
-        s += (i < nbt) ? counts[i] : 0;
-    }
-    int excl;
-    int tot = block_excl_scan(s, &excl, s_w);
-    if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot;
-}
-
+// Exclusive prefix of the per-tile totals, in place (used when there are too
+// many tiles for every block of the apply kernel to sum its predecessors).
 __global__ __launch_bounds__(1024) void k_scan_tiles(int* __restrict__ tile_sums, int ntiles)
 {
     __shared__ int s_w[1024 / kWave + 1];
@@ -493,28 +494,63 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(int* __restrict__ tile_sums
     }
 }
 
+// Offsets of one tile of kScanTile buckets: the tile's start (the sum of the
+// preceding tiles' totals, or an already-scanned prefix when `scanned`) plus
+// an in-block exclusive scan of its counts, 16 per thread as 16-byte vectors.
+// Also clears the other parity's tile totals for the next count pass.
 __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int* __restrict__ counts, int nbt,
-                                                            const int* __restrict__ tile_excl,
-                                                            int* __restrict__ offsets)
+                                                            const int* __restrict__ tsum, int scanned,
+                                                            int* __restrict__ tsum_next, int* __restrict__ offsets)
 {
     __shared__ int s_w[kScanThreads / kWave + 1];
-    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    __shared__ int s_pre;
+    const int tile = blockIdx.x;
+    // tile start
+    int pre;
+    if (scanned) {
+        pre = tsum[tile];
+    } else {
+        int part = 0;
+        for (int t = threadIdx.x; t < tile; t += blockDim.x) part += tsum[t];
+        int excl;
+        pre = block_excl_scan(part, &excl, s_w);
+    }
+    if (threadIdx.x == 0) {
+        s_pre = pre;
+        tsum_next[tile] = 0;
+    }
+    const int base = tile * kScanTile + threadIdx.x * kScanItems;
     int c[kScanItems];
+    if (base + kScanItems <= nbt) {
+#pragma unroll
+        for (int k = 0; k < kScanItems; k += 4) {
+            const int4 v = *reinterpret_cast<const int4*>(counts + base + k);
+            c[k] = v.x; c[k + 1] = v.y; c[k + 2] = v.z; c[k + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) c[k] = (base + k < nbt) ? counts[base + k] : 0;
+    }
     int s = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        int i = base + k;
-        c[k] = (i < nbt) ? counts[i] : 0;
-        s += c[k];
-    }
+    for (int k = 0; k < kScanItems; ++k) s += c[k];
     int excl;
     block_excl_scan(s, &excl, s_w);
-    int run = excl + tile_excl[blockIdx.x];
+    int run = excl + s_pre;
+    int o[kScanItems];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        int i = base + k;
-        if (i < nbt) offsets[i] = run;
+        o[k] = run;
         run += c[k];
+    }
+    if (base + kScanItems <= nbt) {
+#pragma unroll
+        for (int k = 0; k < kScanItems; k += 4)
+            *reinterpret_cast<int4*>(offsets + base + k) = make_int4(o[k], o[k + 1], o[k + 2], o[k + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k)
+            if (base + k < nbt) offsets[base + k] = o[k];
     }
 }
 
@@ -531,7 +567,7 @@ static size_t sort_smem(const Geo& g, bool push)
 
 template <int PREC, int VD>
 static hipError_t launch_sort_t(const Geo& g, void* src, void* dst, const double* E, const RowShift* rows,
-                                double dtk, float bk, int* counts, int* offsets, int* tile_sums,
+                                double dtk, float bk, int* counts, int* offsets, int* tile_sums, int* tile_next,
                                 int* flags, bool push, hipStream_t st, int phase)
 {
     using MT = typename MarkersOf<PREC>::T;
@@ -551,14 +587,19 @@ static hipError_t launch_sort_t(const Geo& g, void* src, void* dst, const double
         }
     }
     if (phase == 0) {
-        if (push) hipLaunchKernelGGL((k_count<PREC, VD, true>), dim3(cblocks), dim3(kSortThreads), smem, st, g, s, E, rows, dtk, bk, counts, flags);
-        else hipLaunchKernelGGL((k_count<PREC, VD, false>), dim3(cblocks), dim3(kSortThreads), smem, st, g, s, E, rows, dtk, bk, counts, flags);
+        if (push) hipLaunchKernelGGL((k_count<PREC, VD, true>), dim3(cblocks), dim3(kSortThreads), smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags);
+        else hipLaunchKernelGGL((k_count<PREC, VD, false>), dim3(cblocks), dim3(kSortThreads), smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags);
     } else if (phase == 1) {
+        // tile_sums: this sort's totals; tile_next: the other parity, cleared here
         const int nbt = g.nb + 1;
         const int ntiles = (nbt + kScanTile - 1) / kScanTile;
-        hipLaunchKernelGGL(k_scan_reduce, dim3(ntiles), dim3(kScanThreads), 0, st, counts, nbt, tile_sums);
-        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, tile_sums, ntiles);
-        hipLaunchKernelGGL(k_scan_apply, dim3(ntiles), dim3(kScanThreads), 0, st, counts, nbt, tile_sums, offsets);
+        int scanned = 0;
+        if (ntiles > 1024) {
+            hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, tile_sums, ntiles);
+            scanned = 1;
+        }
+        hipLaunchKernelGGL(k_scan_apply, dim3(ntiles), dim3(kScanThreads), 0, st, counts, nbt, tile_sums, scanned,
+                           tile_next, offsets);
     } else {
         if (push) hipLaunchKernelGGL((k_scatter<PREC, VD, true>), dim3(sblocks), dim3(kSortThreads), smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags);
         else hipLaunchKernelGGL((k_scatter<PREC, VD, false>), dim3(sblocks), dim3(kSortThreads), smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags);
@@ -568,13 +609,13 @@ static hipError_t launch_sort_t(const Geo& g, void* src, void* dst, const double
 
 // phase 0 = count, 1 = scan, 2 = scatter
 hipError_t launch_sort(const Geo& g, void* src, void* dst, const double* E, const RowShift* rows,
-                       double dtk, float bk, int* counts, int* offsets, int* tile_sums, int* flags,
+                       double dtk, float bk, int* counts, int* offsets, int* tile_sums, int* tile_next, int* flags,
                        bool push, hipStream_t st, int phase)
 {
-    if (g.prec == 0 && g.vdim == 1) return launch_sort_t<0, 1>(g, src, dst, E, rows, dtk, bk, counts, offsets, tile_sums, flags, push, st, phase);
-    if (g.prec == 0 && g.vdim == 3) return launch_sort_t<0, 3>(g, src, dst, E, rows, dtk, bk, counts, offsets, tile_sums, flags, push, st, phase);
-    if (g.prec == 1 && g.vdim == 1) return launch_sort_t<1, 1>(g, src, dst, E, rows, dtk, bk, counts, offsets, tile_sums, flags, push, st, phase);
-    return launch_sort_t<1, 3>(g, src, dst, E, rows, dtk, bk, counts, offsets, tile_sums, flags, push, st, phase);
+    if (g.prec == 0 && g.vdim == 1) return launch_sort_t<0, 1>(g, src, dst, E, rows, dtk, bk, counts, offsets, tile_sums, tile_next, flags, push, st, phase);
+    if (g.prec == 0 && g.vdim == 3) return launch_sort_t<0, 3>(g, src, dst, E, rows, dtk, bk, counts, offsets, tile_sums, tile_next, flags, push, st, phase);
+    if (g.prec == 1 && g.vdim == 1) return launch_sort_t<1, 1>(g, src, dst, E, rows, dtk, bk, counts, offsets, tile_sums, tile_next, flags, push, st, phase);
+    return launch_sort_t<1, 3>(g, src, dst, E, rows, dtk, bk, counts, offsets, tile_sums, tile_next, flags, push, st, phase);
 }
 
 hipError_t launch_push(const Geo& g, void* m, const double* E, const RowShift* rows, double dtk, float bk,
