@@ -69,15 +69,19 @@ typedef enum {
  *            its lower-left cloud neighbour plus FP32 offsets in [0,1) from that
  *            centre (a along x, b along each velocity component) and an FP32 f;
  *            the push works in cell units, the f grid is FP32; rho and the field
- *            solve stay FP64. */
+ *            solve stay FP64.  In 1D-3V the vy and vz clouds of every marker
+ *            must touch the velocity grid (they never move; a marker outside
+ *            raises AVL_EINTERNAL at the next avl_check), and the x-velocity
+ *            index may leave the grid by at most 32 rows. */
 typedef enum { AVL_FP64 = 0, AVL_FP32 = 1 } avl_precision;
 
 /* Options.  The reconstruction sums, per run of markers sharing a cell, the
  * moments S_f, S_af, S_bf, S_abf, S_a, S_b, S_ab of the offsets (from which
  * the four cloud-in-cell corner sums follow exactly); by default these
  * accumulate in FP64 in both forms.
- *  AVL_OPT_KAHAN32: FP32 form only: accumulate them in FP32 with compensated
- *                   (Kahan) summation instead. */
+ *  AVL_OPT_KAHAN32: FP32 form of 1D-1V only: accumulate them in FP32 with
+ *                   compensated (Kahan) summation instead (AVL_ENOTSUP for
+ *                   1D-3V, whose reconstruction always sums in FP64). */
 typedef enum { AVL_OPT_KAHAN32 = 1 } avl_option;
 
 typedef struct avl_config {
@@ -133,6 +137,8 @@ int avl_sort(avl_handle* h);
  * cell g, N_g = sum_l alpha_gl f_l, D_g = sum_l alpha_gl, f_g = N_g / D_g with
  * cloud-in-cell area weights alpha (Sec. 2, Fig. "interpolation"); x periodic,
  * cloud parts outside the velocity range dropped; f_g = 0 where D_g = 0.
+ * 1D-1V uses area weights in (x, vx); 1D-3V the volume weights of a cloud of
+ * one cell in (x, vx, vy, vz), 16 cells per marker.
  * f_out and D_out (may be NULL) receive G = nx*prod(nv) values in the storage
  * precision (double for AVL_FP64, float for AVL_FP32). */
 int avl_reconstruct(avl_handle* h, void* f_out, void* D_out);

@@ -65,12 +65,13 @@ int make_geo(const avl_config* c, Geo* g)
     if (!c) return AVL_EINVAL;
     std::memset(g, 0, sizeof(Geo));
     if (c->vdim != 1 && c->vdim != 3) return AVL_EINVAL;
-    if (c->vdim == 3) return AVL_ENOTSUP;
     if (c->nx < 8 || c->nx > kMaxNx || (c->nx & (c->nx - 1))) return AVL_EINVAL;
     if (c->precision != AVL_FP64 && c->precision != AVL_FP32) return AVL_EINVAL;
     if (c->first_kick != 0 && c->first_kick != 1) return AVL_EINVAL;
     if (c->options & ~AVL_OPT_KAHAN32) return AVL_EINVAL;
     if ((c->options & AVL_OPT_KAHAN32) && c->precision != AVL_FP32) return AVL_EINVAL;
+    // the 1D-3V reconstruction always accumulates in FP64
+    if ((c->options & AVL_OPT_KAHAN32) && c->vdim == 3) return AVL_ENOTSUP;
     if (c->n_markers < 0 || c->n_markers >= (int64_t)INT32_MAX) return AVL_ESIZE;
     if (!finite_pos(c->L) || !finite_pos(c->dt) || !finite_pos(c->c_p)) return AVL_EINVAL;
     if (!std::isfinite(c->q) || !std::isfinite(c->m) || c->m == 0.0) return AVL_EINVAL;
@@ -139,12 +140,14 @@ int make_geo(const avl_config* c, Geo* g)
         while (jr < c->nv[0] + 1 + 64) jr <<= 1;
         g->jrange = jr;
         g->jpad = (jr - (c->nv[0] + 1)) / 2;
-        if ((int64_t)jr * (c->nv[1] + 1) * (c->nv[2] + 1) * c->nx >= (int64_t)INT32_MAX) {
-            if (c->precision == AVL_FP32) return AVL_ENOTSUP;
-        }
-        g->nstrip = 0;
+        if (c->precision == AVL_FP32 &&
+            (int64_t)jr * (c->nv[1] + 1) * (c->nv[2] + 1) * c->nx >= (int64_t)INT32_MAX)
+            return AVL_ESIZE;
+        // one wave task per 63-column strip and target (vy, vz) plane; the rho
+        // partials are per plane
+        g->nstrip = (c->nx + kReconCols - 1) / kReconCols;
         g->rc = 1;
-        g->nchunk = (int)(rows / (c->nv[0] + 1));   // one partial per (vy, vz) plane of dual rows
+        g->nchunk = c->nv[1] * c->nv[2];
         g->cap = 0;
     }
     return AVL_OK;

@@ -205,7 +205,7 @@ def bump_on_tail(nx: int = 1024, nv: int = 1024, ppc: int = 16, seed: int = 3901
         weights=weights)
 
 
-def two_stream_3v(nx: int = 512, nv: int = 64, ppc: int = 4, seed: int = 3,
+def two_stream_3v(nx: int = 512, nv: int = 64, ppc: int = 2, seed: int = 3,
                   steps: int = 100) -> Workload:
     """Two counter-drifting Maxwellians (+-3 along x), isotropic in vy and vz."""
     return Workload(

@@ -91,3 +91,14 @@ def test_three_v_config_sizes():
     c = avl.make_config(w, precision=avl.AVL_FP32)
     n = avl.avl_workspace_bytes(c)
     assert n == 0 or n > 2 * 24 * w.n_markers
+
+
+def test_three_v_rejects_kahan_option():
+    """The 1D-3V reconstruction sums in FP64 only; the compensated FP32 option is refused."""
+    w = inputs.two_stream_3v(nx=16, nv=8, ppc=2)
+    c = avl.make_config(w, precision=avl.AVL_FP32, options=avl.AVL_OPT_KAHAN32)
+    assert avl.avl_workspace_bytes(c) == 0
+    lib = avl.load()
+    h = ctypes.c_void_p()
+    rc = lib.avl_init(ctypes.byref(c), ctypes.c_void_p(256), 1 << 30, None, None, None, None, ctypes.byref(h))
+    assert rc == -6 and not h.value
