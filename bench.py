@@ -12,6 +12,10 @@ beside it.  ``roofline`` is for the reconstruction kernel, timed with HIP
 events on the library's stream around every launch in a second timed region
 of direct launches.
 ``cpu_baseline`` times the CPU oracle on a bounded sample of the same workload.
+
+``--workload two_stream_3v`` measures the 1D-3V two-stream case instead (512 x
+64^3 cells, 4 markers per cell, 536,870,912 markers; FP32 form by default, no
+CPU baseline).
 """
 import argparse
 import json
@@ -91,6 +95,41 @@ def run_form(avl, inputs, w, x, v, f, form, steps, warmup):
     return ms / steps, ms_graph / steps, kt
 
 
+RECON_SOURCES = ("paper_1804_03901_amd/csrc/avl_recon.hip", "paper_1804_03901_amd/csrc/avl_device.h")
+TRAFFIC_SUMMARY = "profiles/hbm_traffic_bump_on_tail_16M.txt"
+
+
+def source_digest(paths=RECON_SOURCES):
+    """sha256 over the sources that define the reconstruction kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel_tag):
+    """HBM bytes per launch of the reconstruction from the committed PMC
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel
+    calibration), or None when the kernel sources changed since the counters
+    were taken or no summary exists."""
+    path = os.path.join(ROOT, TRAFFIC_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    digest = None
+    rows = {}
+    for line in open(path):
+        if line.startswith("# source_sha256"):
+            digest = line.split()[-1]
+        elif line.startswith("traffic "):
+            _, tag, fetch, write = line.split()[:4]
+            rows[tag] = (float(fetch), float(write))
+    if digest != source_digest() or kernel_tag not in rows:
+        return None
+    return rows[kernel_tag][0] + rows[kernel_tag][1]
+
+
 def cpu_baseline(inputs, w, x, v, f, steps):
     import oracle
     g = oracle.Grid.from_workload(w)
@@ -120,9 +159,11 @@ def main():
     ap.add_argument("--nx", type=int, default=1024)
     ap.add_argument("--nv", type=int, default=1024)
     ap.add_argument("--ppc", type=int, default=16)
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--forms", default="fp32,fp32_kahan,fp64")
+    ap.add_argument("--forms", default=None, help="default: fp32,fp32_kahan,fp64 (1D-1V); fp32 (1D-3V)")
+    ap.add_argument("--workload", default="bump_on_tail", choices=["bump_on_tail", "two_stream_3v"],
+                    help="two_stream_3v: the 1D-3V two-stream case, 512 x 64^3 cells, 4 markers per cell")
     ap.add_argument("--no-probe", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -132,16 +173,22 @@ def main():
     import torch
     from paper_1804_03901_amd import avl, inputs
 
-    w = inputs.bump_on_tail(nx=args.nx, nv=args.nv, ppc=args.ppc)
+    three_v = args.workload == "two_stream_3v"
+    if three_v:
+        w = inputs.two_stream_3v()
+        args.no_cpu = True
+    else:
+        w = inputs.bump_on_tail(nx=args.nx, nv=args.nv, ppc=args.ppc)
+    forms = (args.forms or ("fp32" if three_v else "fp32,fp32_kahan,fp64")).split(",")
     log(f"generating {w.n_markers} markers ({w.name})")
-    x, v, f = inputs.markers(w)
+    x, v, f = inputs.markers_threaded(w)
     v = v.reshape(-1)
     results = {}
     probe = None
     if not args.no_probe:
         probe = copy_probe(avl)
         log(f"copy probe: {probe[0]:.0f} GB/s")
-    for form in args.forms.split(","):
+    for form in forms:
         log(f"form {form}: warmup {args.warmup}, timed {args.steps}")
         results[form] = run_form(avl, inputs, w, x, v, f, form, args.steps, args.warmup)
         log(f"form {form}: {results[form][1]:.4f} ms/step graph, {results[form][0]:.4f} direct with events")
@@ -149,9 +196,11 @@ def main():
     ms_direct, ms, kt = results[main_form]
     value = w.n_markers / (ms * 1e-3)
     rk = kt["reconstruct"]
+    recon_kernel = "k_recon_3v" if three_v else "k_recon_1v"
     achieved = rk["bytes_per_launch"] / (rk["ms_avg"] * 1e-3) / 1e9
     out = {
-        "metric": "marker-steps/s, 1D-1V 16.8M markers, FP32+batched vs FP64 plain; % HBM peak",
+        "metric": ("marker-steps/s, 1D-3V two-stream 537M markers, FP32 form; % HBM peak" if three_v else
+                   "marker-steps/s, 1D-1V 16.8M markers, FP32+batched vs FP64 plain; % HBM peak"),
         "value": value,
         "unit": "marker-steps/s",
         "n_gpus": 1,
@@ -163,10 +212,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if main_form == "fp64" else "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "markers": w.n_markers, "nx": w.nx, "nv": w.nv[0], "ppc": w.ppc,
+        "config": {"workload": w.name, "markers": w.n_markers, "nx": w.nx, "nv": list(w.nv[: w.vdim]), "ppc": w.ppc,
                    "form": main_form, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_recon_1v",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None if three_v else measured_traffic(f"recon_{main_form}"),
+                     "traffic_unit": "bytes per launch (PMC, calibrated)", "kernel": recon_kernel,
                      "bytes_per_launch": rk["bytes_per_launch"], "ms_per_launch": rk["ms_avg"]},
         "timing": "value: HIP-graph replay of the step, events around the whole timed region; kernels: a "
                   "second timed region of direct launches with events around every kernel",

@@ -99,6 +99,10 @@ typedef struct avl_config {
     double q;            /* species charge (enters rho) */
     double m;            /* species mass (acceleration is q/m * E), finite != 0 */
     double c_p;          /* Poisson constant, finite > 0 */
+    int32_t tune[4];     /* kernel tuning knobs, 0 = library default (results do not depend on
+                            them beyond summation order):
+                            [0] target velocity rows per 1D-1V reconstruction task, 1..256;
+                            [1]..[3] reserved, must be 0 */
 } avl_config;
 
 typedef struct avl_handle avl_handle;

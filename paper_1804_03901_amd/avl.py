@@ -41,7 +41,12 @@ class AvlConfig(ctypes.Structure):
         ("n_markers", ctypes.c_int64), ("L", ctypes.c_double),
         ("vmin", ctypes.c_double * 3), ("vmax", ctypes.c_double * 3),
         ("dt", ctypes.c_double), ("q", ctypes.c_double), ("m", ctypes.c_double), ("c_p", ctypes.c_double),
+        ("tune", ctypes.c_int32 * 4),
     ]
+
+
+# avl_config.tune slots (0 leaves the library's choice)
+TUNE_RECON_ROWS = 0       # target velocity rows per 1D-1V reconstruction task, 1..256
 
 
 _lib = None
@@ -118,7 +123,7 @@ def _stream_ptr(stream) -> Optional[int]:
 
 
 def make_config(w: "inputs.Workload", precision: int = AVL_FP64, n_markers: Optional[int] = None,
-                options: int = 0) -> AvlConfig:
+                options: int = 0, tune: Optional[dict] = None) -> AvlConfig:
     c = AvlConfig()
     c.vdim = w.vdim
     c.nx = w.nx
@@ -132,6 +137,8 @@ def make_config(w: "inputs.Workload", precision: int = AVL_FP64, n_markers: Opti
     c.n_markers = w.n_markers if n_markers is None else n_markers
     c.L = w.L
     c.dt, c.q, c.m, c.c_p = w.dt, w.q, w.m, w.c_p
+    for slot, value in (tune or {}).items():
+        c.tune[slot] = int(value)
     return c
 
 
@@ -233,7 +240,7 @@ class Simulation:
     """One VHS species on one GPU: owns a torch workspace and a libavl handle."""
 
     def __init__(self, w: "inputs.Workload", x, v, f, precision: int = AVL_FP64, device: str = "cuda:0",
-                 stream=None, options: int = 0):
+                 stream=None, options: int = 0, tune: Optional[dict] = None):
         import torch
         self.w = w
         self.device = torch.device(device)
@@ -242,7 +249,7 @@ class Simulation:
         v = torch.as_tensor(v, dtype=torch.float64, device=self.device).reshape(-1).contiguous()
         f = torch.as_tensor(f, dtype=torch.float64, device=self.device).contiguous()
         self.n = x.numel()
-        self.cfg = make_config(w, precision, self.n, options)
+        self.cfg = make_config(w, precision, self.n, options, tune)
         nbytes = avl_workspace_bytes(self.cfg)
         if nbytes == 0:
             raise AvlError(-1, "avl_workspace_bytes")

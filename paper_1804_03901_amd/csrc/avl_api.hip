@@ -24,9 +24,10 @@ hipError_t launch_recon(const Geo& g, void* m, const int* offsets, void* fgrid, 
 int recon_capacity(int prec);
 hipError_t launch_recon3(const Geo& g, void* m, const int* offsets, void* fgrid, void* Dgrid, double* rho_part,
                          void* scratch, hipStream_t st);
-hipError_t launch_field(const Geo& g, const double* rho_part, const double* rho_in, double* rho, double* E_out,
-                        const double2* tw, const double* green, double* diag_ring, long long* step_ctr,
-                        int write_diag, double* W_out, int* flags, int* done, hipStream_t st);
+hipError_t launch_field(const Geo& g, const double* rho_part, const double* rho_in, double* rho_slices, double* rho,
+                        double* E_out, const double2* tw, const double* green, double* diag_ring,
+                        long long* step_ctr, int write_diag, double* W_out, int* flags, hipStream_t st);
+int field_slices(const Geo& g);
 hipError_t launch_validate(const Geo& g, const double* x, const double* v, const double* f, int* bad,
                            hipStream_t st);
 hipError_t launch_to32(const Geo& g, const double* x, const double* v, const double* f, M32 m, int* flags,
@@ -46,8 +47,8 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
-    size_t markers[2], counts, offsets, tile_sums, fgrid, rho_part, rho, E, tw, green, rows, diag, ctr, flags, bad,
-        done, scratch3, total;
+    size_t markers[2], counts, offsets, tile_sums, fgrid, rho_part, rho_slices, rho, E, tw, green, rows, diag, ctr, flags, bad,
+        scratch3, total;
 };
 
 int ilog2(int v)
@@ -69,6 +70,7 @@ int make_geo(const avl_config* c, Geo* g)
     if (c->precision != AVL_FP64 && c->precision != AVL_FP32) return AVL_EINVAL;
     if (c->first_kick != 0 && c->first_kick != 1) return AVL_EINVAL;
     if (c->options & ~AVL_OPT_KAHAN32) return AVL_EINVAL;
+    if (c->tune[0] < 0 || c->tune[0] > 256 || c->tune[1] || c->tune[2] || c->tune[3]) return AVL_EINVAL;
     if ((c->options & AVL_OPT_KAHAN32) && c->precision != AVL_FP32) return AVL_EINVAL;
     // the 1D-3V reconstruction always accumulates in FP64
     if ((c->options & AVL_OPT_KAHAN32) && c->vdim == 3) return AVL_ENOTSUP;
@@ -126,11 +128,11 @@ int make_geo(const avl_config* c, Geo* g)
     // reconstruction decomposition
     if (c->vdim == 1) {
         // about 2048 wave tasks (each a 63-column strip by rc velocity rows)
-        // so that every CU runs several; AVL_RECON_ROWS overrides rc
+        // so that every CU runs several; tune[0] overrides rc
         g->nstrip = (c->nx + kReconCols - 1) / kReconCols;
         int want_chunks = std::max(1, 2048 / g->nstrip);
         int rc = std::max(2, std::min(32, c->nv[0] / want_chunks));
-        if (const char* env = std::getenv("AVL_RECON_ROWS")) rc = std::max(1, std::min(256, std::atoi(env)));
+        if (c->tune[0]) rc = c->tune[0];
         g->rc = rc;
         g->nchunk = (c->nv[0] + rc - 1) / rc;
         g->cap = recon_capacity(c->precision);
@@ -171,6 +173,7 @@ void make_layout(const avl_config* c, const Geo& g, Layout* L)
     L->tile_sums = take(sizeof(int) * 2 * (ntiles + 64));   // two parities of per-tile totals
     L->fgrid = take(esz * cells);
     L->rho_part = take(sizeof(double) * (size_t)std::max(1, g.nchunk) * g.nx);
+    L->rho_slices = take(sizeof(double) * (size_t)kMaxFieldSlices * g.nx);
     L->rho = take(sizeof(double) * g.nx);
     L->E = take(sizeof(double) * g.nx);
     L->tw = take(sizeof(double) * g.nx);
@@ -180,7 +183,6 @@ void make_layout(const avl_config* c, const Geo& g, Layout* L)
     L->ctr = take(sizeof(long long));
     L->flags = take(sizeof(int));
     L->bad = take(sizeof(int));
-    L->done = take(sizeof(int));
     L->scratch3 = take(g.vdim == 3 ? recon3_scratch_bytes(g) : 0);
     L->total = off;
 }
@@ -208,9 +210,9 @@ struct avl_handle {
     M64 m64[2];
     M32 m32[2];
     int cur;
-    int *counts, *offsets, *tile_sums, *flags, *bad, *done;
+    int *counts, *offsets, *tile_sums, *flags, *bad;
     void* fgrid;
-    double *rho_part, *rho, *E, *green, *diag;
+    double *rho_part, *rho_slices, *rho, *E, *green, *diag;
     double2* tw;
     RowShift* rows;
     long long* ctr;
@@ -401,8 +403,8 @@ int do_field(avl_handle* h, const double* rho_in, bool diag, double* W_out)
 {
     Timer t(h, AVL_K_FIELD);
     if (!rho_in && !h->partials) return AVL_ESTATE;
-    AVL_TRY(launch_field(h->g, h->rho_part, rho_in, h->rho, h->E, h->tw, h->green, h->diag, h->ctr, diag ? 1 : 0,
-                         W_out, h->flags, h->done, h->st));
+    AVL_TRY(launch_field(h->g, h->rho_part, rho_in, h->rho_slices, h->rho, h->E, h->tw, h->green, h->diag, h->ctr,
+                         diag ? 1 : 0, W_out, h->flags, h->st));
     if (!rho_in) h->have_rho = true;
     h->have_E = true;
     return AVL_OK;
@@ -530,6 +532,7 @@ int avl_init(const avl_config* cfg, void* workspace, size_t ws_bytes, void* stre
     h->tile_sums = (int*)(h->ws + lay.tile_sums);
     h->fgrid = h->ws + lay.fgrid;
     h->rho_part = (double*)(h->ws + lay.rho_part);
+    h->rho_slices = (double*)(h->ws + lay.rho_slices);
     h->rho = (double*)(h->ws + lay.rho);
     h->E = (double*)(h->ws + lay.E);
     h->tw = (double2*)(h->ws + lay.tw);
@@ -539,7 +542,6 @@ int avl_init(const avl_config* cfg, void* workspace, size_t ws_bytes, void* stre
     h->ctr = (long long*)(h->ws + lay.ctr);
     h->flags = (int*)(h->ws + lay.flags);
     h->bad = (int*)(h->ws + lay.bad);
-    h->done = (int*)(h->ws + lay.done);
     h->scratch3 = h->ws + lay.scratch3;
     h->gexec[0] = h->gexec[1] = nullptr;
     h->cap_st = nullptr;
@@ -555,8 +557,7 @@ int avl_init(const avl_config* cfg, void* workspace, size_t ws_bytes, void* stre
             std::fprintf(stderr, "[avl] lds limit %d B, recon cap %d, hist bins %d, rc %d, chunks %d, strips %d\n", lds,
                          h->g.cap, h->g.hist_bins, h->g.rc, h->g.nchunk, h->g.nstrip);
     }
-    if (hipMemsetAsync(h->flags, 0, sizeof(int), h->st) != hipSuccess ||
-        hipMemsetAsync(h->done, 0, sizeof(int), h->st) != hipSuccess || (rc = upload_tables(h)) != AVL_OK) {
+    if (hipMemsetAsync(h->flags, 0, sizeof(int), h->st) != hipSuccess || (rc = upload_tables(h)) != AVL_OK) {
         delete h;
         return rc ? rc : AVL_EDEVICE;
     }

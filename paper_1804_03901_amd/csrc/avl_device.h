@@ -31,7 +31,8 @@ constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
 constexpr int kReconCols = kWave - 1;                     // target columns per reconstruct wave
 constexpr int kDiagCap = 4096;                            // per-step diagnostics ring
-constexpr int kFieldThreads = 256;
+constexpr int kFieldThreads = 1024;                      // threads of a field-solve block
+constexpr int kMaxFieldSlices = 64;                       // chunk slices of the rho reduction
 constexpr int kMaxNx = 4096;
 
 struct Geo {
@@ -92,6 +93,16 @@ inline hipError_t ensure_lds(const void* fn, size_t bytes, int& granted)
 }
 
 __device__ __forceinline__ int wrap_pow2(int i, int nx) { return i & (nx - 1); }
+
+// Raw buffer descriptor (gfx9 family, 32-bit raw data) over `bytes` bytes at
+// p: buffer loads past the end return zero instead of touching memory, so
+// loads of a ragged tail need no branches.  num_records is a 32-bit byte
+// count; callers keep each descriptor's range below 4 GiB.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* p, size_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0,
+                                             (int)(unsigned)min(bytes, (size_t)0xffffffffu), 0x00020000);
+}
 
 // Bucket of an FP64 marker and its in-cell offsets.  Returns g.nb when the
 // cloud misses the velocity grid (or a coordinate is not finite).

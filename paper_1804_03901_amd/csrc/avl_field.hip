@@ -1,14 +1,18 @@
-// Charge density, spectral field solve and per-step diagnostics, one block.
+// Charge density, spectral field solve and per-step diagnostics in one launch.
 //
 // rho_i = q * prod(dv) * sum_j f_ij is assembled from the reconstruction's
-// per-chunk column partials in chunk order (Sec. 2: the moment is a plain sum
-// over velocity cells at fixed x).  The field follows Eq. (poissonk) with the
-// softening of Eq. (kappasoftening): a radix-2 FFT of rho in LDS (decimation in
-// time from bit-reversed order), multiplication by -i c_p kappa_m / K_m^2 (a
-// host-built table that is zero at m = 0 and at the Nyquist mode), and an
-// inverse FFT (decimation in frequency, natural order in, bit-reversed out).
-// nx <= 4096 complex doubles fit in 64 KB of LDS.  The whole solve is FP64.
+// per-chunk column partials (Sec. 2: the moment is a plain sum over velocity
+// cells at fixed x).  The field follows Eq. (poissonk) with the softening of
+// Eq. (kappasoftening): a forward FFT of rho, multiplication by
+// -i c_p kappa_m / K_m^2 (a host-built table that is zero at m = 0 and at the
+// Nyquist mode), and an inverse FFT, taken as the forward transform of the
+// conjugate spectrum (E is real, so E = Re FFT(conj(E_hat)) / nx).  The FFT is
+// a self-sorting (Stockham) radix-4 transform in LDS, with one radix-2 stage
+// first when log2(nx) is odd; each stage reads all its inputs, synchronises,
+// then writes, so one nx-point buffer suffices.  FP64 throughout.
 // Also here: marker validation/conversion kernels and the copy probe.
+#include <algorithm>
+
 #include "avl_device.h"
 
 namespace avl {
@@ -17,169 +21,246 @@ static int g_lds_limit = 65536;
 void set_lds_limit(int bytes) { g_lds_limit = bytes; }
 int lds_limit() { return g_lds_limit; }
 
-__device__ __forceinline__ int bitrev(int i, int lg) { return (int)(__brev((unsigned)i) >> (32 - lg)); }
+constexpr int kFT = kFieldThreads;            // threads of a field block
+constexpr int kFieldGroups = kFT / 64;         // chunk groups per 64-column block
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-template <int NT>
-__device__ void block_sum3(double& a, double& b, double& c, double* s)
+// e^{-2 pi i idx / N} for idx in [0, N) from the half table (idx < N/2),
+// using w^(idx + N/2) = -w^idx; no branch, one LDS read.
+__device__ __forceinline__ double2 twiddle(const double2* stw, int idx, int half_n)
 {
-    s[threadIdx.x] = a;
-    s[NT + threadIdx.x] = b;
-    s[2 * NT + threadIdx.x] = c;
-    __syncthreads();
-    for (int o = NT / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) {
-            s[threadIdx.x] += s[threadIdx.x + o];
-            s[NT + threadIdx.x] += s[NT + threadIdx.x + o];
-            s[2 * NT + threadIdx.x] += s[2 * NT + threadIdx.x + o];
-        }
-        __syncthreads();
-    }
-    a = s[0];
-    b = s[NT];
-    c = s[2 * NT];
+    const double2 t = stw[idx & (half_n - 1)];
+    const double s = (idx & half_n) ? -1.0 : 1.0;
+    return make_double2(s * t.x, s * t.y);
 }
 
-// One launch for the charge density and the field.  Every block assembles rho
-// for 64 x cells from the reconstruction's chunk partials (four groups of
-// chunks per column, combined in a fixed order), then the last block to
-// finish -- found with a device-scope fence and a counter it resets -- runs
-// the FFT solve.  With rho given by the caller a single block does the solve.
-__global__ __launch_bounds__(kFieldThreads) void k_field(Geo g, const double* __restrict__ rho_part,
-                                                         const double* __restrict__ rho_in,
-                                                         double* __restrict__ rho, double* __restrict__ E_out,
-                                                         const double2* __restrict__ tw,
-                                                         const double* __restrict__ green,
-                                                         double* __restrict__ diag_ring,
-                                                         long long* __restrict__ step_ctr, int write_diag,
-                                                         double* __restrict__ W_out, int* __restrict__ flags,
-                                                         int* __restrict__ done)
+// One Stockham stage of radix R (2 or 4) for the current span Ns: butterfly j
+// takes inputs j + r*N/R, twiddled by w^(r*(j mod Ns)*N/(Ns*R)), and writes
+// output r to (j - j mod Ns)*R + j mod Ns + r*Ns.
+template <int R>
+__device__ __forceinline__ void stockham_stage(double2* z, const double2* stw, int lgN, int lgNs)
 {
+    constexpr int lgR = R == 2 ? 1 : 2;
+    constexpr int MAXJ = (kMaxNx / R + kFT - 1) / kFT;
+    const int N = 1 << lgN, nb = N >> lgR, half_n = N >> 1;
+    const int Ns = 1 << lgNs, tshift = lgN - lgNs - lgR;
+    double2 v[MAXJ][R];
+    int dst[MAXJ];
+#pragma unroll
+    for (int q = 0; q < MAXJ; ++q) {
+        const int j = threadIdx.x + q * kFT;
+        dst[q] = -1;
+        if (j < nb) {
+            const int k = j & (Ns - 1);
+            const int t = k << tshift;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double2 x = z[j + r * nb];
+                v[q][r] = r == 0 ? x : cmul(x, twiddle(stw, r * t, half_n));
+            }
+            if (R == 2) {
+                const double2 a = v[q][0], b = v[q][1];
+                v[q][0] = make_double2(a.x + b.x, a.y + b.y);
+                v[q][1] = make_double2(a.x - b.x, a.y - b.y);
+            } else {
+                const double2 a = make_double2(v[q][0].x + v[q][2].x, v[q][0].y + v[q][2].y);
+                const double2 b = make_double2(v[q][0].x - v[q][2].x, v[q][0].y - v[q][2].y);
+                const double2 c = make_double2(v[q][1].x + v[q][3].x, v[q][1].y + v[q][3].y);
+                const double2 d = make_double2(v[q][1].x - v[q][3].x, v[q][1].y - v[q][3].y);
+                v[q][0] = make_double2(a.x + c.x, a.y + c.y);
+                v[q][1] = make_double2(b.x + d.y, b.y - d.x);      // b - i d
+                v[q][2] = make_double2(a.x - c.x, a.y - c.y);
+                v[q][3] = make_double2(b.x - d.y, b.y + d.x);      // b + i d
+            }
+            dst[q] = (j - k) * R + k;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MAXJ; ++q)
+        if (dst[q] >= 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) z[dst[q] + r * Ns] = v[q][r];
+        }
+    __syncthreads();
+}
+
+// In-place forward DFT, X_m = sum_n z_n e^{-2 pi i m n / N}, natural order in and out.
+__device__ void fft_forward(double2* z, const double2* stw, int lgN)
+{
+    int lgNs = 0;
+    if (lgN & 1) {
+        stockham_stage<2>(z, stw, lgN, 0);
+        lgNs = 1;
+    }
+    for (; lgNs < lgN; lgNs += 2) stockham_stage<4>(z, stw, lgN, lgNs);
+}
+
+
+// Charge density, part 1: block (column group, slice) sums the chunk partials
+// of its slice for 64 x cells (16 groups of chunks per column, combined in a
+// fixed order) into rho_slices[slice][i].
+__global__ __launch_bounds__(kFT) void k_rho(Geo g, const double* __restrict__ rho_part,
+                                             double* __restrict__ rho_slices, int nslice)
+{
+    __shared__ double colsum[kFT];
+    const int nx = g.nx, tid = threadIdx.x;
+    const int ncg = (nx + 63) >> 6;
+    const int cg = blockIdx.x % ncg, sl = blockIdx.x / ncg;
+    const int c = tid & 63, grp = tid >> 6;
+    const int i = cg * 64 + c;
+    const int per = (g.nchunk + nslice - 1) / nslice;
+    const int ch_lo = sl * per, ch_hi = min(g.nchunk, ch_lo + per);
+    double acc = 0.0;
+    if (i < nx) {
+        // batches of 16 independent loads (chunks grp, grp+16, ...), summed in order
+        for (int ch0 = ch_lo + grp; ch0 < ch_hi; ch0 += 16 * kFieldGroups) {
+            double v[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int ch = ch0 + kFieldGroups * k;
+                v[k] = ch < ch_hi ? rho_part[(size_t)ch * nx + i] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < 16; ++k) acc += v[k];
+        }
+    }
+    colsum[grp * 64 + c] = acc;
+    __syncthreads();
+    if (grp == 0 && i < nx) {
+        double t = 0.0;
+        for (int k = 0; k < kFieldGroups; ++k) t += colsum[k * 64 + c];
+        rho_slices[(size_t)sl * nx + i] = t;
+    }
+}
+
+// Charge density, part 2, and the field solve, one block: rho_i = q prod(dv)
+// * (sum of the slices in order) or the caller's rho, then the spectral solve
+// and the diagnostics.  Every global read the block needs is issued up front
+// so that their latencies overlap.
+__global__ __launch_bounds__(kFT) void k_solve(Geo g, const double* __restrict__ rho_slices, int nslice,
+                                               const double* __restrict__ rho_in, double* __restrict__ rho,
+                                               double* __restrict__ E_out, const double2* __restrict__ tw,
+                                               const double* __restrict__ green, double* __restrict__ diag_ring,
+                                               long long* __restrict__ step_ctr, int write_diag,
+                                               double* __restrict__ W_out, int* __restrict__ flags)
+{
+    constexpr int Q = kMaxNx / kFT;               // grid points per thread at most
     extern __shared__ __align__(16) unsigned char smem[];
     const int nx = g.nx, lg = g.lognx;
     const int half_n = nx >> 1;
     double2* z = reinterpret_cast<double2*>(smem);
     double2* stw = z + nx;
-    double* sgr = reinterpret_cast<double*>(stw + half_n);
-    __shared__ double red[3 * kFieldThreads];
-    __shared__ int s_last;
-    const double* src = rho_in;
+    const int tid = threadIdx.x;
 
-    if (!rho_in) {
-        // rho_i = q prod(dv) sum_c part[c][i]
-        double* colsum = red;   // [4][64]
-        const int c = threadIdx.x & 63, grp = threadIdx.x >> 6;
-        const int i = blockIdx.x * 64 + c;
-        double acc = 0.0;
+    const long long ctr = (write_diag && tid == 0) ? *step_ctr : 0;
+    double rv[Q], gv[Q];
+    double2 twv[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int i = tid + q * kFT;
+        rv[q] = 0.0;
+        gv[q] = 0.0;
+        twv[q] = make_double2(0.0, 0.0);
         if (i < nx) {
-            // batches of 16 independent loads (chunks grp, grp+4, ...), summed in order
-            for (int ch0 = grp; ch0 < g.nchunk; ch0 += 64) {
-                double v[16];
-#pragma unroll
-                for (int k = 0; k < 16; ++k) {
-                    const int ch = ch0 + 4 * k;
-                    v[k] = ch < g.nchunk ? rho_part[(size_t)ch * nx + i] : 0.0;
-                }
-#pragma unroll
-                for (int k = 0; k < 16; ++k) acc += v[k];
+            if (rho_in) {
+                rv[q] = rho_in[i];
+            } else {
+                for (int s = 0; s < nslice; ++s) rv[q] += rho_slices[(size_t)s * nx + i];
             }
+            gv[q] = green[i];
+            if (i < half_n) twv[q] = tw[i];
         }
-        colsum[grp * 64 + c] = acc;
-        __syncthreads();
-        if (grp == 0 && i < nx)
-            rho[i] = (((colsum[c] + colsum[64 + c]) + colsum[128 + c]) + colsum[192 + c]) * g.q_vol;
-        __threadfence();
-        __syncthreads();
-        if (threadIdx.x == 0) s_last = atomicAdd(done, 1) == (int)gridDim.x - 1;
-        __syncthreads();
-        if (!s_last) return;
-        __threadfence();
-        src = rho;
     }
-
-    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
-        z[bitrev(i, lg)] = make_double2(src[i], 0.0);
-        sgr[i] = green[i];
-        if (i < half_n) stw[i] = tw[i];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int i = tid + q * kFT;
+        if (i < nx) {
+            double r = rv[q];
+            if (!rho_in) {
+                r *= g.q_vol;
+                rho[i] = r;
+            }
+            z[i] = make_double2(r, 0.0);
+            if (i < half_n) stw[i] = twv[q];
+        }
     }
     __syncthreads();
-    // forward transform, rho_hat_m = sum_i rho_i exp(-2 pi i m i / nx)
-    for (int lh = 0; (1 << lh) < nx; ++lh) {
-        const int half = 1 << lh, len = half << 1, stride = nx / len;
-        for (int b = threadIdx.x; b < half_n; b += blockDim.x) {
-            const int grp = b >> lh, p = b & (half - 1);
-            const int i0 = grp * len + p, i1 = i0 + half;
-            const double2 t = cmul(stw[p * stride], z[i1]);
-            const double2 u = z[i0];
-            z[i0] = make_double2(u.x + t.x, u.y + t.y);
-            z[i1] = make_double2(u.x - t.x, u.y - t.y);
+    // rho_hat_m = sum_i rho_i exp(-2 pi i m i / nx)
+    fft_forward(z, stw, lg);
+    // conj(E_hat_m) with E_hat_m = -i (c_p kappa_m / K_m^2) rho_hat_m
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int m = tid + q * kFT;
+        if (m < nx) {
+            const double2 r = z[m];
+            z[m] = make_double2(gv[q] * r.y, gv[q] * r.x);
         }
-        __syncthreads();
-    }
-    // E_hat_m = -i * (c_p kappa_m / K_m^2) * rho_hat_m
-    for (int m = threadIdx.x; m < nx; m += blockDim.x) {
-        const double2 r = z[m];
-        const double c = sgr[m];
-        z[m] = make_double2(c * r.y, -c * r.x);
     }
     __syncthreads();
-    // inverse transform (unnormalised), natural order in, bit-reversed out
-    for (int lh = lg - 1; lh >= 0; --lh) {
-        const int half = 1 << lh, len = half << 1, stride = nx / len;
-        for (int b = threadIdx.x; b < half_n; b += blockDim.x) {
-            const int grp = b >> lh, p = b & (half - 1);
-            const int i0 = grp * len + p, i1 = i0 + half;
-            const double2 u = z[i0], v = z[i1];
-            const double2 w = stw[p * stride];
-            z[i0] = make_double2(u.x + v.x, u.y + v.y);
-            z[i1] = cmul(make_double2(u.x - v.x, u.y - v.y), make_double2(w.x, -w.y));
-        }
-        __syncthreads();
-    }
-    double sw = 0.0, sre = 0.0, sim = 0.0;
-    int bad = 0;
+    fft_forward(z, stw, lg);
     const double inv_n = 1.0 / nx;
-    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
-        const double E = z[bitrev(i, lg)].x * inv_n;
-        E_out[i] = E;
-        if (!isfinite(E)) bad = 1;
+    int bad = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int i = tid + q * kFT;
+        if (i < nx) {
+            const double E = z[i].x * inv_n;
+            E_out[i] = E;
+            if (!isfinite(E)) bad = 1;
+        }
+    }
+    if (bad) atomicOr(flags, FLAG_NONFINITE);
+    if (tid >= kWave) return;
+    // diagnostics by the first wave: sum E^2 and the mode-1 coefficient of E,
+    // lane-strided then a shuffle tree (fixed order)
+    double sw = 0.0, sre = 0.0, sim = 0.0;
+    for (int i = tid; i < nx; i += kWave) {
+        const double E = z[i].x * inv_n;
+        const double2 w = twiddle(stw, i, half_n);
         sw += E * E;
-        const double2 w = i < half_n ? stw[i] : make_double2(-stw[i - half_n].x, -stw[i - half_n].y);
         sre += E * w.x;
         sim += E * w.y;
     }
-    if (bad) atomicOr(flags, FLAG_NONFINITE);
-    __syncthreads();
-    block_sum3<kFieldThreads>(sw, sre, sim, red);
-    if (threadIdx.x == 0) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        sw += __shfl_xor(sw, o, kWave);
+        sre += __shfl_xor(sre, o, kWave);
+        sim += __shfl_xor(sim, o, kWave);
+    }
+    if (tid == 0) {
         const double W = sw * g.dx / (2.0 * g.cp);
         const double m1 = 2.0 / nx * sqrt(sre * sre + sim * sim);
         if (W_out) *W_out = W;
         if (write_diag) {
-            const long long c = *step_ctr;
-            diag_ring[2 * (c % kDiagCap)] = W;
-            diag_ring[2 * (c % kDiagCap) + 1] = m1;
-            *step_ctr = c + 1;
+            diag_ring[2 * (ctr % kDiagCap)] = W;
+            diag_ring[2 * (ctr % kDiagCap) + 1] = m1;
+            *step_ctr = ctr + 1;
         }
-        if (!rho_in) *done = 0;
     }
 }
 
-hipError_t launch_field(const Geo& g, const double* rho_part, const double* rho_in, double* rho, double* E_out,
-                        const double2* tw, const double* green, double* diag_ring, long long* step_ctr,
-                        int write_diag, double* W_out, int* flags, int* done, hipStream_t st)
+// Chunk slices of the rho reduction: at most 256 chunk partials per block.
+int field_slices(const Geo& g) { return std::max(1, std::min(kMaxFieldSlices, (g.nchunk + 255) / 256)); }
+
+hipError_t launch_field(const Geo& g, const double* rho_part, const double* rho_in, double* rho_slices, double* rho,
+                        double* E_out, const double2* tw, const double* green, double* diag_ring,
+                        long long* step_ctr, int write_diag, double* W_out, int* flags, hipStream_t st)
 {
-    const size_t smem = (sizeof(double2) + sizeof(double2) / 2 + sizeof(double)) * g.nx;
+    const size_t smem = (sizeof(double2) + sizeof(double2) / 2) * g.nx;
     static int granted = 0;
-    hipError_t e = ensure_lds((const void*)k_field, smem, granted);
+    hipError_t e = ensure_lds((const void*)k_solve, smem, granted);
     if (e != hipSuccess) return e;
-    const int blocks = rho_in ? 1 : (g.nx + 63) / 64;
-    hipLaunchKernelGGL(k_field, dim3(blocks), dim3(kFieldThreads), smem, st, g, rho_part, rho_in, rho, E_out, tw,
-                       green, diag_ring, step_ctr, write_diag, W_out, flags, done);
+    const int nslice = field_slices(g);
+    if (!rho_in)
+        hipLaunchKernelGGL(k_rho, dim3(((g.nx + 63) / 64) * nslice), dim3(kFT), 0, st, g, rho_part, rho_slices,
+                           nslice);
+    hipLaunchKernelGGL(k_solve, dim3(1), dim3(kFT), smem, st, g, rho_slices, nslice, rho_in, rho, E_out, tw, green,
+                       diag_ring, step_ctr, write_diag, W_out, flags);
     return hipGetLastError();
 }
 

@@ -109,17 +109,6 @@ template <int PREC> constexpr int recon_cap() { return kWave * (RT<PREC>::KU + 1
 // bytes of LDS per wave: a, b, f as three arrays of the storage type
 template <int PREC> constexpr size_t recon_lds() { return 3 * sizeof(typename RT<PREC>::T) * recon_cap<PREC>(); }
 
-// Raw buffer descriptors (gfx9 family, 32-bit raw data) for the marker
-// arrays the reconstruction reads; out-of-range buffer reads return zero, so
-// the prefetch needs no bounds branches.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* p, size_t bytes)
-{
-    // num_records is a 32-bit byte count: arrays up to 4 GiB (the host limits
-    // 1D-1V marker counts accordingly)
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0,
-                                             (int)(unsigned)min(bytes, (size_t)0xffffffffu), 0x00020000);
-}
-
 // Descriptors cover exactly one range of markers [first, first+count): lanes
 // past the end read zero and cost no memory traffic.
 template <int PREC> struct Src;

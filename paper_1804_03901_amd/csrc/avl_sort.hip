@@ -55,11 +55,12 @@ template <int VD> struct Pay<0, VD> {
 template <int VD> struct Pay<1, VD> {
     int cell;
     float a, b[VD], f;
-    __device__ void load(const M32& m, const Geo& g, int i, bool with_f) {
+    // nvel < VD loads only the first nvel velocity offsets
+    __device__ void load(const M32& m, const Geo& g, int i, bool with_f, int nvel = VD) {
         cell = m.cell[i];
         a = m.a[i];
 #pragma unroll
-        for (int d = 0; d < VD; ++d) b[d] = m.b[(size_t)d * g.np + i];
+        for (int d = 0; d < VD; ++d) b[d] = d < nvel ? m.b[(size_t)d * g.np + i] : 0.0f;
         f = with_f ? m.f[i] : 0.0f;
     }
     __device__ void store(const M32& m, const Geo& g, int i) const {
@@ -98,7 +99,7 @@ template <int PREC, int VD, int K> struct Group;
 
 template <int VD, int K> struct Group<0, VD, K> {
     Pay<0, VD> p[K];
-    __device__ void load(const M64& m, const Geo& g, int first, int last, bool with_f) {
+    __device__ void load(const M64& m, const Geo& g, int first, int last, bool with_f, int = VD) {
         if (first + K - 1 <= last) {
             double t[K];
             vload<double, K>(m.x + first, t);
@@ -124,7 +125,9 @@ template <int VD, int K> struct Group<0, VD, K> {
 
 template <int VD, int K> struct Group<1, VD, K> {
     Pay<1, VD> p[K];
-    __device__ void load(const M32& m, const Geo& g, int first, int last, bool with_f) {
+    // nvel < VD loads only the first nvel velocity offsets (the count pass
+    // needs the cell index, a and the x-velocity offset only)
+    __device__ void load(const M32& m, const Geo& g, int first, int last, bool with_f, int nvel = VD) {
         if (first + K - 1 <= last) {
             int ti[K];
             float t[K];
@@ -136,7 +139,12 @@ template <int VD, int K> struct Group<1, VD, K> {
             for (int k = 0; k < K; ++k) p[k].a = t[k];
 #pragma unroll
             for (int d = 0; d < VD; ++d) {
-                vload<float, K>(m.b + (size_t)d * g.np + first, t);
+                if (d < nvel) {
+                    vload<float, K>(m.b + (size_t)d * g.np + first, t);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < K; ++k) t[k] = 0.0f;
+                }
 #pragma unroll
                 for (int k = 0; k < K; ++k) p[k].b[d] = t[k];
             }
@@ -147,7 +155,7 @@ template <int VD, int K> struct Group<1, VD, K> {
             }
         } else {
 #pragma unroll
-            for (int k = 0; k < K; ++k) p[k].load(m, g, min(first + k, last), with_f);
+            for (int k = 0; k < K; ++k) p[k].load(m, g, min(first + k, last), with_f, nvel);
         }
     }
 };
@@ -193,14 +201,15 @@ struct SortSmem {
 template <int PREC, int VD, int K, bool PUSH>
 __device__ __forceinline__ void sort_setup(const Geo& g, const SortSmem<PREC>& sm, const typename MarkersOf<PREC>::T& m,
                                            Group<PREC, VD, K>& grp, int base, int first, int last, bool with_f,
-                                           const double* E, const RowShift* rows_g, int* s_b, int* s_lo, int* s_nb)
+                                           const double* E, const RowShift* rows_g, int* s_b, int* s_lo, int* s_nb,
+                                           int nvel = VD)
 {
     if (PUSH) {
         stage_field<PREC>(g, E, sm.sE);
         if (PREC)
             for (int i = threadIdx.x; i <= g.nv[0]; i += blockDim.x) sm.sRow[i] = rows_g[i];
     }
-    grp.load(m, g, first, last, with_f);
+    grp.load(m, g, first, last, with_f, nvel);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         if (first + k == base) s_b[0] = grp.p[k].bucket(g);
@@ -258,7 +267,9 @@ __global__ __launch_bounds__(kSortThreads) void k_count(Geo g, typename MarkersO
     const int first = base + threadIdx.x * K;
     if (threadIdx.x == 0) s_flags = 0;
     Group<PREC, VD, K> grp;
-    sort_setup<PREC, VD, K, PUSH>(g, sm, m, grp, base, first, last, false, E, rows_g, s_b, &s_lo, &s_nb);
+    // FP32 form: the bucket comes from the cell index, the push needs b[0] only
+    sort_setup<PREC, VD, K, PUSH>(g, sm, m, grp, base, first, last, false, E, rows_g, s_b, &s_lo, &s_nb,
+                                  PREC ? 1 : VD);
     const int lo = s_lo, nbw = s_nb;
     int fl = 0;
     int bkt[K];

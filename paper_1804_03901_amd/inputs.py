@@ -177,6 +177,35 @@ def markers(w: Workload, row_begin: int = 0, row_end: int | None = None):
     return x, v, f
 
 
+def markers_threaded(w: Workload, threads: int | None = None, block_rows: int | None = None):
+    """Same arrays as ``markers(w)``, drawn by a pool of threads over blocks of
+    velocity rows (numpy releases the interpreter lock inside its kernels), for
+    the large configurations."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    nrows = int(np.prod(w.nv[: w.vdim]))
+    per_row = w.nx * w.ppc
+    n = nrows * per_row
+    threads = threads or min(16, os.cpu_count() or 1)
+    if block_rows is None:
+        block_rows = max(1, min(nrows, (1 << 21) // max(per_row, 1)))
+    x = np.empty(n)
+    v = np.empty((w.vdim, n))
+    f = np.empty(n)
+
+    def work(r0):
+        r1 = min(nrows, r0 + block_rows)
+        xs, vs, fs = markers(w, r0, r1)
+        a, b = r0 * per_row, r1 * per_row
+        x[a:b] = xs
+        v[:, a:b] = vs
+        f[a:b] = fs
+
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(work, range(0, nrows, block_rows)))
+    return x, v, f
+
+
 # ---------------------------------------------------------------------------
 # Workloads.  L, dt and the perturbation of the larger cases are not fixed by
 # any printed source; the choices below (L = 20*pi so that k_m = 0.1 m, dt =
@@ -205,7 +234,7 @@ def bump_on_tail(nx: int = 1024, nv: int = 1024, ppc: int = 16, seed: int = 3901
         weights=weights)
 
 
-def two_stream_3v(nx: int = 512, nv: int = 64, ppc: int = 2, seed: int = 3,
+def two_stream_3v(nx: int = 512, nv: int = 64, ppc: int = 4, seed: int = 3,
                   steps: int = 100) -> Workload:
     """Two counter-drifting Maxwellians (+-3 along x), isotropic in vy and vz."""
     return Workload(

@@ -32,7 +32,7 @@ def _cfg(**kw):
     w = inputs.landau_small()
     c = avl.make_config(w)
     for k, v in kw.items():
-        if k in ("nv", "vmin", "vmax"):
+        if k in ("nv", "vmin", "vmax", "tune"):
             arr = getattr(c, k)
             for i, x in enumerate(v):
                 arr[i] = x
@@ -52,6 +52,7 @@ def test_workspace_bytes_valid_config():
     dict(nx=48), dict(nx=4), dict(nx=8192), dict(vdim=2), dict(precision=7), dict(first_kick=2),
     dict(options=2), dict(options=1), dict(L=0.0), dict(L=float("nan")), dict(dt=-0.1), dict(c_p=0.0), dict(m=0.0),
     dict(nv=(1, 1, 1)), dict(vmin=(6.0, 0, 0)), dict(n_markers=-1), dict(n_markers=2 ** 31),
+    dict(tune=(-1, 0, 0, 0)), dict(tune=(300, 0, 0, 0)), dict(tune=(0, 1, 0, 0)), dict(tune=(0, 0, 0, 1)),
 ])
 def test_invalid_configs_rejected_on_host(bad):
     assert avl.avl_workspace_bytes(_cfg(**bad)) == 0
@@ -102,3 +103,8 @@ def test_three_v_rejects_kahan_option():
     h = ctypes.c_void_p()
     rc = lib.avl_init(ctypes.byref(c), ctypes.c_void_p(256), 1 << 30, None, None, None, None, ctypes.byref(h))
     assert rc == -6 and not h.value
+
+
+def test_tuning_knobs_accepted():
+    for t in [(0, 0, 0, 0), (4, 0, 0, 0), (256, 0, 0, 0)]:
+        assert avl.avl_workspace_bytes(_cfg(tune=t)) > 0

@@ -246,3 +246,26 @@ def test_set_markers_resume():
     Ea, rho_a = a.field()
     Eb, _ = b.field()
     assert e_err(t2n(Eb), t2n(Ea), t2n(rho_a), w) <= TOL64
+
+
+@pytest.mark.parametrize("precision", [avl.AVL_FP64, avl.AVL_FP32])
+def test_full_size_bump_on_tail_step(precision):
+    """The benchmark workload at full size (1024 x 1024 cells, 16 markers per
+    cell, 16.8M markers), stepped as a replayed graph as the benchmark does:
+    one step from the exported state against the oracle (FP64 path 1e-12,
+    FP32 form 1e-5 on f and 1e-6 on rho and E)."""
+    w = inputs.bump_on_tail()
+    sim, _ = sim_for(w, precision=precision)
+    tol_f, tol_r = (TOL64, TOL64) if precision == avl.AVL_FP64 else (1e-5, 1e-6)
+    sim.step(2, graph=True, diag=False)
+    x, v, f = (t2n(a) for a in sim.markers())
+    E = t2n(sim.field()[0])
+    xo, vo, fo, Do, rho_o, E_o, _ = _one_step_oracle(w, x, v.reshape(1, -1), f, E)
+    sim.step(1, graph=True, diag=False)
+    fg, Dg = sim.reconstruct(want_D=True)
+    E_g, rho_g = sim.field()
+    sim.check()
+    assert nrel(t2n(fg), fo) <= tol_f
+    assert nrel(t2n(Dg), Do) <= tol_r
+    assert nrel(t2n(rho_g), rho_o) <= tol_r
+    assert e_err(t2n(E_g), E_o, rho_o, w) <= tol_r
