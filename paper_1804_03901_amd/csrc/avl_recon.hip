@@ -128,6 +128,25 @@ template <> struct Src<0> {           // x, v (first component), f
         r.f = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rf, byte_off, soff, 0));
         return r;
     }
+    // V consecutive markers as one 16-byte load per array
+    static constexpr int V = 2;
+    struct Vec { Raw r[V]; };
+    __device__ Vec loadv(int byte_off, int soff) const {
+        const auto x = __builtin_amdgcn_raw_buffer_load_b128(rx, byte_off, soff, 0);
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rv, byte_off, soff, 0);
+        const auto f = __builtin_amdgcn_raw_buffer_load_b128(rf, byte_off, soff, 0);
+        const unsigned x0 = x[0], x1 = x[1], x2 = x[2], x3 = x[3];
+        const unsigned v0 = v[0], v1 = v[1], v2 = v[2], v3 = v[3];
+        const unsigned f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3];
+        Vec o;
+        o.r[0].x = __hiloint2double((int)x1, (int)x0);
+        o.r[1].x = __hiloint2double((int)x3, (int)x2);
+        o.r[0].v = __hiloint2double((int)v1, (int)v0);
+        o.r[1].v = __hiloint2double((int)v3, (int)v2);
+        o.r[0].f = __hiloint2double((int)f1, (int)f0);
+        o.r[1].f = __hiloint2double((int)f3, (int)f2);
+        return o;
+    }
 };
 template <> struct Src<1> {           // a, b (first component), f
     __amdgpu_buffer_rsrc_t ra, rb, rf;
@@ -144,6 +163,25 @@ template <> struct Src<1> {           // a, b (first component), f
         r.b = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, byte_off, soff, 0));
         r.f = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rf, byte_off, soff, 0));
         return r;
+    }
+    // V consecutive markers as one 16-byte load per array
+    static constexpr int V = 4;
+    struct Vec { Raw r[V]; };
+    __device__ Vec loadv(int byte_off, int soff) const {
+        const auto a = __builtin_amdgcn_raw_buffer_load_b128(ra, byte_off, soff, 0);
+        const auto b = __builtin_amdgcn_raw_buffer_load_b128(rb, byte_off, soff, 0);
+        const auto f = __builtin_amdgcn_raw_buffer_load_b128(rf, byte_off, soff, 0);
+        Vec o;
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+            // elements taken as values first (a bit cast of a vector element
+            // subscript reads element 0)
+            const unsigned ua = a[q], ub = b[q], uf = f[q];
+            o.r[q].a = __uint_as_float(ua);
+            o.r[q].b = __uint_as_float(ub);
+            o.r[q].f = __uint_as_float(uf);
+        }
+        return o;
     }
 };
 
@@ -231,26 +269,36 @@ __device__ __forceinline__ Seg make_seg(int beg, int end, int first_lane, int la
 }
 
 // Issue the loads of one row segment into registers: KU markers per lane of
-// the main range and the lane's marker of the wrapped run.  The loads carry
-// no branches: each goes through a descriptor bounded to its range.
+// the main range, V consecutive markers per 16-byte load (lane l takes
+// markers u*64*V + l*V + q), and the lane's marker of the wrapped run.  The
+// loads carry no branches: each goes through a descriptor bounded to its
+// range (rounded up to whole vectors; the few markers read past a segment lie
+// inside the marker buffer and are never staged), and a segment that does
+// not fit is given an empty range, so all its loads return zero.
 template <int PREC>
 __device__ __forceinline__ void prefetch(const typename RT<PREC>::M& m, const Seg& s, int lane,
-                                         typename Src<PREC>::Raw* r, typename Src<PREC>::Raw& w)
+                                         typename Src<PREC>::Vec* r, typename Src<PREC>::Raw& w)
 {
     constexpr int KU = RT<PREC>::KU;
+    constexpr int V = Src<PREC>::V;
     constexpr int esz = sizeof(typename RT<PREC>::T);
-    if (!s.fits(kWave * KU)) return;   // summed from global memory instead
+    const bool fit = s.fits(kWave * KU);
+    const int lo = __builtin_amdgcn_readfirstlane(s.lo);
+    const int nm = __builtin_amdgcn_readfirstlane(fit ? (s.nmain + V - 1) / V * V : 0);
     Src<PREC> src;
-    src.init(m, __builtin_amdgcn_readfirstlane(s.lo), __builtin_amdgcn_readfirstlane(s.nmain));
-    const int off = lane * esz;
+    src.init(m, lo, nm);
+    const int off = lane * V * esz;
 #pragma unroll
-    for (int k = 0; k < KU; ++k) r[k] = src.load(off, k * kWave * esz);
-    if (s.wlen) {
-        Src<PREC> ws;
-        ws.init(m, __builtin_amdgcn_readfirstlane(s.wbeg), __builtin_amdgcn_readfirstlane(s.wlen));
-        w = ws.load(off, 0);
-    }
+    for (int u = 0; u < KU / V; ++u) r[u] = src.loadv(off, u * kWave * V * esz);
+    Src<PREC> ws;
+    ws.init(m, __builtin_amdgcn_readfirstlane(s.wbeg), __builtin_amdgcn_readfirstlane(fit ? s.wlen : 0));
+    w = ws.load(lane * esz, 0);
 }
+
+// Register prefetch depth: rows of markers in flight per wave while one row
+// is summed.  The FP32 form holds two rows ahead (its rows take 60 registers);
+// the FP64 form one.
+template <int PREC> constexpr int recon_depth() { return PREC ? 2 : 1; }
 
 template <int PREC, bool KAHAN>
 __global__ __launch_bounds__(kWave) void k_recon_1v(Geo g, typename RT<PREC>::M m, const int* __restrict__ offsets,
@@ -260,8 +308,12 @@ __global__ __launch_bounds__(kWave) void k_recon_1v(Geo g, typename RT<PREC>::M 
 {
     using T = typename RT<PREC>::T;
     using A = typename std::conditional<KAHAN, Kahan<float>, Plain>::type;
+    using Raw = typename Src<PREC>::Raw;
+    using Vec = typename Src<PREC>::Vec;
+    constexpr int V = Src<PREC>::V;
     constexpr int KU = RT<PREC>::KU;
     constexpr int MAIN = kWave * KU;
+    constexpr int DEPTH = recon_depth<PREC>();
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x;
     // XCD-aware dealing: blocks go round-robin over the 8 XCDs; give each XCD
@@ -284,62 +336,83 @@ __global__ __launch_bounds__(kWave) void k_recon_1v(Geo g, typename RT<PREC>::M 
     const int last_lane = last_col - (strip * kReconCols - 1);
     const int j_begin = chunk * g.rc;
     const int j_end = min(j_begin + g.rc, g.nv[0]);
+    // the chunk walks dual rows j_begin-1 .. j_end-1 (row k of the walk is
+    // dual row j_begin-1+k)
+    const int nrows = j_end - j_begin + 1;
 
-    auto row_offsets = [&](int jd, int& beg, int& end) {
-        beg = 0;
-        end = 0;
-        if (run_ok && jd < j_end) {
-            const int bk = (jd + 1) * nx + colw;
-            beg = offsets[bk];
-            end = offsets[bk + 1];
-        }
+    // run bounds through a bounded descriptor: an invalid lane or row reads
+    // past the end and gets (0, 0), with no branch
+    const __amdgpu_buffer_rsrc_t roff = rsrc(offsets, sizeof(int) * ((size_t)g.nb + 2));
+    auto row_offsets = [&](int k, int& beg, int& end) {
+        const bool ok = run_ok && k < nrows;
+        const int bk = ok ? (j_begin + k) * nx + colw : g.nb + 2;
+        const auto t = __builtin_amdgcn_raw_buffer_load_b64(roff, bk * (int)sizeof(int), 0, 0);
+        const unsigned t0 = t[0], t1 = t[1];
+        beg = (int)t0;
+        end = (int)t1;
     };
 
-    typename Src<PREC>::Raw regs[KU], wreg;
-    int beg, end, nbeg, nend;
-    row_offsets(j_begin - 1, beg, end);
-    Seg seg = make_seg(beg, end, first_lane, last_lane, wrapped);
-    prefetch<PREC>(m, seg, lane, regs, wreg);
-    row_offsets(j_begin, nbeg, nend);
+    // Pipeline state: the lane's run bounds and the segment of the current
+    // row (k) and of the rows already in flight, and the run bounds of the
+    // row whose loads are issued next.
+    Vec regs[DEPTH][KU / V];
+    Raw wreg[DEPTH];
+    int rb[DEPTH + 2], re[DEPTH + 2];
+    Seg sg[DEPTH + 1];
+#pragma unroll
+    for (int q = 0; q < DEPTH + 1; ++q) row_offsets(q, rb[q], re[q]);
+#pragma unroll
+    for (int q = 0; q < DEPTH; ++q) {
+        sg[q] = make_seg(rb[q], re[q], first_lane, last_lane, wrapped);
+        prefetch<PREC>(m, sg[q], lane, regs[q], wreg[q]);
+    }
 
     double upN = 0.0, upD = 0.0;
     double rp = 0.0;
 
-    for (int jd = j_begin - 1; jd < j_end; ++jd) {
+    // one row of the walk; its markers are in regs[buf]
+    auto row = [&](int k, Vec* R, Raw& W) {
+        const int jd = j_begin - 1 + k;
+        const Seg seg = sg[0];
+        const int beg = rb[0], end = re[0];
         const bool staged = seg.fits(MAIN);
         if (staged) {
 #pragma unroll
-            for (int k = 0; k < KU; ++k) {
-                const int p = lane + k * kWave;
-                if (p < seg.nmain) lds.put(g, p, regs[k]);
-            }
-            if (lane < seg.wlen) lds.put(g, seg.nmain + lane, wreg);
+            for (int u = 0; u < KU / V; ++u)
+#pragma unroll
+                for (int q = 0; q < V; ++q) {
+                    const int p = u * kWave * V + lane * V + q;
+                    if (p < seg.nmain) lds.put(g, p, R[u].r[q]);
+                }
+            if (lane < seg.wlen) lds.put(g, seg.nmain + lane, W);
         }
         wave_sync_lds();
         const int p0 = staged ? ((wrapped && lane == 0) ? seg.nmain : beg - seg.lo) : beg;
         const int len = end - beg;
-        // start the next row's loads before summing this one
-        Seg nseg = make_seg(nbeg, nend, first_lane, last_lane, wrapped);
-        if (jd + 1 < j_end) prefetch<PREC>(m, nseg, lane, regs, wreg);
-        int nnbeg, nnend;
-        row_offsets(jd + 2, nnbeg, nnend);
+        // fetch the run bounds of row k+DEPTH+1, then refill the buffer just
+        // staged with row k+DEPTH (an empty range past the last row).  The
+        // bounds load goes first: loads complete in issue order, so waiting
+        // for it later must not also wait for this prefetch.
+        row_offsets(k + DEPTH + 1, rb[DEPTH + 1], re[DEPTH + 1]);
+        sg[DEPTH] = make_seg(rb[DEPTH], re[DEPTH], first_lane, last_lane, wrapped);
+        prefetch<PREC>(m, sg[DEPTH], lane, R, W);
 
         // Two separate loops: a single loop with a per-iteration choice makes
         // the compiler fall back to generic (flat) loads, whose waits would also
-        // stall on the prefetch of the next row.
+        // stall on the prefetch of the next rows.
         Moments<A> M;
         M.zero();
         if (staged) {
-            for (int k = 0; k < len; ++k) {
+            for (int u = 0; u < len; ++u) {
                 T a, b, f;
-                lds.get(p0 + k, a, b, f);
+                lds.get(p0 + u, a, b, f);
                 if constexpr (KAHAN) M.add(a, b, f);
                 else M.add((double)a, (double)b, (double)f);
             }
         } else {
-            for (int k = 0; k < len; ++k) {
+            for (int u = 0; u < len; ++u) {
                 T a, b, f;
-                load_global<PREC>(g, m, p0 + k, a, b, f);
+                load_global<PREC>(g, m, p0 + u, a, b, f);
                 if constexpr (KAHAN) M.add(a, b, f);
                 else M.add((double)a, (double)b, (double)f);
             }
@@ -354,7 +427,8 @@ __global__ __launch_bounds__(kWave) void k_recon_1v(Geo g, typename RT<PREC>::M 
         const double n11l = __shfl_up(c.n11, 1, kWave);
         const double d11l = __shfl_up(c.d11, 1, kWave);
 
-        if (jd >= j_begin && tgt_ok) {
+        // target row jd = ((up01 + up11 of dual row jd-1) + down00) + down10
+        if (k > 0 && tgt_ok) {
             const double Nv = (upN + c.n00) + n10l;
             const double Dv = (upD + c.d00) + d10l;
             const double fv = Dv > 0.0 ? Nv / Dv : 0.0;
@@ -366,11 +440,19 @@ __global__ __launch_bounds__(kWave) void k_recon_1v(Geo g, typename RT<PREC>::M 
         upN = c.n01 + n11l;
         upD = c.d01 + d11l;
 
-        beg = nbeg;
-        end = nend;
-        nbeg = nnbeg;
-        nend = nnend;
-        seg = nseg;
+#pragma unroll
+        for (int q = 0; q < DEPTH; ++q) sg[q] = sg[q + 1];
+#pragma unroll
+        for (int q = 0; q < DEPTH + 1; ++q) {
+            rb[q] = rb[q + 1];
+            re[q] = re[q + 1];
+        }
+    };
+
+    for (int k = 0; k < nrows; k += DEPTH) {
+#pragma unroll
+        for (int q = 0; q < DEPTH; ++q)
+            if (k + q < nrows) row(k + q, regs[q], wreg[q]);
     }
     if (tgt_ok) rho_part[(size_t)chunk * nx + col] = rp;
 }
