@@ -60,6 +60,19 @@ int ilog2(int v)
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
+// Compute units of the current device (256 on MI355X, assumed when no device
+// is visible, so that sizes computed without a GPU match).
+int device_cus()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
+        (void)hipGetLastError();
+        return 256;
+    }
+    return cus;
+}
+
 // Validate a configuration and derive the kernel constants.
 int make_geo(const avl_config* c, Geo* g)
 {
@@ -127,11 +140,13 @@ int make_geo(const avl_config* c, Geo* g)
     }
     // reconstruction decomposition
     if (c->vdim == 1) {
-        // about 2048 wave tasks (each a 63-column strip by rc velocity rows)
-        // so that every CU runs several; tune[0] overrides rc
+        // wave tasks of one 63-column strip by rc velocity rows: the fewest
+        // rows per task such that all tasks are resident at once (two waves
+        // per SIMD, the reconstruction's register budget), so there is no
+        // partial second round; tune[0] overrides rc
         g->nstrip = (c->nx + kReconCols - 1) / kReconCols;
-        int want_chunks = std::max(1, 2048 / g->nstrip);
-        int rc = std::max(2, std::min(32, c->nv[0] / want_chunks));
+        const int64_t slots = 8 * (int64_t)device_cus();
+        int rc = (int)std::max<int64_t>(2, std::min<int64_t>(32, ((int64_t)c->nv[0] * g->nstrip + slots - 1) / slots));
         if (c->tune[0]) rc = c->tune[0];
         g->rc = rc;
         g->nchunk = (c->nv[0] + rc - 1) / rc;

@@ -11,7 +11,8 @@
 // every vx row it walks the four dual planes in a fixed order, staging each
 // row segment through LDS (the next segment is prefetched into registers while
 // the current one is summed), and sums per run eight moments of (a, bx)
-// weighted by f w and by w.  Sums are FP64 and in a fixed order: no atomics.
+// weighted by f w and by w (product-sums as fused multiply-adds).  Sums are
+// FP64 and in a fixed order: no atomics.
 //
 // Neighbouring target planes read the same dual planes; tasks are dealt so
 // that each XCD takes consecutive target planes (vy fastest), which keeps the
@@ -194,13 +195,13 @@ __global__ __launch_bounds__(kWave) void k_recon_3v(Geo g, typename R3<PREC>::M 
                 const St3 e = st[p0 + k];
                 const double ab = e.a * e.b;
                 Sw += e.w;
-                Saw += e.a * e.w;
-                Sbw += e.b * e.w;
-                Sabw += ab * e.w;
+                Saw = __fma_rn(e.a, e.w, Saw);
+                Sbw = __fma_rn(e.b, e.w, Sbw);
+                Sabw = __fma_rn(ab, e.w, Sabw);
                 Sf += e.fw;
-                Saf += e.a * e.fw;
-                Sbf += e.b * e.fw;
-                Sabf += ab * e.fw;
+                Saf = __fma_rn(e.a, e.fw, Saf);
+                Sbf = __fma_rn(e.b, e.fw, Sbf);
+                Sabf = __fma_rn(ab, e.fw, Sabf);
             }
         } else {
             for (int k = 0; k < len; ++k) {
@@ -209,13 +210,13 @@ __global__ __launch_bounds__(kWave) void k_recon_3v(Geo g, typename R3<PREC>::M 
                 const St3 e = r.stage(g, cy, cz);
                 const double ab = e.a * e.b;
                 Sw += e.w;
-                Saw += e.a * e.w;
-                Sbw += e.b * e.w;
-                Sabw += ab * e.w;
+                Saw = __fma_rn(e.a, e.w, Saw);
+                Sbw = __fma_rn(e.b, e.w, Sbw);
+                Sabw = __fma_rn(ab, e.w, Sabw);
                 Sf += e.fw;
-                Saf += e.a * e.fw;
-                Sbf += e.b * e.fw;
-                Sabf += ab * e.fw;
+                Saf = __fma_rn(e.a, e.fw, Saf);
+                Sbf = __fma_rn(e.b, e.fw, Sbf);
+                Sabf = __fma_rn(ab, e.fw, Sabf);
             }
         }
         wave_sync_lds3();
