@@ -13,6 +13,9 @@ events on the library's stream around every launch in a second timed region
 of direct launches.
 ``cpu_baseline`` times the CPU oracle on a bounded sample of the same workload.
 
+``batched`` reports the parameter scan (64 uneven 1D-1V instances, FP32 form)
+stepped as batched launches, and its throughput over the plain FP64 path.
+
 ``--workload two_stream_3v`` measures the 1D-3V two-stream case instead (512 x
 64^3 cells, 4 markers per cell, 536,870,912 markers; FP32 form by default, no
 CPU baseline).
@@ -130,6 +133,32 @@ def measured_traffic(kernel_tag):
     return rows[kernel_tag][0] + rows[kernel_tag][1]
 
 
+def run_batched(avl, inputs, steps, warmup, count):
+    """The parameter-scan batch (uneven 1D-1V bump-on-tail instances, FP32
+    form), stepped as batched launches replayed as a HIP graph."""
+    import torch
+    ws = inputs.batched_scan(count=count)
+    mk = [inputs.markers_threaded(w) for w in ws]
+    b = avl.Batch(ws, mk, precision=avl.AVL_FP32)
+    del mk
+    torch.cuda.synchronize()
+    b.step(warmup, diag=False)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(b.stream)
+    b.step(steps, diag=False)
+    t1.record(b.stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    b.check()
+    out = {"instances": len(ws), "markers": b.n_markers, "ms_per_step": ms,
+           "marker_steps_per_s": b.n_markers / (ms * 1e-3), "steps": steps, "form": "fp32",
+           "nx": sorted({w.nx for w in ws}), "nv": sorted({w.nv[0] for w in ws})}
+    b.close()
+    return out
+
+
 def cpu_baseline(inputs, w, x, v, f, steps):
     import oracle
     g = oracle.Grid.from_workload(w)
@@ -165,6 +194,8 @@ def main():
     ap.add_argument("--workload", default="bump_on_tail", choices=["bump_on_tail", "two_stream_3v"],
                     help="two_stream_3v: the 1D-3V two-stream case, 512 x 64^3 cells, 4 markers per cell")
     ap.add_argument("--no-probe", action="store_true")
+    ap.add_argument("--batch", type=int, default=64, help="instances of the batched parameter scan (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
@@ -226,6 +257,14 @@ def main():
     }
     if "fp32" in results and "fp64" in results:
         out["fp32_speedup_over_fp64"] = results["fp64"][1] / results["fp32"][1]
+    if args.batch and not three_v:
+        log(f"batched scan: {args.batch} instances, warmup {args.warmup}, timed {args.batch_steps}")
+        out["batched"] = run_batched(avl, inputs, args.batch_steps, args.warmup, args.batch)
+        log(f"batched scan: {out['batched']['ms_per_step']:.4f} ms/step, "
+            f"{out['batched']['marker_steps_per_s']:.3e} marker-steps/s")
+        if "fp64" in results:
+            fp64_rate = w.n_markers / (results["fp64"][1] * 1e-3)
+            out["batched"]["fp32_batched_over_fp64_plain"] = out["batched"]["marker_steps_per_s"] / fp64_rate
     if probe is not None:
         out["roofline"]["copy_probe_GBs"] = probe[0]
         out["roofline"]["frac_of_copy"] = achieved / probe[0]

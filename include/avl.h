@@ -222,6 +222,49 @@ const char* avl_strerror(int status);
 /* Release the handle (host memory only; the workspace stays the caller's). */
 int avl_destroy(avl_handle* h);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many independent 1D-1V instances (a parameter scan) stepped
+ * together.  Each step of the batch is six launches that cover every
+ * instance (count, scan, scatter, reconstruction, rho, field solve), replayed
+ * as a HIP graph; each launch holds a work list of (instance, block or task)
+ * items, so uneven instances share the GPU without one launch per instance.
+ * The method per instance is exactly the single-handle step above.
+ * ------------------------------------------------------------------------- */
+typedef struct avl_batch avl_batch;
+
+/* Device workspace for `count` instances (1 <= count <= 4096) with
+ * configurations cfgs[0..count) (0 if any is invalid, not 1D-1V, or if they
+ * differ in precision, options or first_kick). */
+size_t avl_batch_workspace_bytes(const avl_config* cfgs, int32_t count);
+
+/* Create a batch.  Instance i is initialised as by avl_init with cfgs[i] and
+ * the markers that follow instance i-1's in the concatenated device arrays x,
+ * v, f (FP64; instance i's markers are elements [o_i, o_i + n_i) with
+ * o_i = n_0 + ... + n_{i-1}, n_i = cfgs[i].n_markers).  `workspace` as for
+ * avl_init (256-byte aligned, >= avl_batch_workspace_bytes, caller-owned).
+ * Errors as avl_init; AVL_ENOTSUP for combinations the batch does not take. */
+int avl_batch_init(const avl_config* cfgs, int32_t count, void* workspace, size_t ws_bytes, void* stream,
+                   const double* x, const double* v, const double* f, avl_batch** out);
+
+/* `nsteps` steps of every instance.  diag_out (NULL or count*nsteps*2
+ * doubles, instance-major) receives each instance's per-step W and mode-1
+ * amplitude as avl_step does. */
+int avl_batch_step(avl_batch* b, int32_t nsteps, double* diag_out);
+
+/* Instance i as a handle for the per-handle calls (avl_get_field,
+ * avl_get_markers, avl_reconstruct, avl_check, ...), owned by the batch:
+ * do not destroy it.  NULL if i is out of range. */
+avl_handle* avl_batch_instance(avl_batch* b, int32_t i);
+
+/* Number of instances (-1 for NULL). */
+int avl_batch_count(const avl_batch* b);
+
+/* avl_check over every instance (the first failure is returned). */
+int avl_batch_check(avl_batch* b);
+
+/* Release the batch and its instance handles. */
+int avl_batch_destroy(avl_batch* b);
+
 #if defined(__GNUC__)
 #pragma GCC visibility pop
 #endif

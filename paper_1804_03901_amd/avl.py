@@ -54,7 +54,8 @@ _lib = None
 EXPORTS = ["avl_workspace_bytes", "avl_init", "avl_push", "avl_sort", "avl_reconstruct", "avl_moments",
            "avl_poisson", "avl_step", "avl_step_graph", "avl_get_markers", "avl_set_markers", "avl_get_field",
            "avl_step_count", "avl_check", "avl_set_stream", "avl_timing", "avl_kernel_time", "avl_kernel_bytes",
-           "avl_copy_probe", "avl_strerror", "avl_destroy"]
+           "avl_copy_probe", "avl_strerror", "avl_destroy", "avl_batch_workspace_bytes", "avl_batch_init",
+           "avl_batch_step", "avl_batch_instance", "avl_batch_count", "avl_batch_check", "avl_batch_destroy"]
 
 
 def load(path: str = LIB_PATH):
@@ -92,8 +93,18 @@ def load(path: str = LIB_PATH):
     lib.avl_strerror.argtypes = [c.c_int]
     lib.avl_strerror.restype = c.c_char_p
     lib.avl_destroy.argtypes = [vp]
+    lib.avl_batch_workspace_bytes.argtypes = [P(AvlConfig), c.c_int32]
+    lib.avl_batch_workspace_bytes.restype = c.c_size_t
+    lib.avl_batch_init.argtypes = [P(AvlConfig), c.c_int32, vp, c.c_size_t, vp, vp, vp, vp, P(vp)]
+    lib.avl_batch_step.argtypes = [vp, c.c_int32, vp]
+    lib.avl_batch_instance.argtypes = [vp, c.c_int32]
+    lib.avl_batch_instance.restype = vp
+    lib.avl_batch_count.argtypes = [vp]
+    lib.avl_batch_check.argtypes = [vp]
+    lib.avl_batch_destroy.argtypes = [vp]
     for name in EXPORTS:
-        if name not in ("avl_workspace_bytes", "avl_step_count", "avl_kernel_bytes", "avl_strerror"):
+        if name not in ("avl_workspace_bytes", "avl_step_count", "avl_kernel_bytes", "avl_strerror",
+                        "avl_batch_workspace_bytes", "avl_batch_instance"):
             getattr(lib, name).restype = c.c_int
     _lib = lib
     return lib
@@ -232,8 +243,50 @@ def avl_destroy(h):
     return _ck(load().avl_destroy(h), "avl_destroy")
 
 
+def _cfg_array(cfgs):
+    arr = (AvlConfig * len(cfgs))()
+    for i, c in enumerate(cfgs):
+        arr[i] = c
+    return arr
+
+
+def avl_batch_workspace_bytes(cfgs) -> int:
+    return int(load().avl_batch_workspace_bytes(_cfg_array(cfgs), len(cfgs)))
+
+
+def avl_batch_init(cfgs, workspace, stream, x, v, f) -> ctypes.c_void_p:
+    b = ctypes.c_void_p()
+    _ck(load().avl_batch_init(_cfg_array(cfgs), len(cfgs), _ptr(workspace),
+                              workspace.numel() * workspace.element_size(), _stream_ptr(stream), _ptr(x), _ptr(v),
+                              _ptr(f), ctypes.byref(b)), "avl_batch_init")
+    return b
+
+
+def avl_batch_step(b, nsteps: int, diag_out=None):
+    return _ck(load().avl_batch_step(b, int(nsteps), _ptr(diag_out)), "avl_batch_step")
+
+
+def avl_batch_instance(b, i: int):
+    h = load().avl_batch_instance(b, int(i))
+    if not h:
+        raise AvlError(-1, "avl_batch_instance")
+    return ctypes.c_void_p(h)
+
+
+def avl_batch_count(b) -> int:
+    return int(load().avl_batch_count(b))
+
+
+def avl_batch_check(b):
+    return load().avl_batch_check(b)
+
+
+def avl_batch_destroy(b):
+    return _ck(load().avl_batch_destroy(b), "avl_batch_destroy")
+
+
 # ---------------------------------------------------------------------------
-# Convenience wrapper
+# Convenience wrappers
 # ---------------------------------------------------------------------------
 
 class Simulation:
@@ -339,3 +392,76 @@ class Simulation:
             self.close()
         except Exception:
             pass
+
+
+class _Instance(Simulation):
+    """A batch instance seen as a Simulation (the handle belongs to the batch)."""
+
+    def __init__(self, batch: "Batch", i: int):  # noqa: D401 - no Simulation.__init__
+        self.w = batch.workloads[i]
+        self.device = batch.device
+        self.precision = batch.precision
+        self.n = self.w.n_markers
+        self.h = avl_batch_instance(batch.b, i)
+        self.stream = batch.stream
+        import torch
+        self._grid_dtype = torch.float64 if self.precision == AVL_FP64 else torch.float32
+        self._batch = batch
+
+    def close(self):
+        self.h = None
+
+
+class Batch:
+    """Independent 1D-1V instances stepped together (one set of batched launches per step)."""
+
+    def __init__(self, workloads, markers, precision: int = AVL_FP32, device: str = "cuda:0", stream=None,
+                 options: int = 0, tunes=None):
+        """``markers``: per-instance (x, v, f) arrays (FP64), concatenated here in instance order."""
+        import torch
+        self.workloads = list(workloads)
+        self.device = torch.device(device)
+        self.precision = precision
+        xs, vs, fs = zip(*markers)
+        to = lambda a: torch.as_tensor(a, dtype=torch.float64, device=self.device).reshape(-1)
+        x = torch.cat([to(a) for a in xs]).contiguous()
+        v = torch.cat([to(a) for a in vs]).contiguous()
+        f = torch.cat([to(a) for a in fs]).contiguous()
+        tunes = tunes or [None] * len(self.workloads)
+        self.cfgs = [make_config(w, precision, None, options, t) for w, t in zip(self.workloads, tunes)]
+        nbytes = avl_batch_workspace_bytes(self.cfgs)
+        if nbytes == 0:
+            raise AvlError(-6, "avl_batch_workspace_bytes")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self.workspace = self.workspace[off:off + nbytes]
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.b = avl_batch_init(self.cfgs, self.workspace, self.stream, x, v, f)
+        self.n_markers = sum(w.n_markers for w in self.workloads)
+
+    def __len__(self):
+        return len(self.workloads)
+
+    def instance(self, i: int) -> Simulation:
+        return _Instance(self, i)
+
+    def step(self, nsteps: int, diag: bool = True):
+        import torch
+        d = torch.empty(len(self) * 2 * max(nsteps, 1), dtype=torch.float64, device=self.device) if diag else None
+        avl_batch_step(self.b, nsteps, d)
+        return d[: len(self) * 2 * nsteps].reshape(len(self), nsteps, 2) if diag else None
+
+    def check(self):
+        _ck(avl_batch_check(self.b), "avl_batch_check")
+
+    def close(self):
+        if getattr(self, "b", None):
+            avl_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

@@ -35,6 +35,14 @@ hipError_t launch_to32(const Geo& g, const double* x, const double* v, const dou
 hipError_t launch_to64(const Geo& g, M32 m, double* x, double* v, double* f, hipStream_t st);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
 size_t recon3_scratch_bytes(const Geo& g);
+int sort_blocks(const Geo& g, int phase);
+size_t sort_lds(const Geo& g);
+hipError_t launch_sort_batch(int prec, const BInst* tab, const int* pre, int ninst, int blocks, size_t smem, int cur,
+                             hipStream_t st, int phase);
+hipError_t launch_recon_batch(int prec, int kahan, const BInst* tab, const int* pre, int ninst, int tasks, int cur,
+                              hipStream_t st);
+hipError_t launch_field_batch(const BInst* tab, const int* pre, int ninst, int rho_blocks, int max_nx, int write_diag,
+                              hipStream_t st);
 void set_lds_limit(int bytes);
 }  // namespace avl
 
@@ -869,6 +877,300 @@ int avl_destroy(avl_handle* h)
     for (int k = 0; k < AVL_K_COUNT; ++k)
         for (hipEvent_t e : h->ev[k]) (void)hipEventDestroy(e);
     delete h;
+    return AVL_OK;
+}
+
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batches of independent 1D-1V instances
+// ---------------------------------------------------------------------------
+
+struct avl_batch {
+    int n;
+    std::vector<avl_handle*> h;
+    hipStream_t st;
+    BInst* tab;                 // device
+    int* pre;                   // device, BPRE_KINDS x (n+1)
+    int tot[BPRE_KINDS];
+    int prec, kahan, max_nx;
+    size_t lds;
+    hipGraphExec_t gexec[2];
+    hipStream_t cap_st;
+    bool graph_ok;
+};
+
+namespace {
+
+constexpr int kMaxBatch = 4096;
+
+// Byte offsets of the instances' workspace slices and of the batch tables.
+bool batch_layout(const avl_config* cfgs, int32_t count, std::vector<size_t>* off, size_t* tab_off, size_t* pre_off,
+                  size_t* total)
+{
+    if (!cfgs || count < 1 || count > kMaxBatch) return false;
+    size_t o = 0;
+    off->assign(count, 0);
+    for (int i = 0; i < count; ++i) {
+        if (cfgs[i].vdim != 1) return false;
+        if (cfgs[i].precision != cfgs[0].precision || cfgs[i].options != cfgs[0].options ||
+            cfgs[i].first_kick != cfgs[0].first_kick)
+            return false;
+        Geo g;
+        if (make_geo(&cfgs[i], &g) != AVL_OK) return false;
+        // the batched scan takes each tile's prefix from its predecessors directly
+        if ((g.nb + 1 + kScanTile - 1) / kScanTile > 1024) return false;
+        Layout L;
+        make_layout(&cfgs[i], g, &L);
+        (*off)[i] = o;
+        o = align_up(o + L.total);
+    }
+    *tab_off = o;
+    o = align_up(o + sizeof(BInst) * (size_t)count);
+    *pre_off = o;
+    o = align_up(o + sizeof(int) * BPRE_KINDS * ((size_t)count + 1));
+    *total = o;
+    return true;
+}
+
+void drop_batch_graphs(avl_batch* b)
+{
+    for (int k = 0; k < 2; ++k)
+        if (b->gexec[k]) {
+            (void)hipGraphExecDestroy(b->gexec[k]);
+            b->gexec[k] = nullptr;
+        }
+    b->graph_ok = false;
+}
+
+// One step of every instance: six batched launches on `st`, from buffer parity cur.
+int batch_launch(avl_batch* b, int cur, hipStream_t st)
+{
+    AVL_TRY(launch_sort_batch(b->prec, b->tab, b->pre, b->n, b->tot[BPRE_COUNT], b->lds, cur, st, 0));
+    AVL_TRY(launch_sort_batch(b->prec, b->tab, b->pre, b->n, b->tot[BPRE_SCAN], b->lds, cur, st, 1));
+    AVL_TRY(launch_sort_batch(b->prec, b->tab, b->pre, b->n, b->tot[BPRE_SCATTER], b->lds, cur, st, 2));
+    AVL_TRY(launch_recon_batch(b->prec, b->kahan, b->tab, b->pre, b->n, b->tot[BPRE_RECON], 1 - cur, st));
+    AVL_TRY(launch_field_batch(b->tab, b->pre, b->n, b->tot[BPRE_RHO], b->max_nx, 1, st));
+    return AVL_OK;
+}
+
+// Host-side state of the instances after a batched step.
+void batch_advance(avl_batch* b)
+{
+    for (avl_handle* h : b->h) {
+        h->cur = 1 - h->cur;
+        h->steps += 1;
+        h->sorted = h->kicked = true;
+        h->have_f = h->have_rho = h->have_E = h->partials = true;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t avl_batch_workspace_bytes(const avl_config* cfgs, int32_t count)
+{
+    std::vector<size_t> off;
+    size_t tab_off, pre_off, total;
+    return batch_layout(cfgs, count, &off, &tab_off, &pre_off, &total) ? total : 0;
+}
+
+int avl_batch_init(const avl_config* cfgs, int32_t count, void* workspace, size_t ws_bytes, void* stream,
+                   const double* x, const double* v, const double* f, avl_batch** out)
+{
+    if (!out || !workspace) return AVL_EINVAL;
+    *out = nullptr;
+    std::vector<size_t> off;
+    size_t tab_off, pre_off, total;
+    if (!batch_layout(cfgs, count, &off, &tab_off, &pre_off, &total)) {
+        // tell unsupported shapes from invalid ones
+        for (int i = 0; cfgs && i < count && i < kMaxBatch; ++i) {
+            Geo g;
+            const int rc = make_geo(&cfgs[i], &g);
+            if (rc) return rc;
+        }
+        return (count < 1 || count > kMaxBatch || !cfgs) ? AVL_EINVAL : AVL_ENOTSUP;
+    }
+    if ((uintptr_t)workspace & 255) return AVL_EALIGN;
+    if (ws_bytes < total) return AVL_ESIZE;
+    avl_batch* b = new avl_batch();
+    b->n = count;
+    b->st = (hipStream_t)stream;
+    char* ws = (char*)workspace;
+    int64_t mo = 0;
+    for (int i = 0; i < count; ++i) {
+        avl_handle* h = nullptr;
+        Geo g;
+        make_geo(&cfgs[i], &g);
+        Layout L;
+        make_layout(&cfgs[i], g, &L);
+        const int64_t n = cfgs[i].n_markers;
+        const int rc = avl_init(&cfgs[i], ws + off[i], L.total, stream, x ? x + mo : nullptr, v ? v + mo : nullptr,
+                                f ? f + mo : nullptr, &h);
+        if (rc) {
+            for (avl_handle* q : b->h) avl_destroy(q);
+            delete b;
+            return rc;
+        }
+        b->h.push_back(h);
+        mo += n;
+    }
+    // instance table and work-item prefixes
+    std::vector<BInst> tab(count);
+    std::vector<int> pre(BPRE_KINDS * (size_t)(count + 1), 0);
+    b->prec = cfgs[0].precision;
+    b->kahan = (cfgs[0].options & AVL_OPT_KAHAN32) ? 1 : 0;
+    b->max_nx = 0;
+    b->lds = 0;
+    for (int i = 0; i < count; ++i) {
+        avl_handle* h = b->h[i];
+        const Geo& g = h->g;
+        BInst& I = tab[i];
+        std::memset(&I, 0, sizeof(BInst));
+        I.g = g;
+        for (int p = 0; p < 2; ++p) {
+            I.m64[p] = h->m64[p];
+            I.m32[p] = h->m32[p];
+        }
+        I.E = h->E;
+        I.rows = h->rows;
+        I.counts = h->counts;
+        I.offsets = h->offsets;
+        const size_t tstride = ((size_t)g.nb + 1 + kScanTile - 1) / kScanTile + 64;
+        I.tsum[0] = h->tile_sums;
+        I.tsum[1] = h->tile_sums + tstride;
+        I.fgrid = h->fgrid;
+        I.rho_part = h->rho_part;
+        I.rho_slices = h->rho_slices;
+        I.rho = h->rho;
+        I.tw = h->tw;
+        I.green = h->green;
+        I.diag = h->diag;
+        I.ctr = h->ctr;
+        I.flags = h->flags;
+        I.dtk = g.dt;
+        I.bk = g.bscale;
+        I.nslice = field_slices(g);
+        const int items[BPRE_KINDS] = {sort_blocks(g, 0), sort_blocks(g, 1), sort_blocks(g, 2), g.nstrip * g.nchunk,
+                                       ((g.nx + 63) / 64) * I.nslice};
+        for (int k = 0; k < BPRE_KINDS; ++k)
+            pre[(size_t)k * (count + 1) + i + 1] = pre[(size_t)k * (count + 1) + i] + (g.n > 0 || k == BPRE_SCAN ||
+                                                                                       k >= BPRE_RECON ? items[k] : 0);
+        b->max_nx = std::max(b->max_nx, g.nx);
+        b->lds = std::max(b->lds, sort_lds(g));
+    }
+    for (int k = 0; k < BPRE_KINDS; ++k) b->tot[k] = pre[(size_t)k * (count + 1) + count];
+    b->tab = (BInst*)(ws + tab_off);
+    b->pre = (int*)(ws + pre_off);
+    hipError_t e = hipMemcpyAsync(b->tab, tab.data(), sizeof(BInst) * count, hipMemcpyHostToDevice, b->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->pre, pre.data(), sizeof(int) * pre.size(), hipMemcpyHostToDevice, b->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->st);
+    if (e != hipSuccess) {
+        for (avl_handle* q : b->h) avl_destroy(q);
+        delete b;
+        return report(e, "batch tables", __LINE__);
+    }
+    *out = b;
+    return AVL_OK;
+}
+
+int avl_batch_step(avl_batch* b, int32_t nsteps, double* diag_out)
+{
+    if (!b) return AVL_EINVAL;
+    if (nsteps < 0) return AVL_EINVAL;
+    const int cur = b->h[0]->cur;
+    for (avl_handle* h : b->h)
+        if (!h->have_E || !h->sorted || h->cur != cur) return AVL_ESTATE;
+    std::vector<int64_t> first(b->n);
+    for (int i = 0; i < b->n; ++i) first[i] = b->h[i]->steps;
+    int32_t s = 0;
+    // a half first kick is a different launch argument: run it per instance
+    if (nsteps > 0 && kick_fraction(b->h[0]) != 1.0) {
+        for (avl_handle* h : b->h) {
+            const hipStream_t own = h->st;
+            h->st = b->st;
+            const int rc = one_step(h);
+            h->st = own;
+            if (rc) return rc;
+        }
+        s = 1;
+    }
+    if (!b->graph_ok && s < nsteps) {
+        if (!b->cap_st) AVL_TRY(hipStreamCreateWithFlags(&b->cap_st, hipStreamNonBlocking));
+        AVL_TRY(hipStreamSynchronize(b->st));
+        for (int p = 0; p < 2; ++p) {
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamBeginCapture(b->cap_st, hipStreamCaptureModeThreadLocal);
+            int rc = e == hipSuccess ? batch_launch(b, p, b->cap_st) : AVL_EDEVICE;
+            hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(b->cap_st, &graph) : e;
+            if (e != hipSuccess) return report(e, "hipStreamBeginCapture", __LINE__);
+            if (e2 != hipSuccess) return report(e2, "hipStreamEndCapture", __LINE__);
+            if (rc) return rc;
+            e = hipGraphInstantiate(&b->gexec[p], graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                drop_batch_graphs(b);
+                return report(e, "hipGraphInstantiate", __LINE__);
+            }
+        }
+        b->graph_ok = true;
+    }
+    for (; s < nsteps; ++s) {
+        AVL_TRY(hipGraphLaunch(b->gexec[b->h[0]->cur], b->st));
+        batch_advance(b);
+        if (diag_out && ((s + 1) % kDiagCap == 0))
+            for (int i = 0; i < b->n; ++i) {
+                avl_handle* h = b->h[i];
+                const hipStream_t own = h->st;
+                h->st = b->st;
+                const int rc = copy_diag(h, first[i] + s + 1 - kDiagCap, kDiagCap,
+                                         diag_out + 2 * ((size_t)i * nsteps + s + 1 - kDiagCap));
+                h->st = own;
+                if (rc) return rc;
+            }
+    }
+    if (diag_out) {
+        const int32_t tail = nsteps % kDiagCap;
+        for (int i = 0; tail && i < b->n; ++i) {
+            avl_handle* h = b->h[i];
+            const hipStream_t own = h->st;
+            h->st = b->st;
+            const int rc = copy_diag(h, first[i] + nsteps - tail, tail, diag_out + 2 * ((size_t)i * nsteps + nsteps - tail));
+            h->st = own;
+            if (rc) return rc;
+        }
+    }
+    return AVL_OK;
+}
+
+avl_handle* avl_batch_instance(avl_batch* b, int32_t i)
+{
+    if (!b || i < 0 || i >= b->n) return nullptr;
+    return b->h[i];
+}
+
+int avl_batch_count(const avl_batch* b) { return b ? b->n : -1; }
+
+int avl_batch_check(avl_batch* b)
+{
+    if (!b) return AVL_EINVAL;
+    AVL_TRY(hipStreamSynchronize(b->st));
+    for (avl_handle* h : b->h) {
+        const int rc = avl_check(h);
+        if (rc) return rc;
+    }
+    return AVL_OK;
+}
+
+int avl_batch_destroy(avl_batch* b)
+{
+    if (!b) return AVL_EINVAL;
+    drop_batch_graphs(b);
+    if (b->cap_st) (void)hipStreamDestroy(b->cap_st);
+    for (avl_handle* h : b->h) avl_destroy(h);
+    delete b;
     return AVL_OK;
 }
 

@@ -79,6 +79,47 @@ struct RowShift {
     float frac;
 };
 
+// One 1D-1V instance of a batch, as the batched kernels see it: its geometry
+// and the buffers of its own workspace slice (the same layout a single handle
+// uses).  Markers alternate between two buffers; the parity selects them.
+struct BInst {
+    Geo g;
+    M64 m64[2];
+    M32 m32[2];
+    double* E;                 // the field (read by the push, written by the solve)
+    const RowShift* rows;
+    int* counts;
+    int* offsets;
+    int* tsum[2];              // per-scan-tile totals, by buffer parity
+    void* fgrid;
+    double* rho_part;
+    double* rho_slices;
+    double* rho;
+    const double2* tw;
+    const double* green;
+    double* diag;
+    long long* ctr;
+    int* flags;
+    double dtk;                // full-step kick
+    float bk;
+    int nslice;                // chunk slices of the rho reduction
+};
+
+// Work-item prefixes of a batch: instance i owns items [pre[i], pre[i+1]) of
+// a batched launch.  Returns the instance of item b (pre has ninst+1 entries).
+__device__ __forceinline__ int find_inst(const int* __restrict__ pre, int ninst, int b)
+{
+    int lo = 0, hi = ninst - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+enum : int { BPRE_COUNT = 0, BPRE_SCAN = 1, BPRE_SCATTER = 2, BPRE_RECON = 3, BPRE_RHO = 4, BPRE_KINDS = 5 };
+
 // Dynamic LDS a block may opt into on the current device (set at load time).
 int lds_limit();
 

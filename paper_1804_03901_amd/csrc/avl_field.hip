@@ -104,13 +104,13 @@ __device__ void fft_forward(double2* z, const double2* stw, int lgN)
 // Charge density, part 1: block (column group, slice) sums the chunk partials
 // of its slice for 64 x cells (16 groups of chunks per column, combined in a
 // fixed order) into rho_slices[slice][i].
-__global__ __launch_bounds__(kFT) void k_rho(Geo g, const double* __restrict__ rho_part,
-                                             double* __restrict__ rho_slices, int nslice)
+__device__ __forceinline__ void rho_block(const Geo& g, const double* __restrict__ rho_part,
+                                          double* __restrict__ rho_slices, int nslice, int blk)
 {
     __shared__ double colsum[kFT];
     const int nx = g.nx, tid = threadIdx.x;
     const int ncg = (nx + 63) >> 6;
-    const int cg = blockIdx.x % ncg, sl = blockIdx.x / ncg;
+    const int cg = blk % ncg, sl = blk / ncg;
     const int c = tid & 63, grp = tid >> 6;
     const int i = cg * 64 + c;
     const int per = (g.nchunk + nslice - 1) / nslice;
@@ -138,16 +138,22 @@ __global__ __launch_bounds__(kFT) void k_rho(Geo g, const double* __restrict__ r
     }
 }
 
+__global__ __launch_bounds__(kFT) void k_rho(Geo g, const double* __restrict__ rho_part,
+                                             double* __restrict__ rho_slices, int nslice)
+{
+    rho_block(g, rho_part, rho_slices, nslice, blockIdx.x);
+}
+
 // Charge density, part 2, and the field solve, one block: rho_i = q prod(dv)
 // * (sum of the slices in order) or the caller's rho, then the spectral solve
 // and the diagnostics.  Every global read the block needs is issued up front
 // so that their latencies overlap.
-__global__ __launch_bounds__(kFT) void k_solve(Geo g, const double* __restrict__ rho_slices, int nslice,
-                                               const double* __restrict__ rho_in, double* __restrict__ rho,
-                                               double* __restrict__ E_out, const double2* __restrict__ tw,
-                                               const double* __restrict__ green, double* __restrict__ diag_ring,
-                                               long long* __restrict__ step_ctr, int write_diag,
-                                               double* __restrict__ W_out, int* __restrict__ flags)
+__device__ __forceinline__ void solve_block(const Geo& g, const double* __restrict__ rho_slices, int nslice,
+                                            const double* __restrict__ rho_in, double* __restrict__ rho,
+                                            double* __restrict__ E_out, const double2* __restrict__ tw,
+                                            const double* __restrict__ green, double* __restrict__ diag_ring,
+                                            long long* __restrict__ step_ctr, int write_diag,
+                                            double* __restrict__ W_out, int* __restrict__ flags)
 {
     constexpr int Q = kMaxNx / kFT;               // grid points per thread at most
     extern __shared__ __align__(16) unsigned char smem[];
@@ -242,6 +248,45 @@ __global__ __launch_bounds__(kFT) void k_solve(Geo g, const double* __restrict__
             *step_ctr = ctr + 1;
         }
     }
+}
+
+__global__ __launch_bounds__(kFT) void k_solve(Geo g, const double* __restrict__ rho_slices, int nslice,
+                                               const double* __restrict__ rho_in, double* __restrict__ rho,
+                                               double* __restrict__ E_out, const double2* __restrict__ tw,
+                                               const double* __restrict__ green, double* __restrict__ diag_ring,
+                                               long long* __restrict__ step_ctr, int write_diag,
+                                               double* __restrict__ W_out, int* __restrict__ flags)
+{
+    solve_block(g, rho_slices, nslice, rho_in, rho, E_out, tw, green, diag_ring, step_ctr, write_diag, W_out, flags);
+}
+
+// Batched charge density and field solve: rho blocks of every instance in one
+// launch, then one solve block per instance.
+__global__ __launch_bounds__(kFT) void k_rho_b(const BInst* __restrict__ tab, const int* __restrict__ pre, int ninst)
+{
+    const int* pr = pre + BPRE_RHO * (ninst + 1);
+    const int i = find_inst(pr, ninst, blockIdx.x);
+    const BInst& I = tab[i];
+    rho_block(I.g, I.rho_part, I.rho_slices, I.nslice, blockIdx.x - pr[i]);
+}
+
+__global__ __launch_bounds__(kFT) void k_solve_b(const BInst* __restrict__ tab, int write_diag)
+{
+    const BInst& I = tab[blockIdx.x];
+    solve_block(I.g, I.rho_slices, I.nslice, nullptr, I.rho, I.E, I.tw, I.green, I.diag, I.ctr, write_diag, nullptr,
+                I.flags);
+}
+
+hipError_t launch_field_batch(const BInst* tab, const int* pre, int ninst, int rho_blocks, int max_nx, int write_diag,
+                              hipStream_t st)
+{
+    const size_t smem = (sizeof(double2) + sizeof(double2) / 2) * max_nx;
+    static int granted = 0;
+    hipError_t e = ensure_lds((const void*)k_solve_b, smem, granted);
+    if (e != hipSuccess) return e;
+    if (rho_blocks > 0) hipLaunchKernelGGL(k_rho_b, dim3(rho_blocks), dim3(kFT), 0, st, tab, pre, ninst);
+    hipLaunchKernelGGL(k_solve_b, dim3(ninst), dim3(kFT), smem, st, tab, write_diag);
+    return hipGetLastError();
 }
 
 // Chunk slices of the rho reduction: at most 256 chunk partials per block.

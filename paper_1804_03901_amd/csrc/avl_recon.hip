@@ -320,10 +320,10 @@ __device__ __forceinline__ void prefetch(const typename RT<PREC>::M& m, const Se
 template <int PREC> constexpr int recon_depth() { return PREC ? 2 : 1; }
 
 template <int PREC, bool KAHAN>
-__global__ __launch_bounds__(kWave) void k_recon_1v(Geo g, typename RT<PREC>::M m, const int* __restrict__ offsets,
-                                                    typename RT<PREC>::T* __restrict__ fgrid,
-                                                    typename RT<PREC>::T* __restrict__ Dgrid,
-                                                    double* __restrict__ rho_part, int tasks_per_xcd)
+__device__ __forceinline__ void recon_task(const Geo& g, const typename RT<PREC>::M& m,
+                                           const int* __restrict__ offsets, typename RT<PREC>::T* __restrict__ fgrid,
+                                           typename RT<PREC>::T* __restrict__ Dgrid, double* __restrict__ rho_part,
+                                           int task)
 {
     using T = typename RT<PREC>::T;
     using A = typename std::conditional<KAHAN, Kahan<float>, Plain>::type;
@@ -335,10 +335,6 @@ __global__ __launch_bounds__(kWave) void k_recon_1v(Geo g, typename RT<PREC>::M 
     constexpr int DEPTH = recon_depth<PREC>();
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x;
-    // XCD-aware dealing: blocks go round-robin over the 8 XCDs; give each XCD
-    // a contiguous range of (strip-major) tasks
-    const int task = (blockIdx.x & 7) * tasks_per_xcd + (blockIdx.x >> 3);
-    if ((blockIdx.x >> 3) >= tasks_per_xcd || task >= g.nstrip * g.nchunk) return;
     Lds<PREC> lds;
     lds.init(smem);
 
@@ -474,6 +470,66 @@ __global__ __launch_bounds__(kWave) void k_recon_1v(Geo g, typename RT<PREC>::M 
             if (k + q < nrows) row(k + q, regs[q], wreg[q]);
     }
     if (tgt_ok) rho_part[(size_t)chunk * nx + col] = rp;
+}
+
+// XCD-aware dealing: blocks go round-robin over the 8 XCDs; give each XCD a
+// contiguous range of (strip-major) tasks.  Returns -1 past the last task.
+__device__ __forceinline__ int dealt_task(int tasks_per_xcd, int ntask)
+{
+    const int task = (blockIdx.x & 7) * tasks_per_xcd + (blockIdx.x >> 3);
+    return ((blockIdx.x >> 3) >= tasks_per_xcd || task >= ntask) ? -1 : task;
+}
+
+template <int PREC, bool KAHAN>
+__global__ __launch_bounds__(kWave) void k_recon_1v(Geo g, typename RT<PREC>::M m, const int* __restrict__ offsets,
+                                                    typename RT<PREC>::T* __restrict__ fgrid,
+                                                    typename RT<PREC>::T* __restrict__ Dgrid,
+                                                    double* __restrict__ rho_part, int tasks_per_xcd)
+{
+    const int task = dealt_task(tasks_per_xcd, g.nstrip * g.nchunk);
+    if (task < 0) return;
+    recon_task<PREC, KAHAN>(g, m, offsets, fgrid, Dgrid, rho_part, task);
+}
+
+// Batched reconstruction: the tasks of every instance form one list, dealt
+// over the XCDs as above; a task runs with its instance's geometry.
+template <int PREC> __device__ __forceinline__ const typename RT<PREC>::M& rmark(const BInst& I, int b);
+template <> __device__ __forceinline__ const M64& rmark<0>(const BInst& I, int b) { return I.m64[b]; }
+template <> __device__ __forceinline__ const M32& rmark<1>(const BInst& I, int b) { return I.m32[b]; }
+
+template <int PREC, bool KAHAN>
+__global__ __launch_bounds__(kWave) void k_recon_b(const BInst* __restrict__ tab, const int* __restrict__ pre,
+                                                   int ninst, int cur, int tasks_per_xcd)
+{
+    const int* pr = pre + BPRE_RECON * (ninst + 1);
+    const int task = dealt_task(tasks_per_xcd, pr[ninst]);
+    if (task < 0) return;
+    const int i = find_inst(pr, ninst, task);
+    const BInst& I = tab[i];
+    recon_task<PREC, KAHAN>(I.g, rmark<PREC>(I, cur), I.offsets, (typename RT<PREC>::T*)I.fgrid, nullptr,
+                            I.rho_part, task - pr[i]);
+}
+
+hipError_t launch_recon_batch(int prec, int kahan, const BInst* tab, const int* pre, int ninst, int tasks, int cur,
+                              hipStream_t st)
+{
+    if (tasks <= 0) return hipSuccess;
+    const int per_xcd = (tasks + 7) / 8;
+    const int blocks = per_xcd * 8;
+    const size_t smem = prec ? recon_lds<1>() : recon_lds<0>();
+    static int granted[3] = {0, 0, 0};
+    const int var = prec == 0 ? 0 : (kahan ? 2 : 1);
+    const void* fns[3] = {(const void*)k_recon_b<0, false>, (const void*)k_recon_b<1, false>,
+                          (const void*)k_recon_b<1, true>};
+    hipError_t e = ensure_lds(fns[var], smem, granted[var]);
+    if (e != hipSuccess) return e;
+    if (var == 0)
+        hipLaunchKernelGGL((k_recon_b<0, false>), dim3(blocks), dim3(kWave), smem, st, tab, pre, ninst, cur, per_xcd);
+    else if (var == 1)
+        hipLaunchKernelGGL((k_recon_b<1, false>), dim3(blocks), dim3(kWave), smem, st, tab, pre, ninst, cur, per_xcd);
+    else
+        hipLaunchKernelGGL((k_recon_b<1, true>), dim3(blocks), dim3(kWave), smem, st, tab, pre, ninst, cur, per_xcd);
+    return hipGetLastError();
 }
 
 hipError_t launch_recon(const Geo& g, void* m, const int* offsets, void* fgrid, void* Dgrid,

@@ -251,18 +251,16 @@ struct Agg {
 // count pass
 // ---------------------------------------------------------------------------
 template <int PREC, int VD, bool PUSH>
-__global__ __launch_bounds__(kSortThreads) void k_count(Geo g, typename MarkersOf<PREC>::T m,
-                                                        const double* __restrict__ E,
-                                                        const RowShift* __restrict__ rows_g,
-                                                        double dtk, float bk,
-                                                        int* __restrict__ counts, int* __restrict__ tsum,
-                                                        int* __restrict__ flags)
+__device__ __forceinline__ void count_block(const Geo& g, const typename MarkersOf<PREC>::T& m,
+                                            const double* __restrict__ E, const RowShift* __restrict__ rows_g,
+                                            double dtk, float bk, int* __restrict__ counts, int* __restrict__ tsum,
+                                            int* __restrict__ flags, int blk)
 {
     constexpr int K = kCountMPT;
     extern __shared__ __align__(16) unsigned char smem[];
     SortSmem<PREC> sm(smem, g);
     __shared__ int s_b[2], s_lo, s_nb, s_flags, s_tile[8];
-    const int base = blockIdx.x * kCountTile;
+    const int base = blk * kCountTile;
     const int last = min(base + kCountTile, g.n) - 1;
     const int first = base + threadIdx.x * K;
     if (threadIdx.x == 0) s_flags = 0;
@@ -316,6 +314,17 @@ __global__ __launch_bounds__(kSortThreads) void k_count(Geo g, typename MarkersO
     if (threadIdx.x == 0 && s_flags) atomicOr(flags, s_flags);
 }
 
+template <int PREC, int VD, bool PUSH>
+__global__ __launch_bounds__(kSortThreads) void k_count(Geo g, typename MarkersOf<PREC>::T m,
+                                                        const double* __restrict__ E,
+                                                        const RowShift* __restrict__ rows_g,
+                                                        double dtk, float bk,
+                                                        int* __restrict__ counts, int* __restrict__ tsum,
+                                                        int* __restrict__ flags)
+{
+    count_block<PREC, VD, PUSH>(g, m, E, rows_g, dtk, bk, counts, tsum, flags, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // scatter pass: src (sorted by the previous buckets) -> dst (sorted by new)
 //
@@ -325,19 +334,17 @@ __global__ __launch_bounds__(kSortThreads) void k_count(Geo g, typename MarkersO
 // instruction writes a few contiguous stretches instead of 64 scattered words.
 // ---------------------------------------------------------------------------
 template <int PREC, int VD, bool PUSH>
-__global__ __launch_bounds__(kSortThreads) void k_scatter(Geo g, typename MarkersOf<PREC>::T src,
-                                                          typename MarkersOf<PREC>::T dst,
-                                                          const double* __restrict__ E,
-                                                          const RowShift* __restrict__ rows_g,
-                                                          double dtk, float bk,
-                                                          const int* __restrict__ offsets,
-                                                          int* __restrict__ counts, int* __restrict__ flags)
+__device__ __forceinline__ void scatter_block(const Geo& g, const typename MarkersOf<PREC>::T& src,
+                                              const typename MarkersOf<PREC>::T& dst,
+                                              const double* __restrict__ E, const RowShift* __restrict__ rows_g,
+                                              double dtk, float bk, const int* __restrict__ offsets,
+                                              int* __restrict__ counts, int* __restrict__ flags, int blk)
 {
     constexpr int K = kSortMPT;
     extern __shared__ __align__(16) unsigned char smem[];
     SortSmem<PREC> sm(smem, g);
     __shared__ int s_b[2], s_lo, s_nb, s_flags;
-    const int base = blockIdx.x * kSortTile;
+    const int base = blk * kSortTile;
     const int last = min(base + kSortTile, g.n) - 1;
     if (threadIdx.x == 0) s_flags = 0;
     if (PUSH) {
@@ -418,6 +425,18 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(Geo g, typename Marker
     if (fl) atomicOr(&s_flags, fl);
     __syncthreads();
     if (threadIdx.x == 0 && s_flags) atomicOr(flags, s_flags);
+}
+
+template <int PREC, int VD, bool PUSH>
+__global__ __launch_bounds__(kSortThreads) void k_scatter(Geo g, typename MarkersOf<PREC>::T src,
+                                                          typename MarkersOf<PREC>::T dst,
+                                                          const double* __restrict__ E,
+                                                          const RowShift* __restrict__ rows_g,
+                                                          double dtk, float bk,
+                                                          const int* __restrict__ offsets,
+                                                          int* __restrict__ counts, int* __restrict__ flags)
+{
+    scatter_block<PREC, VD, PUSH>(g, src, dst, E, rows_g, dtk, bk, offsets, counts, flags, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -509,13 +528,12 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(int* __restrict__ tile_sums
 // preceding tiles' totals, or an already-scanned prefix when `scanned`) plus
 // an in-block exclusive scan of its counts, 16 per thread as 16-byte vectors.
 // Also clears the other parity's tile totals for the next count pass.
-__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int* __restrict__ counts, int nbt,
-                                                            const int* __restrict__ tsum, int scanned,
-                                                            int* __restrict__ tsum_next, int* __restrict__ offsets)
+__device__ __forceinline__ void scan_tile(const int* __restrict__ counts, int nbt, const int* __restrict__ tsum,
+                                          int scanned, int* __restrict__ tsum_next, int* __restrict__ offsets,
+                                          int tile)
 {
     __shared__ int s_w[kScanThreads / kWave + 1];
     __shared__ int s_pre;
-    const int tile = blockIdx.x;
     // tile start
     int pre;
     if (scanned) {
@@ -563,6 +581,13 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int* __restri
         for (int k = 0; k < kScanItems; ++k)
             if (base + k < nbt) offsets[base + k] = o[k];
     }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int* __restrict__ counts, int nbt,
+                                                            const int* __restrict__ tsum, int scanned,
+                                                            int* __restrict__ tsum_next, int* __restrict__ offsets)
+{
+    scan_tile(counts, nbt, tsum, scanned, tsum_next, offsets, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -627,6 +652,82 @@ hipError_t launch_sort(const Geo& g, void* src, void* dst, const double* E, cons
     if (g.prec == 0 && g.vdim == 3) return launch_sort_t<0, 3>(g, src, dst, E, rows, dtk, bk, counts, offsets, tile_sums, tile_next, flags, push, st, phase);
     if (g.prec == 1 && g.vdim == 1) return launch_sort_t<1, 1>(g, src, dst, E, rows, dtk, bk, counts, offsets, tile_sums, tile_next, flags, push, st, phase);
     return launch_sort_t<1, 3>(g, src, dst, E, rows, dtk, bk, counts, offsets, tile_sums, tile_next, flags, push, st, phase);
+}
+
+// ---------------------------------------------------------------------------
+// batched passes: one launch covers every instance of a batch (1D-1V); block b
+// belongs to the instance whose prefix range holds b and runs that
+// instance's block body with the instance's own geometry and buffers.
+// ---------------------------------------------------------------------------
+template <int PREC> __device__ __forceinline__ const typename MarkersOf<PREC>::T& bmark(const BInst& I, int b);
+template <> __device__ __forceinline__ const M64& bmark<0>(const BInst& I, int b) { return I.m64[b]; }
+template <> __device__ __forceinline__ const M32& bmark<1>(const BInst& I, int b) { return I.m32[b]; }
+
+template <int PREC>
+__global__ __launch_bounds__(kSortThreads) void k_count_b(const BInst* __restrict__ tab, const int* __restrict__ pre,
+                                                          int ninst, int cur)
+{
+    const int* pr = pre + BPRE_COUNT * (ninst + 1);
+    const int i = find_inst(pr, ninst, blockIdx.x);
+    const BInst& I = tab[i];
+    count_block<PREC, 1, true>(I.g, bmark<PREC>(I, cur), I.E, I.rows, I.dtk, I.bk, I.counts, I.tsum[cur], I.flags,
+                               blockIdx.x - pr[i]);
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_b(const BInst* __restrict__ tab, const int* __restrict__ pre,
+                                                         int ninst, int cur)
+{
+    const int* pr = pre + BPRE_SCAN * (ninst + 1);
+    const int i = find_inst(pr, ninst, blockIdx.x);
+    const BInst& I = tab[i];
+    scan_tile(I.counts, I.g.nb + 1, I.tsum[cur], 0, I.tsum[1 - cur], I.offsets, blockIdx.x - pr[i]);
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kSortThreads) void k_scatter_b(const BInst* __restrict__ tab,
+                                                            const int* __restrict__ pre, int ninst, int cur)
+{
+    const int* pr = pre + BPRE_SCATTER * (ninst + 1);
+    const int i = find_inst(pr, ninst, blockIdx.x);
+    const BInst& I = tab[i];
+    scatter_block<PREC, 1, true>(I.g, bmark<PREC>(I, cur), bmark<PREC>(I, 1 - cur), I.E, I.rows, I.dtk, I.bk,
+                                 I.offsets, I.counts, I.flags, blockIdx.x - pr[i]);
+}
+
+// Blocks of a batched pass for one instance (host side).
+int sort_blocks(const Geo& g, int phase)
+{
+    if (phase == 0) return (g.n + kCountTile - 1) / kCountTile;
+    if (phase == 1) return (g.nb + 1 + kScanTile - 1) / kScanTile;
+    return (g.n + kSortTile - 1) / kSortTile;
+}
+
+// LDS of the count and scatter blocks for one instance (host side).
+size_t sort_lds(const Geo& g) { return g.prec ? sort_smem<1>(g, true) : sort_smem<0>(g, true); }
+
+// phase 0 = count (with push), 1 = scan, 2 = scatter, over `blocks` blocks
+hipError_t launch_sort_batch(int prec, const BInst* tab, const int* pre, int ninst, int blocks, size_t smem, int cur,
+                             hipStream_t st, int phase)
+{
+    if (blocks <= 0) return hipSuccess;
+    static int granted[4] = {0, 0, 0, 0};
+    const void* fns[4] = {(const void*)k_count_b<0>, (const void*)k_count_b<1>, (const void*)k_scatter_b<0>,
+                          (const void*)k_scatter_b<1>};
+    for (int i = 0; i < 4; ++i) {
+        hipError_t e = ensure_lds(fns[i], smem, granted[i]);
+        if (e != hipSuccess) return e;
+    }
+    const dim3 gr(blocks);
+    if (phase == 0) {
+        if (prec == 0) hipLaunchKernelGGL(k_count_b<0>, gr, dim3(kSortThreads), smem, st, tab, pre, ninst, cur);
+        else hipLaunchKernelGGL(k_count_b<1>, gr, dim3(kSortThreads), smem, st, tab, pre, ninst, cur);
+    } else if (phase == 1) {
+        hipLaunchKernelGGL(k_scan_b, gr, dim3(kScanThreads), 0, st, tab, pre, ninst, cur);
+    } else {
+        if (prec == 0) hipLaunchKernelGGL(k_scatter_b<0>, gr, dim3(kSortThreads), smem, st, tab, pre, ninst, cur);
+        else hipLaunchKernelGGL(k_scatter_b<1>, gr, dim3(kSortThreads), smem, st, tab, pre, ninst, cur);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_push(const Geo& g, void* m, const double* E, const RowShift* rows, double dtk, float bk,

@@ -245,6 +245,25 @@ def two_stream_3v(nx: int = 512, nv: int = 64, ppc: int = 4, seed: int = 3,
         mode_numbers=(1,), mode_amplitude=1e-4, random_phases=False)
 
 
+def batched_scan(count: int = 64, seed: int = 4000, steps: int = 500, ppc: int = 8,
+                 nx_choices: Sequence[int] = (128, 256, 512, 1024),
+                 nv_choices: Sequence[int] = (128, 256, 512)) -> list:
+    """A parameter scan of bump-on-tail instances of uneven size: instance b
+    has nx and nv drawn uniformly from the choices, beam drift uniform in
+    [3, 6], beam density log-uniform in [1e-6, 1e-2] (four draws per instance
+    from the stream of ``seed``), and markers from seed + b."""
+    u = uniforms(seed, 0, 4 * count).reshape(count, 4)
+    out = []
+    for b in range(count):
+        nx = nx_choices[min(int(u[b, 0] * len(nx_choices)), len(nx_choices) - 1)]
+        nv = nv_choices[min(int(u[b, 1] * len(nv_choices)), len(nv_choices) - 1)]
+        drift = 3.0 + 3.0 * float(u[b, 2])
+        dens = 10.0 ** (-6.0 + 4.0 * float(u[b, 3]))
+        w = bump_on_tail(nx=nx, nv=nv, ppc=ppc, seed=seed + b, steps=steps, beam_drift=drift, beam_density=dens)
+        out.append(w.replace(name=f"scan{b}_nx{nx}_nv{nv}_drift{drift:.3f}_dens{dens:.2e}"))
+    return out
+
+
 def adjoint_case() -> Workload:
     return bump_on_tail(nx=1024, nv=512, ppc=8, seed=5, steps=500)
 

@@ -108,3 +108,35 @@ def test_three_v_rejects_kahan_option():
 def test_tuning_knobs_accepted():
     for t in [(0, 0, 0, 0), (4, 0, 0, 0), (256, 0, 0, 0)]:
         assert avl.avl_workspace_bytes(_cfg(tune=t)) > 0
+
+
+def test_batch_workspace_and_rejections():
+    ws = inputs.batched_scan(count=3, seed=5, ppc=2, nx_choices=(16, 32), nv_choices=(8, 16))
+    cfgs = [avl.make_config(w, precision=avl.AVL_FP32) for w in ws]
+    total = avl.avl_batch_workspace_bytes(cfgs)
+    assert total >= sum(avl.avl_workspace_bytes(c) for c in cfgs)
+    # precisions must agree, 1D-3V is not batched, the count must be positive
+    mixed = cfgs[:2] + [avl.make_config(ws[2], precision=avl.AVL_FP64)]
+    assert avl.avl_batch_workspace_bytes(mixed) == 0
+    three_v = cfgs[:2] + [avl.make_config(inputs.two_stream_3v(nx=16, nv=4, ppc=1), precision=avl.AVL_FP32)]
+    assert avl.avl_batch_workspace_bytes(three_v) == 0
+    lib = avl.load()
+    assert lib.avl_batch_workspace_bytes(None, 0) == 0
+    b = ctypes.c_void_p()
+    arr = avl._cfg_array(three_v)
+    rc = lib.avl_batch_init(arr, 3, ctypes.c_void_p(256), 1 << 30, None, None, None, None, ctypes.byref(b))
+    assert rc == -6 and not b.value
+    assert lib.avl_batch_step(None, 1, None) == -1
+    assert lib.avl_batch_count(None) == -1
+    assert lib.avl_batch_destroy(None) == -1
+
+
+def test_batched_scan_recipe():
+    ws = inputs.batched_scan()
+    assert len(ws) == 64
+    assert {w.nx for w in ws} <= {128, 256, 512, 1024} and {w.nv[0] for w in ws} <= {128, 256, 512}
+    for w in ws:
+        drift, dens = w.populations[1].drift[0], w.populations[1].density
+        assert 3.0 <= drift <= 6.0 and 1e-6 <= dens <= 1e-2
+        assert w.ppc == 8 and w.vmin[0] == -8.0 and w.vmax[0] == 8.0
+    assert 5e7 < sum(w.n_markers for w in ws) < 1.2e8
