@@ -137,9 +137,13 @@ def run_batched(avl, inputs, steps, warmup, count):
     """The parameter-scan batch (uneven 1D-1V bump-on-tail instances, FP32
     form), stepped as batched launches replayed as a HIP graph."""
     import torch
+    from paper_1804_03901_amd import tune
     ws = inputs.batched_scan(count=count)
     mk = [inputs.markers_threaded(w) for w in ws]
-    b = avl.Batch(ws, mk, precision=avl.AVL_FP32)
+    # rows per reconstruction task for the batch, chosen by timing candidates
+    tunes, table = tune.tune_batch(ws, mk, precision=avl.AVL_FP32, candidates=(0, 6, 12, 24), steps=5, warmup=2,
+                                   cache_path=None)
+    b = avl.Batch(ws, mk, precision=avl.AVL_FP32, tunes=tunes)
     del mk
     torch.cuda.synchronize()
     b.step(warmup, diag=False)
@@ -154,7 +158,9 @@ def run_batched(avl, inputs, steps, warmup, count):
     b.check()
     out = {"instances": len(ws), "markers": b.n_markers, "ms_per_step": ms,
            "marker_steps_per_s": b.n_markers / (ms * 1e-3), "steps": steps, "form": "fp32",
-           "nx": sorted({w.nx for w in ws}), "nv": sorted({w.nv[0] for w in ws})}
+           "nx": sorted({w.nx for w in ws}), "nv": sorted({w.nv[0] for w in ws}),
+           "tuned_recon_rows": tunes[0][avl.TUNE_RECON_ROWS],
+           "tuning_ms_per_step": {str(k): v for k, v in table.items()}}
     b.close()
     return out
 

@@ -265,6 +265,33 @@ int avl_batch_check(avl_batch* b);
 /* Release the batch and its instance handles. */
 int avl_batch_destroy(avl_batch* b);
 
+/* ---------------------------------------------------------------------------
+ * Adjoint (1D-1V, FP64 form): the gradient of the time-integrated field
+ * energy J = sum_{n=1..nsteps} sum_i (E_i^n)^2 dx dt with respect to the
+ * marker weights f_l, by the reverse of every stage of the step (gather,
+ * push, reconstruction f = N/D, moments, spectral solve; Sec. 2 and
+ * Eq. (reconstruction), Eq. (poissonk)).  Parameters of the initial
+ * distribution enter through f_l = f0(x_l, v_l), so dJ/dtheta =
+ * sum_l dJ/df_l df_l/dtheta.
+ * ------------------------------------------------------------------------- */
+
+/* Device recording workspace for an adjoint run of `nsteps` steps that keeps
+ * a checkpoint every `every` steps: the checkpoints, one segment's states and
+ * grids, and the adjoint arrays (0 if the configuration is not 1D-1V FP64 or
+ * nsteps, every < 1). */
+size_t avl_adjoint_workspace_bytes(const avl_config* cfg, int32_t nsteps, int32_t every);
+
+/* Load (x, v, f) into h as avl_set_markers does but from step 0, run nsteps
+ * steps keeping a checkpoint every `every` steps in `rec` (device, 256-byte
+ * aligned, >= avl_adjoint_workspace_bytes, caller-owned), then sweep back
+ * segment by segment, recomputing each from its checkpoint.  Writes J to
+ * J_out (1 device double) and dJ/df_l for every marker, in the order of f, to
+ * grad_f (n device doubles).  Synchronises.  Afterwards h holds a recomputed
+ * state inside the first segment (reload before further stepping).
+ * AVL_ENOTSUP for other forms; AVL_ESTATE while kernel timing is enabled. */
+int avl_adjoint(avl_handle* h, const double* x, const double* v, const double* f, int32_t nsteps, int32_t every,
+                void* rec, size_t rec_bytes, double* J_out, double* grad_f);
+
 #if defined(__GNUC__)
 #pragma GCC visibility pop
 #endif

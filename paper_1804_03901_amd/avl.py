@@ -55,7 +55,8 @@ EXPORTS = ["avl_workspace_bytes", "avl_init", "avl_push", "avl_sort", "avl_recon
            "avl_poisson", "avl_step", "avl_step_graph", "avl_get_markers", "avl_set_markers", "avl_get_field",
            "avl_step_count", "avl_check", "avl_set_stream", "avl_timing", "avl_kernel_time", "avl_kernel_bytes",
            "avl_copy_probe", "avl_strerror", "avl_destroy", "avl_batch_workspace_bytes", "avl_batch_init",
-           "avl_batch_step", "avl_batch_instance", "avl_batch_count", "avl_batch_check", "avl_batch_destroy"]
+           "avl_batch_step", "avl_batch_instance", "avl_batch_count", "avl_batch_check", "avl_batch_destroy",
+           "avl_adjoint_workspace_bytes", "avl_adjoint"]
 
 
 def load(path: str = LIB_PATH):
@@ -102,9 +103,12 @@ def load(path: str = LIB_PATH):
     lib.avl_batch_count.argtypes = [vp]
     lib.avl_batch_check.argtypes = [vp]
     lib.avl_batch_destroy.argtypes = [vp]
+    lib.avl_adjoint_workspace_bytes.argtypes = [P(AvlConfig), c.c_int32, c.c_int32]
+    lib.avl_adjoint_workspace_bytes.restype = c.c_size_t
+    lib.avl_adjoint.argtypes = [vp, vp, vp, vp, c.c_int32, c.c_int32, vp, c.c_size_t, vp, vp]
     for name in EXPORTS:
         if name not in ("avl_workspace_bytes", "avl_step_count", "avl_kernel_bytes", "avl_strerror",
-                        "avl_batch_workspace_bytes", "avl_batch_instance"):
+                        "avl_batch_workspace_bytes", "avl_batch_instance", "avl_adjoint_workspace_bytes"):
             getattr(lib, name).restype = c.c_int
     _lib = lib
     return lib
@@ -241,6 +245,15 @@ def avl_copy_probe(dst, src, nbytes: int, stream=None):
 
 def avl_destroy(h):
     return _ck(load().avl_destroy(h), "avl_destroy")
+
+
+def avl_adjoint_workspace_bytes(cfg: AvlConfig, nsteps: int, every: int) -> int:
+    return int(load().avl_adjoint_workspace_bytes(ctypes.byref(cfg), int(nsteps), int(every)))
+
+
+def avl_adjoint(h, x, v, f, nsteps: int, every: int, rec, J_out, grad_f):
+    return _ck(load().avl_adjoint(h, _ptr(x), _ptr(v), _ptr(f), int(nsteps), int(every), _ptr(rec),
+                                  rec.numel() * rec.element_size(), _ptr(J_out), _ptr(grad_f)), "avl_adjoint")
 
 
 def _cfg_array(cfgs):

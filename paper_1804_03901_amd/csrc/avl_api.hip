@@ -35,6 +35,14 @@ hipError_t launch_to32(const Geo& g, const double* x, const double* v, const dou
 hipError_t launch_to64(const Geo& g, M32 m, double* x, double* v, double* f, hipStream_t st);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
 size_t recon3_scratch_bytes(const Geo& g);
+hipError_t launch_iota(int* id, int n, hipStream_t st);
+hipError_t launch_gather_f(const int* id, const double* f_by_id, double* f, int n, hipStream_t st);
+hipError_t launch_adj_deposit(const Geo& g, const double* x, const double* v, const int* id, const double* f_by_id,
+                              const double* fg, const double* Dg, const double* Pmu, double* lam_x, double* lam_v,
+                              double* f_bar, int with_positions, hipStream_t st);
+hipError_t launch_adj_push(const Geo& g, const double* x, const int* id, const double* E, double c, double* lam_x,
+                           double* lam_v, double* mu_dep, hipStream_t st);
+hipError_t launch_adj_mu(int nx, const double* E, double w, double* mu_dep, double* mu, hipStream_t st);
 int sort_blocks(const Geo& g, int phase);
 size_t sort_lds(const Geo& g);
 hipError_t launch_sort_batch(int prec, const BInst* tab, const int* pre, int ninst, int blocks, size_t smem, int cur,
@@ -248,6 +256,7 @@ struct avl_handle {
     hipStream_t cap_st;   // capture stream (the legacy default stream cannot be captured)
     bool graph_ok;
     bool timing;
+    void* rec_D;        // adjoint runs: the step's reconstruction also writes D here
     std::vector<hipEvent_t> ev[AVL_K_COUNT];
     size_t ev_used[AVL_K_COUNT];
 };
@@ -269,6 +278,7 @@ void set_views(avl_handle* h)
             h->m64[b].x = d;
             h->m64[b].v = d + n;
             h->m64[b].f = d + n * (1 + h->g.vdim);
+            h->m64[b].id = nullptr;
         } else {
             int* c = reinterpret_cast<int*>(p);
             h->m32[b].cell = c;
@@ -438,7 +448,7 @@ int one_step(avl_handle* h)
     Timer t(h, AVL_K_STEP);
     int rc = do_sort(h, true, kick_fraction(h));
     if (rc) return rc;
-    if ((rc = do_recon(h, nullptr))) return rc;
+    if ((rc = do_recon(h, h->rec_D))) return rc;
     if ((rc = do_field(h, nullptr, true, nullptr))) return rc;
     h->steps += 1;
     return AVL_OK;
@@ -467,6 +477,8 @@ int load_markers(avl_handle* h, const double* x, const double* v, const double* 
             AVL_TRY(hipMemcpyAsync(h->m64[0].v + (size_t)d * g.np, v + (size_t)d * n, sizeof(double) * n,
                                    hipMemcpyDeviceToDevice, h->st));
         AVL_TRY(hipMemcpyAsync(h->m64[0].f, f, sizeof(double) * n, hipMemcpyDeviceToDevice, h->st));
+        // adjoint runs: identities are the positions in the caller's order
+        if (h->m64[0].id) AVL_TRY(launch_iota(h->m64[0].id, (int)n, h->st));
     } else {
         AVL_TRY(launch_to32(g, x, v, f, h->m32[0], h->flags, h->st));
     }
@@ -1172,6 +1184,226 @@ int avl_batch_destroy(avl_batch* b)
     for (avl_handle* h : b->h) avl_destroy(h);
     delete b;
     return AVL_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// adjoint runs (1D-1V, FP64 form)
+// ---------------------------------------------------------------------------
+namespace {
+
+// Recording workspace: checkpoints (marker state and field every `every`
+// steps), the states of one segment with their grids, adjoints by marker
+// identity, identity arrays for both marker buffers, small field buffers.
+struct AdjLayout {
+    size_t cp, cp_stride, seg, seg_stride, ids[2], lam_x, lam_v, f_bar, f_by_id, Pmu, mu, mu_dep, diag, total;
+    size_t st_x, st_v, st_id, st_fg, st_D, st_E;   // offsets inside one state record
+    int nseg;
+};
+
+bool adj_layout(const Geo& g, int32_t nsteps, int32_t every, AdjLayout* A)
+{
+    if (nsteps < 1 || every < 1 || g.vdim != 1 || g.prec != AVL_FP64) return false;
+    const size_t n = (size_t)g.np, G = (size_t)g.nx * g.nv[0], nx = (size_t)g.nx;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+    A->nseg = (nsteps + every - 1) / every;
+    // one state: x, v, id, f grid, D grid, E
+    size_t so = 0;
+    auto stake = [&](size_t bytes) { size_t r = so; so = align_up(so + bytes); return r; };
+    A->st_x = stake(8 * n);
+    A->st_v = stake(8 * n);
+    A->st_id = stake(4 * n);
+    A->st_fg = stake(8 * G);
+    A->st_D = stake(8 * G);
+    A->st_E = stake(8 * nx);
+    A->seg_stride = so;
+    // a checkpoint keeps the markers and the field only
+    A->cp_stride = align_up(A->st_fg) + align_up(8 * nx);
+    A->cp = take(A->cp_stride * (size_t)A->nseg);
+    A->seg = take(A->seg_stride * ((size_t)every + 1));
+    A->ids[0] = take(4 * n);
+    A->ids[1] = take(4 * n);
+    A->lam_x = take(8 * n);
+    A->lam_v = take(8 * n);
+    A->f_bar = take(8 * n);
+    A->f_by_id = take(8 * n);
+    A->Pmu = take(8 * nx);
+    A->mu = take(8 * nx);
+    A->mu_dep = take(8 * nx);
+    A->diag = take(16 * (size_t)nsteps);
+    A->total = o;
+    return true;
+}
+
+// Copy the current markers (x, v, id) and field into a state record; the f
+// grid too when `grid` is set (its D is written by the reconstruction).
+int adj_save(avl_handle* h, char* rec, const AdjLayout& A, bool grid, size_t e_off)
+{
+    const M64& m = h->m64[h->cur];
+    const size_t n = (size_t)h->g.n;
+    AVL_TRY(hipMemcpyAsync(rec + A.st_x, m.x, 8 * n, hipMemcpyDeviceToDevice, h->st));
+    AVL_TRY(hipMemcpyAsync(rec + A.st_v, m.v, 8 * n, hipMemcpyDeviceToDevice, h->st));
+    AVL_TRY(hipMemcpyAsync(rec + A.st_id, m.id, 4 * n, hipMemcpyDeviceToDevice, h->st));
+    if (grid)
+        AVL_TRY(hipMemcpyAsync(rec + A.st_fg, h->fgrid, 8 * (size_t)h->g.nx * h->g.nv[0], hipMemcpyDeviceToDevice,
+                               h->st));
+    AVL_TRY(hipMemcpyAsync(rec + e_off, h->E, 8 * (size_t)h->g.nx, hipMemcpyDeviceToDevice, h->st));
+    return AVL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t avl_adjoint_workspace_bytes(const avl_config* cfg, int32_t nsteps, int32_t every)
+{
+    Geo g;
+    if (make_geo(cfg, &g) != AVL_OK) return 0;
+    AdjLayout A;
+    return adj_layout(g, nsteps, every, &A) ? A.total : 0;
+}
+
+int avl_adjoint(avl_handle* h, const double* x, const double* v, const double* f, int32_t nsteps, int32_t every,
+                void* rec, size_t rec_bytes, double* J_out, double* grad_f)
+{
+    if (!h || !rec || !J_out || !grad_f) return AVL_EINVAL;
+    if (h->g.vdim != 1 || h->g.prec != AVL_FP64) return AVL_ENOTSUP;
+    AdjLayout A;
+    if (!adj_layout(h->g, nsteps, every, &A)) return AVL_EINVAL;
+    if ((uintptr_t)rec & 255) return AVL_EALIGN;
+    if (rec_bytes < A.total) return AVL_ESIZE;
+    if (h->timing) return AVL_ESTATE;
+    const Geo& g = h->g;
+    const int n = g.n;
+    char* R = (char*)rec;
+    double* lam_x = (double*)(R + A.lam_x);
+    double* lam_v = (double*)(R + A.lam_v);
+    double* f_bar = (double*)(R + A.f_bar);
+    double* f_by_id = (double*)(R + A.f_by_id);
+    double* Pmu = (double*)(R + A.Pmu);
+    double* mu = (double*)(R + A.mu);
+    double* mu_dep = (double*)(R + A.mu_dep);
+    double* diag = (double*)(R + A.diag);
+    auto state = [&](int q) { return R + A.seg + A.seg_stride * (size_t)q; };
+    auto ckpt = [&](int k) { return R + A.cp + A.cp_stride * (size_t)k; };
+    const size_t cp_E = align_up(A.st_fg);
+    const double dxdt2 = 2.0 * g.dx * g.dt;
+    drop_graphs(h);
+    for (int b = 0; b < 2; ++b) {
+        h->m64[b].id = (int*)(R + A.ids[b]);
+        // every slot holds a valid identity even before the first scatter fills it
+        hipError_t e = hipMemsetAsync(h->m64[b].id, 0, 4 * (size_t)g.np, h->st);
+        if (e != hipSuccess) {
+            for (int q = 0; q < 2; ++q) h->m64[q].id = nullptr;
+            return report(e, "id clear", __LINE__);
+        }
+    }
+    int rc = AVL_OK;
+    auto done = [&](int r) {
+        for (int b = 0; b < 2; ++b) h->m64[b].id = nullptr;
+        h->rec_D = nullptr;
+        return r;
+    };
+    // forward: load (identities = caller's order), checkpoint every `every` steps
+    if (n > 0) {
+        if (!x || !v || !f) return done(AVL_EINVAL);
+        hipError_t e = hipMemcpyAsync(f_by_id, f, 8 * (size_t)n, hipMemcpyDeviceToDevice, h->st);
+        if (e != hipSuccess) return done(report(e, "f copy", __LINE__));
+    }
+    if ((rc = load_markers(h, x, v, f, true))) return done(rc);
+    for (int k = 0; k < A.nseg; ++k) {
+        if ((rc = adj_save(h, ckpt(k), A, false, cp_E))) return done(rc);
+        const int s0 = k * every, s1 = std::min(nsteps, s0 + every);
+        if ((rc = avl_step(h, s1 - s0, diag + 2 * (size_t)s0))) return done(rc);
+    }
+    // J = sum_n sum_i E_i^2 dx dt = 2 c_p dt sum_n W^n
+    {
+        std::vector<double> hd(2 * (size_t)nsteps);
+        hipError_t e = hipMemcpyAsync(hd.data(), diag, 16 * (size_t)nsteps, hipMemcpyDeviceToHost, h->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+        if (e != hipSuccess) return done(report(e, "diag copy", __LINE__));
+        double J = 0.0;
+        for (int s = 0; s < nsteps; ++s) J += hd[2 * s];
+        J *= 2.0 * g.cp * g.dt;
+        e = hipMemcpyAsync(J_out, &J, sizeof(double), hipMemcpyHostToDevice, h->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+        if (e != hipSuccess) return done(report(e, "J copy", __LINE__));
+    }
+    // reverse sweep, one segment at a time from its checkpoint
+    hipError_t e = hipMemsetAsync(lam_x, 0, 8 * (size_t)g.np, h->st);
+    if (e == hipSuccess) e = hipMemsetAsync(lam_v, 0, 8 * (size_t)g.np, h->st);
+    if (e == hipSuccess) e = hipMemsetAsync(f_bar, 0, 8 * (size_t)g.np, h->st);
+    if (e == hipSuccess) e = hipMemsetAsync(mu_dep, 0, 8 * (size_t)g.nx, h->st);
+    if (e != hipSuccess) return done(report(e, "adjoint clear", __LINE__));
+    // mu^N = 2 dx dt E^N
+    if (launch_adj_mu(g.nx, h->E, dxdt2, mu_dep, mu, h->st) != hipSuccess) return done(AVL_EDEVICE);
+    const double c_full = g.qm * g.dt;
+    for (int k = A.nseg - 1; k >= 0; --k) {
+        const int s0 = k * every, s1 = std::min(nsteps, s0 + every);
+        // restore the checkpoint into the current buffer, re-sort it (run
+        // bounds for the reconstruction), rebuild f, D
+        {
+            char* C = ckpt(k);
+            M64& m = h->m64[h->cur];
+            const size_t bytes = 8 * (size_t)n;
+            e = hipMemcpyAsync(m.x, C + A.st_x, bytes, hipMemcpyDeviceToDevice, h->st);
+            if (e == hipSuccess) e = hipMemcpyAsync(m.v, C + A.st_v, bytes, hipMemcpyDeviceToDevice, h->st);
+            if (e == hipSuccess) e = hipMemcpyAsync(m.id, C + A.st_id, 4 * (size_t)n, hipMemcpyDeviceToDevice, h->st);
+            if (e == hipSuccess) e = launch_gather_f(m.id, f_by_id, m.f, n, h->st);
+            if (e == hipSuccess) e = hipMemcpyAsync(h->E, C + cp_E, 8 * (size_t)g.nx, hipMemcpyDeviceToDevice, h->st);
+            if (e != hipSuccess) return done(report(e, "checkpoint restore", __LINE__));
+            h->steps = s0;
+            h->kicked = s0 > 0;
+            h->have_E = true;
+            if ((rc = do_sort(h, false, 1.0))) return done(rc);
+            if ((rc = do_recon(h, state(0) + A.st_D))) return done(rc);
+            if ((rc = adj_save(h, state(0), A, true, A.st_E))) return done(rc);
+        }
+        for (int q = 0; q < s1 - s0; ++q) {
+            h->rec_D = state(q + 1) + A.st_D;
+            if ((rc = one_step(h))) return done(rc);
+            if ((rc = adj_save(h, state(q + 1), A, true, A.st_E))) return done(rc);
+        }
+        h->rec_D = nullptr;
+        for (int q = s1 - s0 - 1; q >= 0; --q) {
+            const int step = s0 + q;                       // reverse of step -> step+1
+            char* S1 = state(q + 1);
+            char* S0 = state(q);
+            if (launch_field(g, nullptr, mu, h->rho_slices, h->rho, Pmu, h->tw, h->green, h->diag, h->ctr, 0, nullptr,
+                             h->flags, h->st) != hipSuccess)
+                return done(AVL_EDEVICE);
+            if (launch_adj_deposit(g, (double*)(S1 + A.st_x), (double*)(S1 + A.st_v), (int*)(S1 + A.st_id), f_by_id,
+                                   (double*)(S1 + A.st_fg), (double*)(S1 + A.st_D), Pmu, lam_x, lam_v, f_bar, 1,
+                                   h->st) != hipSuccess)
+                return done(AVL_EDEVICE);
+            const double kick = (step == 0 && h->cfg.first_kick) ? 0.5 : 1.0;
+            if (launch_adj_push(g, (double*)(S0 + A.st_x), (int*)(S0 + A.st_id), (double*)(S0 + A.st_E),
+                                c_full * kick, lam_x, lam_v, mu_dep, h->st) != hipSuccess)
+                return done(AVL_EDEVICE);
+            if (launch_adj_mu(g.nx, (double*)(S0 + A.st_E), step >= 1 ? dxdt2 : 0.0, mu_dep, mu, h->st) != hipSuccess)
+                return done(AVL_EDEVICE);
+        }
+        if (k == 0) {
+            // the initial reconstruction: weights only (the loaded positions are fixed)
+            char* S0 = state(0);
+            if (launch_field(g, nullptr, mu, h->rho_slices, h->rho, Pmu, h->tw, h->green, h->diag, h->ctr, 0, nullptr,
+                             h->flags, h->st) != hipSuccess)
+                return done(AVL_EDEVICE);
+            if (launch_adj_deposit(g, (double*)(S0 + A.st_x), (double*)(S0 + A.st_v), (int*)(S0 + A.st_id), f_by_id,
+                                   (double*)(S0 + A.st_fg), (double*)(S0 + A.st_D), Pmu, lam_x, lam_v, f_bar, 0,
+                                   h->st) != hipSuccess)
+                return done(AVL_EDEVICE);
+        }
+    }
+    e = hipMemcpyAsync(grad_f, f_bar, 8 * (size_t)n, hipMemcpyDeviceToDevice, h->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+    if (e != hipSuccess) return done(report(e, "gradient copy", __LINE__));
+    // the handle now holds a recomputed state of the first segment; its
+    // field and f are current for that state
+    h->have_rho = h->partials = false;
+    return done(AVL_OK);
 }
 
 }  // extern "C"

@@ -62,6 +62,7 @@ struct M64 {             // plain FP64 marker arrays
     double* x;
     double* v;           // component d of marker l at v[d*np + l]
     double* f;
+    int* id;             // optional marker identities carried through the sort (adjoint runs), else null
 };
 
 struct M32 {             // FP32 form: dual cell index + offsets

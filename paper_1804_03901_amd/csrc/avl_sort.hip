@@ -29,17 +29,20 @@ template <int PREC, int VD> struct Pay;
 
 template <int VD> struct Pay<0, VD> {
     double x, v[VD], f;
+    int id;
     __device__ void load(const M64& m, const Geo& g, int i, bool with_f) {
         x = m.x[i];
 #pragma unroll
         for (int d = 0; d < VD; ++d) v[d] = m.v[(size_t)d * g.np + i];
         f = with_f ? m.f[i] : 0.0;
+        id = (with_f && m.id) ? m.id[i] : 0;
     }
     __device__ void store(const M64& m, const Geo& g, int i) const {
         m.x[i] = x;
 #pragma unroll
         for (int d = 0; d < VD; ++d) m.v[(size_t)d * g.np + i] = v[d];
         m.f[i] = f;
+        if (m.id) m.id[i] = id;
     }
     __device__ void push(const Geo& g, const double* sE, const RowShift*, double dtk, float, int& flags) {
         push64(g, sE, dtk, x, v[0]);

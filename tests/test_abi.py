@@ -140,3 +140,16 @@ def test_batched_scan_recipe():
         assert 3.0 <= drift <= 6.0 and 1e-6 <= dens <= 1e-2
         assert w.ppc == 8 and w.vmin[0] == -8.0 and w.vmax[0] == 8.0
     assert 5e7 < sum(w.n_markers for w in ws) < 1.2e8
+
+
+def test_adjoint_workspace_rules():
+    w = inputs.bump_on_tail(nx=64, nv=64, ppc=2)
+    c64 = avl.make_config(w, precision=avl.AVL_FP64)
+    n1 = avl.avl_adjoint_workspace_bytes(c64, 30, 10)
+    n2 = avl.avl_adjoint_workspace_bytes(c64, 30, 30)
+    assert n1 > 0 and n2 > n1          # a longer segment keeps more states
+    assert avl.avl_adjoint_workspace_bytes(c64, 0, 10) == 0
+    assert avl.avl_adjoint_workspace_bytes(c64, 10, 0) == 0
+    assert avl.avl_adjoint_workspace_bytes(avl.make_config(w, precision=avl.AVL_FP32), 30, 10) == 0
+    lib = avl.load()
+    assert lib.avl_adjoint(None, None, None, None, 1, 1, None, 0, None, None) == -1
