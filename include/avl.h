@@ -266,7 +266,7 @@ int avl_batch_check(avl_batch* b);
 int avl_batch_destroy(avl_batch* b);
 
 /* ---------------------------------------------------------------------------
- * Adjoint (1D-1V, FP64 form): the gradient of the time-integrated field
+ * Adjoint (1D-1V, either storage form): the gradient of the time-integrated field
  * energy J = sum_{n=1..nsteps} sum_i (E_i^n)^2 dx dt with respect to the
  * marker weights f_l, by the reverse of every stage of the step (gather,
  * push, reconstruction f = N/D, moments, spectral solve; Sec. 2 and
@@ -276,9 +276,11 @@ int avl_batch_destroy(avl_batch* b);
  * ------------------------------------------------------------------------- */
 
 /* Device recording workspace for an adjoint run of `nsteps` steps that keeps
- * a checkpoint every `every` steps: the checkpoints, one segment's states and
- * grids, and the adjoint arrays (0 if the configuration is not 1D-1V FP64 or
- * nsteps, every < 1). */
+ * a checkpoint every `every` steps: the checkpoints (the raw marker buffer),
+ * one segment's states (FP64 coordinates) and grids, and the adjoint arrays
+ * (0 if the configuration is not 1D-1V or nsteps, every < 1).  The reverse
+ * sweep works on FP64 coordinates; for the FP32 form they are the exact
+ * conversions of the stored cell and offsets. */
 size_t avl_adjoint_workspace_bytes(const avl_config* cfg, int32_t nsteps, int32_t every);
 
 /* Load (x, v, f) into h as avl_set_markers does but from step 0, run nsteps
@@ -288,7 +290,7 @@ size_t avl_adjoint_workspace_bytes(const avl_config* cfg, int32_t nsteps, int32_
  * J_out (1 device double) and dJ/df_l for every marker, in the order of f, to
  * grad_f (n device doubles).  Synchronises.  Afterwards h holds a recomputed
  * state inside the first segment (reload before further stepping).
- * AVL_ENOTSUP for other forms; AVL_ESTATE while kernel timing is enabled. */
+ * AVL_ENOTSUP for 1D-3V; AVL_ESTATE while kernel timing is enabled. */
 int avl_adjoint(avl_handle* h, const double* x, const double* v, const double* f, int32_t nsteps, int32_t every,
                 void* rec, size_t rec_bytes, double* J_out, double* grad_f);
 

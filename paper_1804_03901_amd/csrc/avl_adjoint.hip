@@ -1,4 +1,5 @@
-// Reverse-mode (adjoint) kernels of the 1D-1V FP64 step, for gradients of
+// Reverse-mode (adjoint) kernels of the 1D-1V step (either storage form; the
+// states are handed over as FP64 coordinates), for gradients of
 // J = sum over steps n = 1..N of sum_i (E_i^n)^2 dx dt with respect to the
 // marker weights f_l.
 //
@@ -32,18 +33,12 @@ __global__ void k_iota(int* __restrict__ id, int n)
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) id[i] = i;
 }
 
-// f of every marker of a state from the weights held by identity.
-__global__ void k_gather_f(const int* __restrict__ id, const double* __restrict__ f_by_id, double* __restrict__ f,
-                           int n)
-{
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) f[i] = f_by_id[id[i]];
-}
-
 // Reverse of the reconstruction and moments for the markers of one state:
 // Pmu = P mu (so rho_bar = -Pmu), fg and Dg the state's grids.
+template <typename T>
 __global__ void k_adj_deposit(Geo g, const double* __restrict__ x, const double* __restrict__ v,
                               const int* __restrict__ id, const double* __restrict__ f_by_id,
-                              const double* __restrict__ fg, const double* __restrict__ Dg,
+                              const T* __restrict__ fg, const T* __restrict__ Dg,
                               const double* __restrict__ Pmu, double* __restrict__ lam_x,
                               double* __restrict__ lam_v, double* __restrict__ f_bar, int with_positions)
 {
@@ -69,9 +64,9 @@ __global__ void k_adj_deposit(Geo g, const double* __restrict__ x, const double*
             for (int ci = 0; ci < 2; ++ci) {
                 const int col = ci ? ib : ia;
                 const size_t gi = (size_t)j * g.nx + col;
-                const double D = Dg[gi];
+                const double D = (double)Dg[gi];
                 const double Nb = D > 0.0 ? -g.q_vol * Pmu[col] / D : 0.0;
-                const double Db = -Nb * fg[gi];
+                const double Db = -Nb * (double)fg[gi];
                 const double G = Nb * fl + Db;
                 const double wx = ci ? a : 1.0 - a;
                 fb += wx * wy * Nb;
@@ -142,20 +137,18 @@ hipError_t launch_iota(int* id, int n, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_gather_f(const int* id, const double* f_by_id, double* f, int n, hipStream_t st)
-{
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather_f, dim3(grid_for(n, 256)), dim3(256), 0, st, id, f_by_id, f, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_adj_deposit(const Geo& g, const double* x, const double* v, const int* id, const double* f_by_id,
-                              const double* fg, const double* Dg, const double* Pmu, double* lam_x, double* lam_v,
-                              double* f_bar, int with_positions, hipStream_t st)
+hipError_t launch_adj_deposit(const Geo& g, int grid_prec, const double* x, const double* v, const int* id,
+                              const double* f_by_id, const void* fg, const void* Dg, const double* Pmu, double* lam_x,
+                              double* lam_v, double* f_bar, int with_positions, hipStream_t st)
 {
     if (g.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_adj_deposit, dim3(grid_for(g.n, 256)), dim3(256), 0, st, g, x, v, id, f_by_id, fg, Dg, Pmu,
-                       lam_x, lam_v, f_bar, with_positions);
+    const dim3 gr(grid_for(g.n, 256)), bl(256);
+    if (grid_prec == 0)
+        hipLaunchKernelGGL(k_adj_deposit<double>, gr, bl, 0, st, g, x, v, id, f_by_id, (const double*)fg,
+                           (const double*)Dg, Pmu, lam_x, lam_v, f_bar, with_positions);
+    else
+        hipLaunchKernelGGL(k_adj_deposit<float>, gr, bl, 0, st, g, x, v, id, f_by_id, (const float*)fg,
+                           (const float*)Dg, Pmu, lam_x, lam_v, f_bar, with_positions);
     return hipGetLastError();
 }
 

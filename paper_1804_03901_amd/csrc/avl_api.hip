@@ -36,10 +36,9 @@ hipError_t launch_to64(const Geo& g, M32 m, double* x, double* v, double* f, hip
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
 size_t recon3_scratch_bytes(const Geo& g);
 hipError_t launch_iota(int* id, int n, hipStream_t st);
-hipError_t launch_gather_f(const int* id, const double* f_by_id, double* f, int n, hipStream_t st);
-hipError_t launch_adj_deposit(const Geo& g, const double* x, const double* v, const int* id, const double* f_by_id,
-                              const double* fg, const double* Dg, const double* Pmu, double* lam_x, double* lam_v,
-                              double* f_bar, int with_positions, hipStream_t st);
+hipError_t launch_adj_deposit(const Geo& g, int grid_prec, const double* x, const double* v, const int* id,
+                              const double* f_by_id, const void* fg, const void* Dg, const double* Pmu, double* lam_x,
+                              double* lam_v, double* f_bar, int with_positions, hipStream_t st);
 hipError_t launch_adj_push(const Geo& g, const double* x, const int* id, const double* E, double c, double* lam_x,
                            double* lam_v, double* mu_dep, hipStream_t st);
 hipError_t launch_adj_mu(int nx, const double* E, double w, double* mu_dep, double* mu, hipStream_t st);
@@ -285,6 +284,7 @@ void set_views(avl_handle* h)
             h->m32[b].a = reinterpret_cast<float*>(c + n);
             h->m32[b].b = reinterpret_cast<float*>(c + 2 * n);
             h->m32[b].f = reinterpret_cast<float*>(c + n * (2 + h->g.vdim));
+            h->m32[b].id = nullptr;
         }
     }
 }
@@ -481,6 +481,7 @@ int load_markers(avl_handle* h, const double* x, const double* v, const double* 
         if (h->m64[0].id) AVL_TRY(launch_iota(h->m64[0].id, (int)n, h->st));
     } else {
         AVL_TRY(launch_to32(g, x, v, f, h->m32[0], h->flags, h->st));
+        if (h->m32[0].id) AVL_TRY(launch_iota(h->m32[0].id, (int)n, h->st));
     }
     const int total = g.n;
     const size_t nbt = (size_t)g.nb + 1;
@@ -1189,38 +1190,48 @@ int avl_batch_destroy(avl_batch* b)
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
-// adjoint runs (1D-1V, FP64 form)
+// adjoint runs (1D-1V, both storage forms)
 // ---------------------------------------------------------------------------
 namespace {
 
-// Recording workspace: checkpoints (marker state and field every `every`
-// steps), the states of one segment with their grids, adjoints by marker
-// identity, identity arrays for both marker buffers, small field buffers.
+// Recording workspace: checkpoints (a raw copy of the marker buffer with the
+// identities, and the field, every `every` steps), the states of one segment
+// (FP64 positions and velocities, identities, f and D grids in the storage
+// precision, the field), adjoints by marker identity, identity arrays for
+// both marker buffers, small field buffers.
 struct AdjLayout {
-    size_t cp, cp_stride, seg, seg_stride, ids[2], lam_x, lam_v, f_bar, f_by_id, Pmu, mu, mu_dep, diag, total;
-    size_t st_x, st_v, st_id, st_fg, st_D, st_E;   // offsets inside one state record
+    size_t cp, cp_stride, cp_ids, cp_E, mbytes;
+    size_t seg, seg_stride, st_x, st_v, st_id, st_fg, st_D, st_E;
+    size_t ids[2], lam_x, lam_v, f_bar, f_by_id, f_tmp, Pmu, mu, mu_dep, diag, total;
     int nseg;
 };
 
-bool adj_layout(const Geo& g, int32_t nsteps, int32_t every, AdjLayout* A)
+bool adj_layout(const avl_config* c, const Geo& g, int32_t nsteps, int32_t every, AdjLayout* A)
 {
-    if (nsteps < 1 || every < 1 || g.vdim != 1 || g.prec != AVL_FP64) return false;
+    if (nsteps < 1 || every < 1 || g.vdim != 1) return false;
+    Layout L;
+    make_layout(c, g, &L);
     const size_t n = (size_t)g.np, G = (size_t)g.nx * g.nv[0], nx = (size_t)g.nx;
-    size_t o = 0;
-    auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+    const size_t esz = g.prec == AVL_FP64 ? 8 : 4;
+    A->mbytes = L.markers[1] - L.markers[0];
     A->nseg = (nsteps + every - 1) / every;
-    // one state: x, v, id, f grid, D grid, E
+    size_t co = 0;
+    auto ctake = [&](size_t bytes) { size_t r = co; co = align_up(co + bytes); return r; };
+    ctake(A->mbytes);
+    A->cp_ids = ctake(4 * n);
+    A->cp_E = ctake(8 * nx);
+    A->cp_stride = co;
     size_t so = 0;
     auto stake = [&](size_t bytes) { size_t r = so; so = align_up(so + bytes); return r; };
     A->st_x = stake(8 * n);
     A->st_v = stake(8 * n);
     A->st_id = stake(4 * n);
-    A->st_fg = stake(8 * G);
-    A->st_D = stake(8 * G);
+    A->st_fg = stake(esz * G);
+    A->st_D = stake(esz * G);
     A->st_E = stake(8 * nx);
     A->seg_stride = so;
-    // a checkpoint keeps the markers and the field only
-    A->cp_stride = align_up(A->st_fg) + align_up(8 * nx);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
     A->cp = take(A->cp_stride * (size_t)A->nseg);
     A->seg = take(A->seg_stride * ((size_t)every + 1));
     A->ids[0] = take(4 * n);
@@ -1229,6 +1240,7 @@ bool adj_layout(const Geo& g, int32_t nsteps, int32_t every, AdjLayout* A)
     A->lam_v = take(8 * n);
     A->f_bar = take(8 * n);
     A->f_by_id = take(8 * n);
+    A->f_tmp = take(8 * n);
     A->Pmu = take(8 * nx);
     A->mu = take(8 * nx);
     A->mu_dep = take(8 * nx);
@@ -1237,19 +1249,52 @@ bool adj_layout(const Geo& g, int32_t nsteps, int32_t every, AdjLayout* A)
     return true;
 }
 
-// Copy the current markers (x, v, id) and field into a state record; the f
-// grid too when `grid` is set (its D is written by the reconstruction).
-int adj_save(avl_handle* h, char* rec, const AdjLayout& A, bool grid, size_t e_off)
+int* id_of(avl_handle* h, int b) { return h->g.prec == AVL_FP64 ? h->m64[b].id : h->m32[b].id; }
+
+void set_ids(avl_handle* h, int b, int* p)
 {
-    const M64& m = h->m64[h->cur];
-    const size_t n = (size_t)h->g.n;
-    AVL_TRY(hipMemcpyAsync(rec + A.st_x, m.x, 8 * n, hipMemcpyDeviceToDevice, h->st));
-    AVL_TRY(hipMemcpyAsync(rec + A.st_v, m.v, 8 * n, hipMemcpyDeviceToDevice, h->st));
-    AVL_TRY(hipMemcpyAsync(rec + A.st_id, m.id, 4 * n, hipMemcpyDeviceToDevice, h->st));
-    if (grid)
-        AVL_TRY(hipMemcpyAsync(rec + A.st_fg, h->fgrid, 8 * (size_t)h->g.nx * h->g.nv[0], hipMemcpyDeviceToDevice,
-                               h->st));
-    AVL_TRY(hipMemcpyAsync(rec + e_off, h->E, 8 * (size_t)h->g.nx, hipMemcpyDeviceToDevice, h->st));
+    if (h->g.prec == AVL_FP64) h->m64[b].id = p;
+    else h->m32[b].id = p;
+}
+
+// Checkpoint: the current marker buffer as it is, its identities, the field.
+int adj_checkpoint(avl_handle* h, char* C, const AdjLayout& A, bool restore)
+{
+    char* mk = h->ws + h->lay.markers[h->cur];
+    int* id = id_of(h, h->cur);
+    const size_t n = (size_t)h->g.np;
+    if (restore) {
+        AVL_TRY(hipMemcpyAsync(mk, C, A.mbytes, hipMemcpyDeviceToDevice, h->st));
+        AVL_TRY(hipMemcpyAsync(id, C + A.cp_ids, 4 * n, hipMemcpyDeviceToDevice, h->st));
+        AVL_TRY(hipMemcpyAsync(h->E, C + A.cp_E, 8 * (size_t)h->g.nx, hipMemcpyDeviceToDevice, h->st));
+    } else {
+        AVL_TRY(hipMemcpyAsync(C, mk, A.mbytes, hipMemcpyDeviceToDevice, h->st));
+        AVL_TRY(hipMemcpyAsync(C + A.cp_ids, id, 4 * n, hipMemcpyDeviceToDevice, h->st));
+        AVL_TRY(hipMemcpyAsync(C + A.cp_E, h->E, 8 * (size_t)h->g.nx, hipMemcpyDeviceToDevice, h->st));
+    }
+    return AVL_OK;
+}
+
+// State record: FP64 positions and velocities of the current markers (the
+// FP32 form converted exactly), identities, the f grid and the field (its D
+// grid is written by the reconstruction).
+int adj_save(avl_handle* h, char* S, const AdjLayout& A, double* f_tmp)
+{
+    const Geo& g = h->g;
+    const size_t n = (size_t)g.n;
+    if (g.prec == AVL_FP64) {
+        const M64& m = h->m64[h->cur];
+        AVL_TRY(hipMemcpyAsync(S + A.st_x, m.x, 8 * n, hipMemcpyDeviceToDevice, h->st));
+        AVL_TRY(hipMemcpyAsync(S + A.st_v, m.v, 8 * n, hipMemcpyDeviceToDevice, h->st));
+        AVL_TRY(hipMemcpyAsync(S + A.st_id, m.id, 4 * n, hipMemcpyDeviceToDevice, h->st));
+    } else {
+        const M32& m = h->m32[h->cur];
+        if (n) AVL_TRY(launch_to64(g, m, (double*)(S + A.st_x), (double*)(S + A.st_v), f_tmp, h->st));
+        AVL_TRY(hipMemcpyAsync(S + A.st_id, m.id, 4 * n, hipMemcpyDeviceToDevice, h->st));
+    }
+    const size_t esz = g.prec == AVL_FP64 ? 8 : 4;
+    AVL_TRY(hipMemcpyAsync(S + A.st_fg, h->fgrid, esz * (size_t)g.nx * g.nv[0], hipMemcpyDeviceToDevice, h->st));
+    AVL_TRY(hipMemcpyAsync(S + A.st_E, h->E, 8 * (size_t)g.nx, hipMemcpyDeviceToDevice, h->st));
     return AVL_OK;
 }
 
@@ -1262,16 +1307,16 @@ size_t avl_adjoint_workspace_bytes(const avl_config* cfg, int32_t nsteps, int32_
     Geo g;
     if (make_geo(cfg, &g) != AVL_OK) return 0;
     AdjLayout A;
-    return adj_layout(g, nsteps, every, &A) ? A.total : 0;
+    return adj_layout(cfg, g, nsteps, every, &A) ? A.total : 0;
 }
 
 int avl_adjoint(avl_handle* h, const double* x, const double* v, const double* f, int32_t nsteps, int32_t every,
                 void* rec, size_t rec_bytes, double* J_out, double* grad_f)
 {
     if (!h || !rec || !J_out || !grad_f) return AVL_EINVAL;
-    if (h->g.vdim != 1 || h->g.prec != AVL_FP64) return AVL_ENOTSUP;
+    if (h->g.vdim != 1) return AVL_ENOTSUP;
     AdjLayout A;
-    if (!adj_layout(h->g, nsteps, every, &A)) return AVL_EINVAL;
+    if (!adj_layout(&h->cfg, h->g, nsteps, every, &A)) return AVL_EINVAL;
     if ((uintptr_t)rec & 255) return AVL_EALIGN;
     if (rec_bytes < A.total) return AVL_ESIZE;
     if (h->timing) return AVL_ESTATE;
@@ -1282,27 +1327,28 @@ int avl_adjoint(avl_handle* h, const double* x, const double* v, const double* f
     double* lam_v = (double*)(R + A.lam_v);
     double* f_bar = (double*)(R + A.f_bar);
     double* f_by_id = (double*)(R + A.f_by_id);
+    double* f_tmp = (double*)(R + A.f_tmp);
     double* Pmu = (double*)(R + A.Pmu);
     double* mu = (double*)(R + A.mu);
     double* mu_dep = (double*)(R + A.mu_dep);
     double* diag = (double*)(R + A.diag);
     auto state = [&](int q) { return R + A.seg + A.seg_stride * (size_t)q; };
     auto ckpt = [&](int k) { return R + A.cp + A.cp_stride * (size_t)k; };
-    const size_t cp_E = align_up(A.st_fg);
     const double dxdt2 = 2.0 * g.dx * g.dt;
+    const int gp = g.prec;
     drop_graphs(h);
     for (int b = 0; b < 2; ++b) {
-        h->m64[b].id = (int*)(R + A.ids[b]);
+        set_ids(h, b, (int*)(R + A.ids[b]));
         // every slot holds a valid identity even before the first scatter fills it
-        hipError_t e = hipMemsetAsync(h->m64[b].id, 0, 4 * (size_t)g.np, h->st);
+        hipError_t e = hipMemsetAsync(id_of(h, b), 0, 4 * (size_t)g.np, h->st);
         if (e != hipSuccess) {
-            for (int q = 0; q < 2; ++q) h->m64[q].id = nullptr;
+            for (int q = 0; q < 2; ++q) set_ids(h, q, nullptr);
             return report(e, "id clear", __LINE__);
         }
     }
     int rc = AVL_OK;
     auto done = [&](int r) {
-        for (int b = 0; b < 2; ++b) h->m64[b].id = nullptr;
+        for (int b = 0; b < 2; ++b) set_ids(h, b, nullptr);
         h->rec_D = nullptr;
         return r;
     };
@@ -1314,7 +1360,7 @@ int avl_adjoint(avl_handle* h, const double* x, const double* v, const double* f
     }
     if ((rc = load_markers(h, x, v, f, true))) return done(rc);
     for (int k = 0; k < A.nseg; ++k) {
-        if ((rc = adj_save(h, ckpt(k), A, false, cp_E))) return done(rc);
+        if ((rc = adj_checkpoint(h, ckpt(k), A, false))) return done(rc);
         const int s0 = k * every, s1 = std::min(nsteps, s0 + every);
         if ((rc = avl_step(h, s1 - s0, diag + 2 * (size_t)s0))) return done(rc);
     }
@@ -1342,29 +1388,19 @@ int avl_adjoint(avl_handle* h, const double* x, const double* v, const double* f
     const double c_full = g.qm * g.dt;
     for (int k = A.nseg - 1; k >= 0; --k) {
         const int s0 = k * every, s1 = std::min(nsteps, s0 + every);
-        // restore the checkpoint into the current buffer, re-sort it (run
-        // bounds for the reconstruction), rebuild f, D
-        {
-            char* C = ckpt(k);
-            M64& m = h->m64[h->cur];
-            const size_t bytes = 8 * (size_t)n;
-            e = hipMemcpyAsync(m.x, C + A.st_x, bytes, hipMemcpyDeviceToDevice, h->st);
-            if (e == hipSuccess) e = hipMemcpyAsync(m.v, C + A.st_v, bytes, hipMemcpyDeviceToDevice, h->st);
-            if (e == hipSuccess) e = hipMemcpyAsync(m.id, C + A.st_id, 4 * (size_t)n, hipMemcpyDeviceToDevice, h->st);
-            if (e == hipSuccess) e = launch_gather_f(m.id, f_by_id, m.f, n, h->st);
-            if (e == hipSuccess) e = hipMemcpyAsync(h->E, C + cp_E, 8 * (size_t)g.nx, hipMemcpyDeviceToDevice, h->st);
-            if (e != hipSuccess) return done(report(e, "checkpoint restore", __LINE__));
-            h->steps = s0;
-            h->kicked = s0 > 0;
-            h->have_E = true;
-            if ((rc = do_sort(h, false, 1.0))) return done(rc);
-            if ((rc = do_recon(h, state(0) + A.st_D))) return done(rc);
-            if ((rc = adj_save(h, state(0), A, true, A.st_E))) return done(rc);
-        }
+        // restore the checkpoint, re-sort it (run bounds for the
+        // reconstruction), rebuild f and D, then recompute the segment
+        if ((rc = adj_checkpoint(h, ckpt(k), A, true))) return done(rc);
+        h->steps = s0;
+        h->kicked = s0 > 0;
+        h->have_E = true;
+        if ((rc = do_sort(h, false, 1.0))) return done(rc);
+        if ((rc = do_recon(h, state(0) + A.st_D))) return done(rc);
+        if ((rc = adj_save(h, state(0), A, f_tmp))) return done(rc);
         for (int q = 0; q < s1 - s0; ++q) {
             h->rec_D = state(q + 1) + A.st_D;
             if ((rc = one_step(h))) return done(rc);
-            if ((rc = adj_save(h, state(q + 1), A, true, A.st_E))) return done(rc);
+            if ((rc = adj_save(h, state(q + 1), A, f_tmp))) return done(rc);
         }
         h->rec_D = nullptr;
         for (int q = s1 - s0 - 1; q >= 0; --q) {
@@ -1374,9 +1410,9 @@ int avl_adjoint(avl_handle* h, const double* x, const double* v, const double* f
             if (launch_field(g, nullptr, mu, h->rho_slices, h->rho, Pmu, h->tw, h->green, h->diag, h->ctr, 0, nullptr,
                              h->flags, h->st) != hipSuccess)
                 return done(AVL_EDEVICE);
-            if (launch_adj_deposit(g, (double*)(S1 + A.st_x), (double*)(S1 + A.st_v), (int*)(S1 + A.st_id), f_by_id,
-                                   (double*)(S1 + A.st_fg), (double*)(S1 + A.st_D), Pmu, lam_x, lam_v, f_bar, 1,
-                                   h->st) != hipSuccess)
+            if (launch_adj_deposit(g, gp, (double*)(S1 + A.st_x), (double*)(S1 + A.st_v), (int*)(S1 + A.st_id),
+                                   f_by_id, S1 + A.st_fg, S1 + A.st_D, Pmu, lam_x, lam_v, f_bar, 1, h->st) !=
+                hipSuccess)
                 return done(AVL_EDEVICE);
             const double kick = (step == 0 && h->cfg.first_kick) ? 0.5 : 1.0;
             if (launch_adj_push(g, (double*)(S0 + A.st_x), (int*)(S0 + A.st_id), (double*)(S0 + A.st_E),
@@ -1391,9 +1427,9 @@ int avl_adjoint(avl_handle* h, const double* x, const double* v, const double* f
             if (launch_field(g, nullptr, mu, h->rho_slices, h->rho, Pmu, h->tw, h->green, h->diag, h->ctr, 0, nullptr,
                              h->flags, h->st) != hipSuccess)
                 return done(AVL_EDEVICE);
-            if (launch_adj_deposit(g, (double*)(S0 + A.st_x), (double*)(S0 + A.st_v), (int*)(S0 + A.st_id), f_by_id,
-                                   (double*)(S0 + A.st_fg), (double*)(S0 + A.st_D), Pmu, lam_x, lam_v, f_bar, 0,
-                                   h->st) != hipSuccess)
+            if (launch_adj_deposit(g, gp, (double*)(S0 + A.st_x), (double*)(S0 + A.st_v), (int*)(S0 + A.st_id),
+                                   f_by_id, S0 + A.st_fg, S0 + A.st_D, Pmu, lam_x, lam_v, f_bar, 0, h->st) !=
+                hipSuccess)
                 return done(AVL_EDEVICE);
         }
     }

@@ -70,6 +70,7 @@ struct M32 {             // FP32 form: dual cell index + offsets
     float* a;
     float* b;            // component d of marker l at b[d*np + l]
     float* f;
+    int* id;             // optional marker identities carried through the sort (adjoint runs), else null
 };
 
 // Drift table for the FP32 form, one entry per dual row j' = j0+1 in [0, nv]:

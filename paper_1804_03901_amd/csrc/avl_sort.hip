@@ -58,6 +58,7 @@ template <int VD> struct Pay<0, VD> {
 template <int VD> struct Pay<1, VD> {
     int cell;
     float a, b[VD], f;
+    int id;
     // nvel < VD loads only the first nvel velocity offsets
     __device__ void load(const M32& m, const Geo& g, int i, bool with_f, int nvel = VD) {
         cell = m.cell[i];
@@ -65,6 +66,7 @@ template <int VD> struct Pay<1, VD> {
 #pragma unroll
         for (int d = 0; d < VD; ++d) b[d] = d < nvel ? m.b[(size_t)d * g.np + i] : 0.0f;
         f = with_f ? m.f[i] : 0.0f;
+        id = (with_f && m.id) ? m.id[i] : 0;
     }
     __device__ void store(const M32& m, const Geo& g, int i) const {
         m.cell[i] = cell;
@@ -72,6 +74,7 @@ template <int VD> struct Pay<1, VD> {
 #pragma unroll
         for (int d = 0; d < VD; ++d) m.b[(size_t)d * g.np + i] = b[d];
         m.f[i] = f;
+        if (m.id) m.id[i] = id;
     }
     __device__ void push(const Geo& g, const float* sE, const RowShift* rows, double, float bk, int& flags) {
         push32<VD>(g, sE, rows, bk, cell, a, b[0], flags);

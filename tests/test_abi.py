@@ -150,6 +150,7 @@ def test_adjoint_workspace_rules():
     assert n1 > 0 and n2 > n1          # a longer segment keeps more states
     assert avl.avl_adjoint_workspace_bytes(c64, 0, 10) == 0
     assert avl.avl_adjoint_workspace_bytes(c64, 10, 0) == 0
-    assert avl.avl_adjoint_workspace_bytes(avl.make_config(w, precision=avl.AVL_FP32), 30, 10) == 0
+    assert avl.avl_adjoint_workspace_bytes(avl.make_config(w, precision=avl.AVL_FP32), 30, 10) > 0
+    assert avl.avl_adjoint_workspace_bytes(avl.make_config(inputs.two_stream_3v(nx=16, nv=4, ppc=1)), 30, 10) == 0
     lib = avl.load()
     assert lib.avl_adjoint(None, None, None, None, 1, 1, None, 0, None, None) == -1

@@ -22,15 +22,16 @@ W = inputs.bump_on_tail(nx=64, nv=64, ppc=4, seed=21, steps=30)
 NSTEPS = 30
 
 
-def setup_case():
+def setup_case(precision=avl.AVL_FP64, w=None):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    x, v, f = inputs.markers(W)
+    w = w or W
+    x, v, f = inputs.markers_threaded(w)
     dev = torch.device("cuda:0")
     xt = torch.tensor(x, device=dev)
     vt = torch.tensor(v.reshape(-1), device=dev)
-    sim = avl.Simulation(W, x, v.reshape(-1), f, precision=avl.AVL_FP64)
-    print(f"[case] adjoint {W.name} steps={NSTEPS}", flush=True)
+    sim = avl.Simulation(w, x, v.reshape(-1), f, precision=precision)
+    print(f"[case] adjoint {w.name} prec={precision}", flush=True)
     return sim, xt, vt, f
 
 
@@ -40,10 +41,10 @@ def theta0(dev):
     return amps, drift
 
 
-def J_gpu(sim, xt, vt, amps, drift):
+def J_gpu(sim, xt, vt, amps, drift, nsteps=NSTEPS):
     with torch.no_grad():
-        f = adjoint.f0_torch(W, xt, vt, amps, drift)
-        J, _ = adjoint.energy_and_gradient(sim, xt, vt, f, NSTEPS, want_grad=False)
+        f = adjoint.f0_torch(sim.w, xt, vt, amps, drift)
+        J, _ = adjoint.energy_and_gradient(sim, xt, vt, f, nsteps, want_grad=False)
     return float(J)
 
 
@@ -53,12 +54,12 @@ def J_oracle(x, v, amps, drift):
     return 2.0 * W.c_p * W.dt * float(r["diag"][:, 0].sum())
 
 
-def adjoint_grad(sim, xt, vt, every=10):
+def adjoint_grad(sim, xt, vt, every=10, nsteps=NSTEPS):
     amps, drift = theta0(xt.device)
     amps.requires_grad_(True)
     drift.requires_grad_(True)
-    f = adjoint.f0_torch(W, xt, vt, amps, drift)
-    J = adjoint.field_energy(f, sim, xt, vt, NSTEPS, every)
+    f = adjoint.f0_torch(sim.w, xt, vt, amps, drift)
+    J = adjoint.field_energy(f, sim, xt, vt, nsteps, every)
     J.backward()
     return float(J.detach()), amps.grad.detach().clone(), float(drift.grad)
 
@@ -145,3 +146,40 @@ def test_weight_gradient_directional_derivative():
     ad = float((g * d).sum())
     print(f"directional: adjoint {ad:.10e} fd {fd:.10e}")
     assert abs(ad - fd) <= 1e-4 * abs(fd)
+
+
+def test_fp32_form_gradient_matches_fp64_finite_differences():
+    """The adjoint of the FP32-form run against central differences of the
+    FP64 path (the two runs agree to the FP32 form's accuracy)."""
+    sim32, xt, vt, f = setup_case(avl.AVL_FP32)
+    _, gA, gd = adjoint_grad(sim32, xt, vt)
+    sim64, _, _, _ = setup_case(avl.AVL_FP64)
+    amps, drift = theta0(xt.device)
+    e = torch.zeros_like(amps)
+    e[0] = 1e-7
+    fdA = (J_gpu(sim64, xt, vt, amps + e, drift) - J_gpu(sim64, xt, vt, amps - e, drift)) / 2e-7
+    fdd = (J_gpu(sim64, xt, vt, amps, drift + 1e-3) - J_gpu(sim64, xt, vt, amps, drift - 1e-3)) / 2e-3
+    print(f"fp32 adjoint A1 {float(gA[0]):.10e} fd64 {fdA:.10e}; drift {gd:.10e} fd64 {fdd:.10e}")
+    assert abs(float(gA[0]) - fdA) <= 1e-4 * abs(fdA)
+    assert abs(gd - fdd) <= 1e-4 * abs(fdd)
+
+
+@pytest.mark.slow
+def test_adjoint_at_full_size():
+    """The adjoint configuration at full size: bump-on-tail nx = 1024, nv = 512,
+    8 markers per cell (4,194,304 markers), 500 steps, FP32 forward with a
+    checkpoint every 50 steps; two gradient components against central
+    differences of the FP64 path."""
+    w = inputs.adjoint_case()
+    sim32, xt, vt, f = setup_case(avl.AVL_FP32, w)
+    _, gA, gd = adjoint_grad(sim32, xt, vt, every=50, nsteps=w.steps)
+    sim32.close()
+    sim64 = avl.Simulation(w, xt, vt, torch.tensor(f, device=xt.device), precision=avl.AVL_FP64)
+    amps, drift = theta0(xt.device)
+    e = torch.zeros_like(amps)
+    e[0] = 1e-7
+    fdA = (J_gpu(sim64, xt, vt, amps + e, drift, w.steps) - J_gpu(sim64, xt, vt, amps - e, drift, w.steps)) / 2e-7
+    fdd = (J_gpu(sim64, xt, vt, amps, drift + 1e-3, w.steps) - J_gpu(sim64, xt, vt, amps, drift - 1e-3, w.steps)) / 2e-3
+    print(f"full size: A1 adjoint {float(gA[0]):.10e} fd64 {fdA:.10e}; drift {gd:.10e} fd64 {fdd:.10e}")
+    assert abs(float(gA[0]) - fdA) <= 1e-4 * abs(fdA)
+    assert abs(gd - fdd) <= 1e-4 * abs(fdd)
