@@ -44,6 +44,7 @@ hipError_t launch_adj_push(const Geo& g, const double* x, const int* id, const d
 hipError_t launch_adj_mu(int nx, const double* E, double w, double* mu_dep, double* mu, hipStream_t st);
 int sort_blocks(const Geo& g, int phase);
 size_t sort_lds(const Geo& g);
+int scatter_blocks_per_cu(const Geo& g);
 hipError_t launch_sort_batch(int prec, const BInst* tab, const int* pre, int ninst, int blocks, size_t smem, int cur,
                              hipStream_t st, int phase);
 hipError_t launch_recon_batch(int prec, int kahan, const BInst* tab, const int* pre, int ninst, int tasks, int cur,
@@ -589,6 +590,7 @@ int avl_init(const avl_config* cfg, void* workspace, size_t ws_bytes, void* stre
             if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) lds = 65536;
         set_lds_limit(lds);
         fit_lds(&h->g, lds);
+        h->g.sblocks = scatter_blocks_per_cu(h->g) * device_cus();
         if (debug_on())
             std::fprintf(stderr, "[avl] lds limit %d B, recon cap %d, hist bins %d, rc %d, chunks %d, strips %d\n", lds,
                          h->g.cap, h->g.hist_bins, h->g.rc, h->g.nchunk, h->g.nstrip);

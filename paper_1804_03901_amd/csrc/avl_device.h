@@ -49,6 +49,7 @@ struct Geo {
     int cap;             // markers staged in LDS per reconstruct wave
     int jpad, jrange;    // FP32 1D-3V: x-velocity dual index stored with offset jpad, range jrange
     int kahan;           // FP32 form: compensated FP32 accumulation instead of FP64 accumulators
+    int sblocks;         // blocks of the tiled scatter (FP32 1D-1V): the resident capacity; 0 = a tile per block
     double L, inv_L, dx, inv_dx;
     double vmin[3], dv[3], inv_dv[3];
     double dt, qm, cp;

@@ -6,20 +6,22 @@
 // (i, j), (i+1, j), (i, j+1), (i+1, j+1) with weights (1-a)(1-b), a(1-b),
 // (1-a)b, ab.  One wavefront owns a strip of 63 target columns and a chunk of
 // target rows; lane l owns run column strip*63 - 1 + l.  The wave walks the
-// dual rows of its chunk bottom to top: it stages the row segment's markers
-// (one contiguous range of the sorted arrays, plus the wrapped run at x = L
-// for the first strip) into LDS with coalesced loads, then every lane sums its
-// own run into four (N, D) corner partials.  Staging is software-pipelined:
-// the next row's markers are loaded into registers while the current row is
-// summed, so each wave keeps a full row segment (16-24 KB) of loads in
-// flight.  Row segments larger than the LDS capacity are summed straight from
-// global memory (same order, slower).  Tasks are dealt to blocks so that each
-// XCD gets consecutive chunks of the same strip, whose shared halo rows then
-// hit that XCD's L2.  Target cell (i, j) is then
+// dual rows of its chunk, upwards for even chunks and downwards for odd ones,
+// so that the dual row two neighbouring chunks share is read by both at about
+// the same time and the second read hits L2.  For each row it stages the row
+// segment's markers (one contiguous range of the sorted arrays, plus the
+// wrapped run at x = L for the first strip) into LDS with coalesced loads and
+// 16-byte LDS stores, then every lane sums its own run into four (N, D)
+// corner partials.  Staging is software-pipelined: the next two rows'
+// markers are loaded into registers while the current row is summed.  Row
+// segments larger than the LDS capacity are summed straight from global
+// memory (same order, slower).  Tasks are dealt to blocks so that each XCD
+// gets consecutive chunks of the same strip.  Target cell (i, j) is then
 //   ((up01(i, j-1) + up11(i-1, j-1)) + S00(i, j)) + S10(i-1, j)
-// where the (i-1) terms come from the neighbouring lane by a shuffle and the
-// "up" terms are carried in registers from the previous dual row.  Every sum
-// has a fixed order given the sorted input: no float atomics anywhere.
+// in both walk directions, where the (i-1) terms come from the neighbouring
+// lane by a shuffle and the terms of the previous dual row of the walk are
+// carried in registers.  Every sum has a fixed order given the sorted input:
+// no float atomics anywhere.
 //
 // rho: each lane also sums f over the rows of its chunk for its column and
 // writes one partial per (chunk, column); the field kernel adds the chunk
@@ -220,6 +222,12 @@ template <> struct Lds<1> {
         b[p] = r.b;
         f[p] = r.f;
     }
+    // V = 4 consecutive markers from p (a multiple of 4) as 16-byte stores
+    __device__ void putv(const Geo&, int p, const Src<1>::Vec& v) {
+        *reinterpret_cast<float4*>(a + p) = make_float4(v.r[0].a, v.r[1].a, v.r[2].a, v.r[3].a);
+        *reinterpret_cast<float4*>(b + p) = make_float4(v.r[0].b, v.r[1].b, v.r[2].b, v.r[3].b);
+        *reinterpret_cast<float4*>(f + p) = make_float4(v.r[0].f, v.r[1].f, v.r[2].f, v.r[3].f);
+    }
     __device__ void get(int p, float& aa, float& bb, float& ff) const {
         aa = a[p];
         bb = b[p];
@@ -240,6 +248,10 @@ template <> struct Lds<0> {
         locate64<1>(g, r.x, vv, ix, jp, aa, bb);
         ab[p] = make_double2(aa, bb[0]);
         f[p] = r.f;
+    }
+    __device__ void putv(const Geo& g, int p, const Src<0>::Vec& v) {
+#pragma unroll
+        for (int q = 0; q < Src<0>::V; ++q) put(g, p + q, v.r[q]);
     }
     __device__ void get(int p, double& aa, double& bb, double& ff) const {
         const double2 t = ab[p];
@@ -351,16 +363,19 @@ __device__ __forceinline__ void recon_task(const Geo& g, const typename RT<PREC>
     const int last_lane = last_col - (strip * kReconCols - 1);
     const int j_begin = chunk * g.rc;
     const int j_end = min(j_begin + g.rc, g.nv[0]);
-    // the chunk walks dual rows j_begin-1 .. j_end-1 (row k of the walk is
-    // dual row j_begin-1+k)
+    // the chunk walks dual rows j_begin-1 .. j_end-1, upwards for even chunks
+    // and downwards for odd ones: the dual row two neighbouring chunks share
+    // is then read by both at about the same time (both first or both last),
+    // so the second read tends to hit the XCD's L2
     const int nrows = j_end - j_begin + 1;
+    const bool upward = (chunk & 1) == 0;
 
     // run bounds through a bounded descriptor: an invalid lane or row reads
     // past the end and gets (0, 0), with no branch
     const __amdgpu_buffer_rsrc_t roff = rsrc(offsets, sizeof(int) * ((size_t)g.nb + 2));
     auto row_offsets = [&](int k, int& beg, int& end) {
         const bool ok = run_ok && k < nrows;
-        const int bk = ok ? (j_begin + k) * nx + colw : g.nb + 2;
+        const int bk = ok ? (upward ? j_begin + k : j_end - k) * nx + colw : g.nb + 2;
         const auto t = __builtin_amdgcn_raw_buffer_load_b64(roff, bk * (int)sizeof(int), 0, 0);
         const unsigned t0 = t[0], t1 = t[1];
         beg = (int)t0;
@@ -382,23 +397,23 @@ __device__ __forceinline__ void recon_task(const Geo& g, const typename RT<PREC>
         prefetch<PREC>(m, sg[q], lane, regs[q], wreg[q]);
     }
 
-    double upN = 0.0, upD = 0.0;
+    // carried from the previous row of the walk: the up terms (upward) or
+    // the 00 term and the left neighbour's 10 term (downward)
+    double cN = 0.0, cD = 0.0, cN10 = 0.0, cD10 = 0.0;
     double rp = 0.0;
 
     // one row of the walk; its markers are in regs[buf]
     auto row = [&](int k, Vec* R, Raw& W) {
-        const int jd = j_begin - 1 + k;
+        const int tj = upward ? j_begin - 1 + k : j_end - k;   // target row completed by this row
         const Seg seg = sg[0];
         const int beg = rb[0], end = re[0];
         const bool staged = seg.fits(MAIN);
         if (staged) {
 #pragma unroll
             for (int u = 0; u < KU / V; ++u)
-#pragma unroll
-                for (int q = 0; q < V; ++q) {
-                    const int p = u * kWave * V + lane * V + q;
-                    if (p < seg.nmain) lds.put(g, p, R[u].r[q]);
-                }
+                lds.putv(g, u * kWave * V + lane * V, R[u]);
+            // slots past the main range hold zeros from the bounded loads;
+            // the wrapped run is written over them afterwards
             if (lane < seg.wlen) lds.put(g, seg.nmain + lane, W);
         }
         wave_sync_lds();
@@ -442,18 +457,22 @@ __device__ __forceinline__ void recon_task(const Geo& g, const typename RT<PREC>
         const double n11l = __shfl_up(c.n11, 1, kWave);
         const double d11l = __shfl_up(c.d11, 1, kWave);
 
-        // target row jd = ((up01 + up11 of dual row jd-1) + down00) + down10
-        if (k > 0 && tgt_ok) {
-            const double Nv = (upN + c.n00) + n10l;
-            const double Dv = (upD + c.d00) + d10l;
+        // target row j = ((up01 + up11 of dual row j-1) + down00) + down10 of
+        // dual row j, in this order in both walk directions
+        const double uN = c.n01 + n11l, uD = c.d01 + d11l;
+        if (k > 0 && k < nrows && tgt_ok) {
+            const double Nv = upward ? (cN + c.n00) + n10l : (uN + cN) + cN10;
+            const double Dv = upward ? (cD + c.d00) + d10l : (uD + cD) + cD10;
             const double fv = Dv > 0.0 ? Nv / Dv : 0.0;
-            const size_t gi = (size_t)jd * nx + col;
+            const size_t gi = (size_t)tj * nx + col;
             fgrid[gi] = (T)fv;
             if (Dgrid) Dgrid[gi] = (T)Dv;
             rp += (double)(T)fv;
         }
-        upN = c.n01 + n11l;
-        upD = c.d01 + d11l;
+        cN = upward ? uN : c.n00;
+        cD = upward ? uD : c.d00;
+        cN10 = n10l;
+        cD10 = d10l;
 
 #pragma unroll
         for (int q = 0; q < DEPTH; ++q) sg[q] = sg[q + 1];
@@ -464,10 +483,12 @@ __device__ __forceinline__ void recon_task(const Geo& g, const typename RT<PREC>
         }
     };
 
+    // whole groups of DEPTH rows, so every pass of the loop body is the same
+    // (the compiler then keeps the waits for loads at their full depth); a
+    // row past the chunk has empty runs and writes nothing
     for (int k = 0; k < nrows; k += DEPTH) {
 #pragma unroll
-        for (int q = 0; q < DEPTH; ++q)
-            if (k + q < nrows) row(k + q, regs[q], wreg[q]);
+        for (int q = 0; q < DEPTH; ++q) row(k + q, regs[q], wreg[q]);
     }
     if (tgt_ok) rho_part[(size_t)chunk * nx + col] = rp;
 }

@@ -201,34 +201,6 @@ struct SortSmem {
     }
 };
 
-// Block set-up shared by both passes: stage the field (and drift table), load
-// the thread's group, find the histogram window from the block's first and
-// last markers (before the push), clear the window.
-template <int PREC, int VD, int K, bool PUSH>
-__device__ __forceinline__ void sort_setup(const Geo& g, const SortSmem<PREC>& sm, const typename MarkersOf<PREC>::T& m,
-                                           Group<PREC, VD, K>& grp, int base, int first, int last, bool with_f,
-                                           const double* E, const RowShift* rows_g, int* s_b, int* s_lo, int* s_nb,
-                                           int nvel = VD)
-{
-    if (PUSH) {
-        stage_field<PREC>(g, E, sm.sE);
-        if (PREC)
-            for (int i = threadIdx.x; i <= g.nv[0]; i += blockDim.x) sm.sRow[i] = rows_g[i];
-    }
-    grp.load(m, g, first, last, with_f, nvel);
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        if (first + k == base) s_b[0] = grp.p[k].bucket(g);
-        if (first + k == last) s_b[1] = grp.p[k].bucket(g);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) set_window(g, s_b[0], s_b[1], s_lo, s_nb);
-    __syncthreads();
-    const int nbw = *s_nb;
-    for (int i = threadIdx.x; i < nbw; i += blockDim.x) sm.hist[i] = 0;
-    __syncthreads();
-}
-
 // Per-thread aggregation of a group's buckets.  Consecutive markers of the
 // previous order come from one or two runs and land in a few new buckets, so a
 // thread keeps two "open" buckets with counts and gives each marker its rank
@@ -256,26 +228,28 @@ struct Agg {
 // ---------------------------------------------------------------------------
 // count pass
 // ---------------------------------------------------------------------------
+// One tile of the count pass: the thread's group of K consecutive markers
+// [first, first+K) of the tile [base, last] is in grp (previous order), the
+// field and drift table staged in LDS.
 template <int PREC, int VD, bool PUSH>
-__device__ __forceinline__ void count_block(const Geo& g, const typename MarkersOf<PREC>::T& m,
-                                            const double* __restrict__ E, const RowShift* __restrict__ rows_g,
-                                            double dtk, float bk, int* __restrict__ counts, int* __restrict__ tsum,
-                                            int* __restrict__ flags, int blk)
+__device__ __forceinline__ void count_tile(const Geo& g, const SortSmem<PREC>& sm, Group<PREC, VD, kCountMPT>& grp,
+                                           double dtk, float bk, int* __restrict__ counts, int* __restrict__ tsum,
+                                           int base, int last, int* s_b, int* s_lo, int* s_nb, int* s_tile, int& fl)
 {
     constexpr int K = kCountMPT;
-    extern __shared__ __align__(16) unsigned char smem[];
-    SortSmem<PREC> sm(smem, g);
-    __shared__ int s_b[2], s_lo, s_nb, s_flags, s_tile[8];
-    const int base = blk * kCountTile;
-    const int last = min(base + kCountTile, g.n) - 1;
     const int first = base + threadIdx.x * K;
-    if (threadIdx.x == 0) s_flags = 0;
-    Group<PREC, VD, K> grp;
-    // FP32 form: the bucket comes from the cell index, the push needs b[0] only
-    sort_setup<PREC, VD, K, PUSH>(g, sm, m, grp, base, first, last, false, E, rows_g, s_b, &s_lo, &s_nb,
-                                  PREC ? 1 : VD);
-    const int lo = s_lo, nbw = s_nb;
-    int fl = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (first + k == base) s_b[0] = grp.p[k].bucket(g);
+        if (first + k == last) s_b[1] = grp.p[k].bucket(g);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) set_window(g, s_b[0], s_b[1], s_lo, s_nb);
+    __syncthreads();
+    const int lo = *s_lo, nbw = *s_nb;
+    for (int i = threadIdx.x; i < nbw; i += blockDim.x) sm.hist[i] = 0;
+    if (threadIdx.x < 8) s_tile[threadIdx.x] = 0;
+    __syncthreads();
     int bkt[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -301,8 +275,6 @@ __device__ __forceinline__ void count_block(const Geo& g, const typename Markers
 #pragma unroll
     for (int k = 0; k < K; ++k)
         if (ag.tag[k] == 2) add(bkt[k], 1);
-    if (fl) atomicOr(&s_flags, fl);
-    if (threadIdx.x < 8) s_tile[threadIdx.x] = 0;
     __syncthreads();
     // flush the window; the same counts also go into per-scan-tile totals
     // (kScanTile buckets each), so the scan needs no separate reduction pass
@@ -317,16 +289,51 @@ __device__ __forceinline__ void count_block(const Geo& g, const typename Markers
     __syncthreads();
     const int ntile_win = (lo + nbw - 1) / kScanTile - tlo + 1;
     if (threadIdx.x < ntile_win && s_tile[threadIdx.x]) atomicAdd(&tsum[tlo + threadIdx.x], s_tile[threadIdx.x]);
+}
+
+template <int PREC>
+__device__ __forceinline__ void stage_tables(const Geo& g, const SortSmem<PREC>& sm, const double* E,
+                                             const RowShift* rows_g)
+{
+    stage_field<PREC>(g, E, sm.sE);
+    if (PREC)
+        for (int i = threadIdx.x; i <= g.nv[0]; i += blockDim.x) sm.sRow[i] = rows_g[i];
+}
+
+// Tile t of the count pass covers markers [t*kCountTile, ...); in the FP32
+// form the push needs the velocity offset b[0] only.
+__device__ __forceinline__ int count_tile_last(const Geo& g, int t) { return min(t * kCountTile + kCountTile, g.n) - 1; }
+
+// count pass of one block over one tile
+template <int PREC, int VD, bool PUSH>
+__device__ __forceinline__ void count_block(const Geo& g, const typename MarkersOf<PREC>::T& m,
+                                            const double* __restrict__ E, const RowShift* __restrict__ rows_g,
+                                            double dtk, float bk, int* __restrict__ counts, int* __restrict__ tsum,
+                                            int* __restrict__ flags, int blk)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    SortSmem<PREC> sm(smem, g);
+    __shared__ int s_b[2], s_lo, s_nb, s_flags, s_tile[8];
+    if (threadIdx.x == 0) s_flags = 0;
+    if (PUSH) stage_tables<PREC>(g, sm, E, rows_g);
+    Group<PREC, VD, kCountMPT> grp;
+    const int base = blk * kCountTile;
+    grp.load(m, g, base + threadIdx.x * kCountMPT, count_tile_last(g, blk), false, PREC ? 1 : VD);
+    int fl = 0;
+    count_tile<PREC, VD, PUSH>(g, sm, grp, dtk, bk, counts, tsum, base, count_tile_last(g, blk), s_b, &s_lo, &s_nb,
+                               s_tile, fl);
+    if (fl) atomicOr(&s_flags, fl);
+    __syncthreads();
     if (threadIdx.x == 0 && s_flags) atomicOr(flags, s_flags);
 }
 
 template <int PREC, int VD, bool PUSH>
 __global__ __launch_bounds__(kSortThreads) void k_count(Geo g, typename MarkersOf<PREC>::T m,
-                                                        const double* __restrict__ E,
-                                                        const RowShift* __restrict__ rows_g,
-                                                        double dtk, float bk,
-                                                        int* __restrict__ counts, int* __restrict__ tsum,
-                                                        int* __restrict__ flags)
+                                                         const double* __restrict__ E,
+                                                         const RowShift* __restrict__ rows_g,
+                                                         double dtk, float bk,
+                                                         int* __restrict__ counts, int* __restrict__ tsum,
+                                                         int* __restrict__ flags)
 {
     count_block<PREC, VD, PUSH>(g, m, E, rows_g, dtk, bk, counts, tsum, flags, blockIdx.x);
 }
@@ -339,28 +346,15 @@ __global__ __launch_bounds__(kSortThreads) void k_count(Geo g, typename MarkersO
 // consecutive ranks in their new run from the LDS atomics, so each store
 // instruction writes a few contiguous stretches instead of 64 scattered words.
 // ---------------------------------------------------------------------------
+// One tile of the scatter: the markers [base, last] of the previous order are
+// in p[] (lane-strided), the field and drift table staged in LDS.
 template <int PREC, int VD, bool PUSH>
-__device__ __forceinline__ void scatter_block(const Geo& g, const typename MarkersOf<PREC>::T& src,
-                                              const typename MarkersOf<PREC>::T& dst,
-                                              const double* __restrict__ E, const RowShift* __restrict__ rows_g,
-                                              double dtk, float bk, const int* __restrict__ offsets,
-                                              int* __restrict__ counts, int* __restrict__ flags, int blk)
+__device__ __forceinline__ void scatter_tile(const Geo& g, const SortSmem<PREC>& sm, Pay<PREC, VD>* p,
+                                             const typename MarkersOf<PREC>::T& dst, double dtk, float bk,
+                                             const int* __restrict__ offsets, int* __restrict__ counts,
+                                             int base, int last, int* s_b, int* s_lo, int* s_nb, int& fl)
 {
     constexpr int K = kSortMPT;
-    extern __shared__ __align__(16) unsigned char smem[];
-    SortSmem<PREC> sm(smem, g);
-    __shared__ int s_b[2], s_lo, s_nb, s_flags;
-    const int base = blk * kSortTile;
-    const int last = min(base + kSortTile, g.n) - 1;
-    if (threadIdx.x == 0) s_flags = 0;
-    if (PUSH) {
-        stage_field<PREC>(g, E, sm.sE);
-        if (PREC)
-            for (int i = threadIdx.x; i <= g.nv[0]; i += blockDim.x) sm.sRow[i] = rows_g[i];
-    }
-    Pay<PREC, VD> p[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) p[k].load(src, g, min(base + k * kSortThreads + (int)threadIdx.x, last), true);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int i = base + k * kSortThreads + threadIdx.x;
@@ -368,12 +362,11 @@ __device__ __forceinline__ void scatter_block(const Geo& g, const typename Marke
         if (i == last) s_b[1] = p[k].bucket(g);
     }
     __syncthreads();
-    if (threadIdx.x == 0) set_window(g, s_b[0], s_b[1], &s_lo, &s_nb);
+    if (threadIdx.x == 0) set_window(g, s_b[0], s_b[1], s_lo, s_nb);
     __syncthreads();
-    const int lo = s_lo, nbw = s_nb;
+    const int lo = *s_lo, nbw = *s_nb;
     for (int i = threadIdx.x; i < nbw; i += blockDim.x) sm.hist[i] = 0;
     __syncthreads();
-    int fl = 0;
     int bkt[K], rank[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -387,52 +380,87 @@ __device__ __forceinline__ void scatter_block(const Geo& g, const typename Marke
             if (rel >= 0 && rel < nbw) rank[k] = atomicAdd(&sm.hist[rel], 1);
         }
     }
-    // run bounds of every marker's bucket, loaded while slots are claimed
-    int rb[K], re[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int bq = bkt[k] < 0 ? 0 : bkt[k];
-        rb[k] = offsets[bq];
-        re[k] = offsets[bq + 1];
-    }
     __syncthreads();
     // claim each touched in-window bucket's slots: counts[] holds the slots
-    // still free, counting down from the run length
+    // still free, counting down from the run length, so a claim that starts
+    // at or above zero lies inside the run; the histogram entry becomes the
+    // first claimed position
     for (int i = threadIdx.x; i < nbw; i += blockDim.x) {
         const int c = sm.hist[i];
         if (c) {
             const int old = atomicSub(&counts[lo + i], c);
-            int start = old - c;
-            if (start < 0) { fl |= FLAG_SLOT; start = -1; }
-            sm.hist[i] = start;
+            const int start = old - c;
+            if (start < 0) fl |= FLAG_SLOT;
+            sm.hist[i] = start < 0 ? -1 : offsets[lo + i] + start;
         }
     }
     __syncthreads();
-    int slot[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        slot[k] = -1;
-        if (bkt[k] >= 0 && rank[k] >= 0) {
-            const int start = sm.hist[bkt[k] - lo];
-            slot[k] = start < 0 ? -1 : start + rank[k];
-        }
-    }
-    // markers outside the window (large velocity jumps) claim one slot each
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-        if (bkt[k] >= 0 && rank[k] < 0) slot[k] = atomicSub(&counts[bkt[k]], 1) - 1;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         if (bkt[k] < 0) continue;
-        const int dest = rb[k] + slot[k];
-        if (slot[k] < 0 || dest >= re[k]) { fl |= FLAG_SLOT; continue; }
+        int dest;
+        if (rank[k] >= 0) {
+            const int first = sm.hist[bkt[k] - lo];
+            dest = first < 0 ? -1 : first + rank[k];
+        } else {
+            // outside the window (a large velocity jump): one slot at a time
+            const int slot = atomicSub(&counts[bkt[k]], 1) - 1;
+            dest = slot < 0 ? -1 : offsets[bkt[k]] + slot;
+        }
+        if (dest < 0) { fl |= FLAG_SLOT; continue; }
         p[k].store(dst, g, dest);
     }
+}
+
+template <int PREC, int VD>
+__device__ __forceinline__ void load_tile(const typename MarkersOf<PREC>::T& src, const Geo& g, Pay<PREC, VD>* p,
+                                          int base, int last)
+{
+#pragma unroll
+    for (int k = 0; k < kSortMPT; ++k) p[k].load(src, g, min(base + k * kSortThreads + (int)threadIdx.x, last), true);
+}
+
+// scatter pass of one block over one tile (the batched kernel and the forms
+// without a tiled kernel)
+template <int PREC, int VD, bool PUSH>
+__device__ __forceinline__ void scatter_block(const Geo& g, const typename MarkersOf<PREC>::T& src,
+                                              const typename MarkersOf<PREC>::T& dst,
+                                              const double* __restrict__ E, const RowShift* __restrict__ rows_g,
+                                              double dtk, float bk, const int* __restrict__ offsets,
+                                              int* __restrict__ counts, int* __restrict__ flags, int blk)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    SortSmem<PREC> sm(smem, g);
+    __shared__ int s_b[2], s_lo, s_nb, s_flags;
+    const int base = blk * kSortTile;
+    const int last = min(base + kSortTile, g.n) - 1;
+    if (threadIdx.x == 0) s_flags = 0;
+    if (PUSH) stage_tables<PREC>(g, sm, E, rows_g);
+    Pay<PREC, VD> p[kSortMPT];
+    load_tile<PREC, VD>(src, g, p, base, last);
+    int fl = 0;
+    scatter_tile<PREC, VD, PUSH>(g, sm, p, dst, dtk, bk, offsets, counts, base, last, s_b, &s_lo, &s_nb, fl);
     if (fl) atomicOr(&s_flags, fl);
     __syncthreads();
     if (threadIdx.x == 0 && s_flags) atomicOr(flags, s_flags);
 }
 
+template <int PREC, int VD, bool PUSH>
+__global__ __launch_bounds__(kSortThreads) void k_scatter1(Geo g, typename MarkersOf<PREC>::T src,
+                                                           typename MarkersOf<PREC>::T dst,
+                                                           const double* __restrict__ E,
+                                                           const RowShift* __restrict__ rows_g,
+                                                           double dtk, float bk,
+                                                           const int* __restrict__ offsets,
+                                                           int* __restrict__ counts, int* __restrict__ flags)
+{
+    scatter_block<PREC, VD, PUSH>(g, src, dst, E, rows_g, dtk, bk, offsets, counts, flags, blockIdx.x);
+}
+
+// Tiled scatter: each block takes tiles blockIdx.x, blockIdx.x + gridDim.x,
+// ... and loads its next tile's markers while the current one is pushed,
+// ranked, claimed and stored, so the loads of one tile overlap the latency
+// chain of the previous one; the field and drift table are staged once.
 template <int PREC, int VD, bool PUSH>
 __global__ __launch_bounds__(kSortThreads) void k_scatter(Geo g, typename MarkersOf<PREC>::T src,
                                                           typename MarkersOf<PREC>::T dst,
@@ -442,7 +470,27 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(Geo g, typename Marker
                                                           const int* __restrict__ offsets,
                                                           int* __restrict__ counts, int* __restrict__ flags)
 {
-    scatter_block<PREC, VD, PUSH>(g, src, dst, E, rows_g, dtk, bk, offsets, counts, flags, blockIdx.x);
+    extern __shared__ __align__(16) unsigned char smem[];
+    SortSmem<PREC> sm(smem, g);
+    __shared__ int s_b[2], s_lo, s_nb, s_flags;
+    const int ntiles = (g.n + kSortTile - 1) / kSortTile;
+    if (threadIdx.x == 0) s_flags = 0;
+    if (PUSH) stage_tables<PREC>(g, sm, E, rows_g);
+    int fl = 0;
+    Pay<PREC, VD> p[kSortMPT], q[kSortMPT];
+    int t = blockIdx.x;
+    load_tile<PREC, VD>(src, g, p, t * kSortTile, min(t * kSortTile + kSortTile, g.n) - 1);
+    for (; t < ntiles; t += gridDim.x) {
+        const int tn = t + gridDim.x;
+        if (tn < ntiles) load_tile<PREC, VD>(src, g, q, tn * kSortTile, min(tn * kSortTile + kSortTile, g.n) - 1);
+        scatter_tile<PREC, VD, PUSH>(g, sm, p, dst, dtk, bk, offsets, counts, t * kSortTile,
+                                     min(t * kSortTile + kSortTile, g.n) - 1, s_b, &s_lo, &s_nb, fl);
+#pragma unroll
+        for (int k = 0; k < kSortMPT; ++k) p[k] = q[k];
+    }
+    if (fl) atomicOr(&s_flags, fl);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_flags) atomicOr(flags, s_flags);
 }
 
 // ---------------------------------------------------------------------------
@@ -615,22 +663,37 @@ static hipError_t launch_sort_t(const Geo& g, void* src, void* dst, const double
     using MT = typename MarkersOf<PREC>::T;
     MT s = *reinterpret_cast<MT*>(src);
     MT d = dst ? *reinterpret_cast<MT*>(dst) : s;
+    // The FP32 1D-1V form uses the tiled scatter (one block per resident slot,
+    // each walking several tiles and loading the next while working on the
+    // current one); the other forms hold more registers per marker and use
+    // one tile per block.
+    constexpr bool tiled = PREC == 1 && VD == 1;
     const int cblocks = (g.n + kCountTile - 1) / kCountTile;
-    const int sblocks = (g.n + kSortTile - 1) / kSortTile;
+    const int stiles = (g.n + kSortTile - 1) / kSortTile;
+    const int sblocks = tiled && g.sblocks > 0 ? std::min(stiles, g.sblocks) : stiles;
     const size_t smem = sort_smem<PREC>(g, push);
     if (g.n == 0 && phase != 1) return hipSuccess;   // the scan still runs: offsets become zero
     static int granted[4] = {0, 0, 0, 0};
     {
-        const void* fns[4] = {(const void*)k_count<PREC, VD, true>, (const void*)k_count<PREC, VD, false>,
-                              (const void*)k_scatter<PREC, VD, true>, (const void*)k_scatter<PREC, VD, false>};
+        const void* fns[4];
+        fns[0] = (const void*)k_count<PREC, VD, true>;
+        fns[1] = (const void*)k_count<PREC, VD, false>;
+        if constexpr (tiled) {
+            fns[2] = (const void*)k_scatter<PREC, VD, true>;
+            fns[3] = (const void*)k_scatter<PREC, VD, false>;
+        } else {
+            fns[2] = (const void*)k_scatter1<PREC, VD, true>;
+            fns[3] = (const void*)k_scatter1<PREC, VD, false>;
+        }
         for (int i = 0; i < 4; ++i) {
             hipError_t e = ensure_lds(fns[i], smem, granted[i]);
             if (e != hipSuccess) return e;
         }
     }
+    const dim3 bl(kSortThreads);
     if (phase == 0) {
-        if (push) hipLaunchKernelGGL((k_count<PREC, VD, true>), dim3(cblocks), dim3(kSortThreads), smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags);
-        else hipLaunchKernelGGL((k_count<PREC, VD, false>), dim3(cblocks), dim3(kSortThreads), smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags);
+        if (push) hipLaunchKernelGGL((k_count<PREC, VD, true>), dim3(cblocks), bl, smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags);
+        else hipLaunchKernelGGL((k_count<PREC, VD, false>), dim3(cblocks), bl, smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags);
     } else if (phase == 1) {
         // tile_sums: this sort's totals; tile_next: the other parity, cleared here
         const int nbt = g.nb + 1;
@@ -643,8 +706,13 @@ static hipError_t launch_sort_t(const Geo& g, void* src, void* dst, const double
         hipLaunchKernelGGL(k_scan_apply, dim3(ntiles), dim3(kScanThreads), 0, st, counts, nbt, tile_sums, scanned,
                            tile_next, offsets);
     } else {
-        if (push) hipLaunchKernelGGL((k_scatter<PREC, VD, true>), dim3(sblocks), dim3(kSortThreads), smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags);
-        else hipLaunchKernelGGL((k_scatter<PREC, VD, false>), dim3(sblocks), dim3(kSortThreads), smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags);
+        if constexpr (tiled) {
+            if (push) hipLaunchKernelGGL((k_scatter<PREC, VD, true>), dim3(sblocks), bl, smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags);
+            else hipLaunchKernelGGL((k_scatter<PREC, VD, false>), dim3(sblocks), bl, smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags);
+        } else {
+            if (push) hipLaunchKernelGGL((k_scatter1<PREC, VD, true>), dim3(sblocks), bl, smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags);
+            else hipLaunchKernelGGL((k_scatter1<PREC, VD, false>), dim3(sblocks), bl, smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags);
+        }
     }
     return hipGetLastError();
 }
@@ -706,6 +774,24 @@ int sort_blocks(const Geo& g, int phase)
     if (phase == 0) return (g.n + kCountTile - 1) / kCountTile;
     if (phase == 1) return (g.nb + 1 + kScanTile - 1) / kScanTile;
     return (g.n + kSortTile - 1) / kSortTile;
+}
+
+// Blocks of the tiled scatter that fit on one CU at once for g's LDS size
+// (0 where the form has no tiled scatter); host side.
+int scatter_blocks_per_cu(const Geo& g)
+{
+    if (!(g.prec == 1 && g.vdim == 1)) return 0;
+    const size_t smem = sort_smem<1>(g, true);
+    static int granted = 0;
+    int per_cu = 0;
+    if (ensure_lds((const void*)k_scatter<1, 1, true>, smem, granted) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_scatter<1, 1, true>, kSortThreads, smem) !=
+            hipSuccess ||
+        per_cu <= 0) {
+        (void)hipGetLastError();
+        per_cu = 4;
+    }
+    return per_cu;
 }
 
 // LDS of the count and scatter blocks for one instance (host side).
