@@ -221,8 +221,7 @@ void make_layout(const avl_config* c, const Geo& g, Layout* L)
 // Shrink LDS-sized parameters to what one block may use on this device.
 void fit_lds(Geo* g, int lds)
 {
-    const int esz = g->prec ? 4 : 8;
-    (void)esz;
+    const int esz = 8;                    // staged field: double, or the FP32 form's (kick, difference) pair
     if (g->vdim == 1) g->cap = recon_capacity(g->prec);
     const int fixed = esz * g->nx + (g->prec ? (int)sizeof(RowShift) * (g->nv[0] + 1) : 0) + 64;
     int bins = (lds - fixed) / 4;

@@ -212,33 +212,32 @@ __device__ __forceinline__ int bucket32(const Geo& g, int cell)
 // dv (b carries into the dual row), position in units of dx (a carries into
 // the column, with periodic wrap); the large per-row part of the x shift comes
 // from the FP64-built table so no absolute coordinate is ever held in FP32.
+// sE[i] holds the kick in units of dv at cell centre i, e_i = (q/m) E_i dt /
+// dv (times the kick fraction), and its forward difference e_{i+1} - e_i
+// (periodic), so the linear gather is one LDS read and one multiply-add.
 template <int VD>
-__device__ __forceinline__ void push32(const Geo& g, const float* sE, const RowShift* rows,
-                                       float bk, int& cell, float& a, float& b, int& flags)
+__device__ __forceinline__ void push32(const Geo& g, const float2* sE, const RowShift* rows,
+                                       int& cell, float& a, float& b, int& flags)
 {
     int ix = cell & (g.nx - 1);
     int r = cell >> g.lognx;
     int jx, rest;
     if (VD == 1) { jx = r; rest = 0; }
     else { jx = (r % g.jrange) - g.jpad; rest = r / g.jrange; }
-    int ib = (ix + 1) & (g.nx - 1);
-    float El = (1.0f - a) * sE[ix] + a * sE[ib];
-    float bn = b + El * bk;
+    const float2 e = sE[ix];
+    float bn = b + (e.x + a * e.y);
     float fl = floorf(bn);
     jx += (int)fl;
     bn -= fl;
     if (bn >= 1.0f) { bn -= 1.0f; jx += 1; }
-    int whole;
-    float frac;
-    if (jx >= 0 && jx <= g.nv[0]) {
-        whole = rows[jx].whole;
-        frac = rows[jx].frac;
-    } else {
-        float P = ((float)(jx - 1) + g.c0f) * g.gam;
-        float Pf = floorf(P);
-        whole = (int)Pf;
-        frac = P - Pf;
-    }
+    // rows inside the table take its FP64-built shift, rows beyond it the FP32
+    // formula; both are formed and one selected, without a branch
+    const bool in_table = jx >= 0 && jx <= g.nv[0];
+    const RowShift rs = rows[min(max(jx, 0), g.nv[0])];
+    const float P = ((float)(jx - 1) + g.c0f) * g.gam;
+    const float Pf = floorf(P);
+    const int whole = in_table ? rs.whole : (int)Pf;
+    const float frac = in_table ? rs.frac : P - Pf;
     float an = a + frac + bn * g.gam;
     float ca = floorf(an);
     an -= ca;
@@ -246,14 +245,17 @@ __device__ __forceinline__ void push32(const Geo& g, const float* sE, const RowS
     ix = (ix + whole + (int)ca) & (g.nx - 1);
     if (VD == 1) {
         const int lim = (1 << (30 - g.lognx));
-        if (jx < -lim || jx > lim) { flags |= FLAG_RANGE; jx = jx < 0 ? -lim : lim; }
-        cell = jx * g.nx + ix;
+        const int jc = min(max(jx, -lim), lim);
+        if (jc != jx) flags |= FLAG_RANGE;
+        cell = (int)((unsigned)jc << g.lognx) + ix;
     } else {
-        int jj = jx + g.jpad;
-        if (jj < 0 || jj >= g.jrange) { flags |= FLAG_RANGE; jj = jj < 0 ? 0 : g.jrange - 1; }
-        cell = (rest * g.jrange + jj) * g.nx + ix;
+        const int jj = jx + g.jpad;
+        const int jc = min(max(jj, 0), g.jrange - 1);
+        if (jc != jj) flags |= FLAG_RANGE;
+        cell = (rest * g.jrange + jc) * g.nx + ix;
     }
-    if (!(an == an) || !(bn == bn)) flags |= FLAG_NONFINITE;
+    // an and bn lie in [0, 1) unless a NaN or infinity came in
+    if (!(an + bn == an + bn)) flags |= FLAG_NONFINITE;
     a = an;
     b = bn;
 }

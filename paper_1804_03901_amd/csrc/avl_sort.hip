@@ -76,15 +76,15 @@ template <int VD> struct Pay<1, VD> {
         m.f[i] = f;
         if (m.id) m.id[i] = id;
     }
-    __device__ void push(const Geo& g, const float* sE, const RowShift* rows, double, float bk, int& flags) {
-        push32<VD>(g, sE, rows, bk, cell, a, b[0], flags);
+    __device__ void push(const Geo& g, const float2* sE, const RowShift* rows, double, float, int& flags) {
+        push32<VD>(g, sE, rows, cell, a, b[0], flags);
     }
     __device__ int bucket(const Geo& g) const { return bucket32<VD>(g, cell); }
 };
 
 template <int PREC> struct MarkersOf;
 template <> struct MarkersOf<0> { using T = M64; using E = double; };
-template <> struct MarkersOf<1> { using T = M32; using E = float; };
+template <> struct MarkersOf<1> { using T = M32; using E = float2; };   // E: staged field (kick, difference)
 
 // K consecutive elements starting at a 16-byte aligned address, as 16-byte loads.
 template <typename T, int K>
@@ -182,10 +182,44 @@ __device__ __forceinline__ void set_window(const Geo& g, int b0, int b1, int* s_
     *s_nb = (hi - lo + 1) << g.lognx;
 }
 
+// Stage the field and, in the FP32 form, the drift table into LDS.  The FP64
+// path stages E itself; the FP32 form stages the kick in units of dv,
+// e_i = E_i * bk rounded once from FP64, with its forward difference
+// e_{i+1} - e_i.  Each thread issues all its loads before its first LDS
+// store, so staging costs one round trip to L2 instead of one per element.
 template <int PREC>
-__device__ void stage_field(const Geo& g, const double* E, typename MarkersOf<PREC>::E* sE)
+__device__ __forceinline__ void stage_tables(const Geo& g, typename MarkersOf<PREC>::E* sE, RowShift* sRow,
+                                             const double* __restrict__ E, const RowShift* __restrict__ rows_g,
+                                             float bk)
 {
-    for (int i = threadIdx.x; i < g.nx; i += blockDim.x) sE[i] = (typename MarkersOf<PREC>::E)E[i];
+    constexpr int U = 8;
+    const int nr = PREC ? g.nv[0] + 1 : 0;
+    const int span = U * (int)blockDim.x;
+    const int ntot = max(g.nx, nr);
+    for (int i0 = 0; i0 < ntot; i0 += span) {
+        double e[U], e1[U];
+        RowShift r[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
+            e[u] = i < g.nx ? E[i] : 0.0;
+            if (PREC) {
+                e1[u] = i < g.nx ? E[(i + 1) & (g.nx - 1)] : 0.0;
+                r[u] = i < nr ? rows_g[i] : RowShift{0, 0.0f};
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * (int)blockDim.x + (int)threadIdx.x;
+            if constexpr (PREC) {
+                const float k0 = (float)(e[u] * (double)bk), k1 = (float)(e1[u] * (double)bk);
+                if (i < g.nx) sE[i] = make_float2(k0, k1 - k0);
+                if (i < nr) sRow[i] = r[u];
+            } else {
+                if (i < g.nx) sE[i] = e[u];
+            }
+        }
+    }
 }
 
 template <int PREC>
@@ -253,11 +287,11 @@ __device__ __forceinline__ void count_tile(const Geo& g, const SortSmem<PREC>& s
     int bkt[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        bkt[k] = -1;
-        if (first + k <= last) {
-            if (PUSH) grp.p[k].push(g, sm.sE, sm.sRow, dtk, bk, fl);
-            bkt[k] = grp.p[k].bucket(g);
-        }
+        // FP32 form: past the last marker the group holds copies of it, and
+        // pushing them too lets the compiler interleave the markers' LDS
+        // round trips; they are not counted
+        if (PUSH && (PREC == 1 || first + k <= last)) grp.p[k].push(g, sm.sE, sm.sRow, dtk, bk, fl);
+        bkt[k] = first + k <= last ? grp.p[k].bucket(g) : -1;
     }
     Agg<K> ag;
     ag.build(bkt);
@@ -291,15 +325,6 @@ __device__ __forceinline__ void count_tile(const Geo& g, const SortSmem<PREC>& s
     if (threadIdx.x < ntile_win && s_tile[threadIdx.x]) atomicAdd(&tsum[tlo + threadIdx.x], s_tile[threadIdx.x]);
 }
 
-template <int PREC>
-__device__ __forceinline__ void stage_tables(const Geo& g, const SortSmem<PREC>& sm, const double* E,
-                                             const RowShift* rows_g)
-{
-    stage_field<PREC>(g, E, sm.sE);
-    if (PREC)
-        for (int i = threadIdx.x; i <= g.nv[0]; i += blockDim.x) sm.sRow[i] = rows_g[i];
-}
-
 // Tile t of the count pass covers markers [t*kCountTile, ...); in the FP32
 // form the push needs the velocity offset b[0] only.
 __device__ __forceinline__ int count_tile_last(const Geo& g, int t) { return min(t * kCountTile + kCountTile, g.n) - 1; }
@@ -315,7 +340,7 @@ __device__ __forceinline__ void count_block(const Geo& g, const typename Markers
     SortSmem<PREC> sm(smem, g);
     __shared__ int s_b[2], s_lo, s_nb, s_flags, s_tile[8];
     if (threadIdx.x == 0) s_flags = 0;
-    if (PUSH) stage_tables<PREC>(g, sm, E, rows_g);
+    if (PUSH) stage_tables<PREC>(g, sm.sE, sm.sRow, E, rows_g, bk);
     Group<PREC, VD, kCountMPT> grp;
     const int base = blk * kCountTile;
     grp.load(m, g, base + threadIdx.x * kCountMPT, count_tile_last(g, blk), false, PREC ? 1 : VD);
@@ -435,7 +460,7 @@ __device__ __forceinline__ void scatter_block(const Geo& g, const typename Marke
     const int base = blk * kSortTile;
     const int last = min(base + kSortTile, g.n) - 1;
     if (threadIdx.x == 0) s_flags = 0;
-    if (PUSH) stage_tables<PREC>(g, sm, E, rows_g);
+    if (PUSH) stage_tables<PREC>(g, sm.sE, sm.sRow, E, rows_g, bk);
     Pay<PREC, VD> p[kSortMPT];
     load_tile<PREC, VD>(src, g, p, base, last);
     int fl = 0;
@@ -475,7 +500,7 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(Geo g, typename Marker
     __shared__ int s_b[2], s_lo, s_nb, s_flags;
     const int ntiles = (g.n + kSortTile - 1) / kSortTile;
     if (threadIdx.x == 0) s_flags = 0;
-    if (PUSH) stage_tables<PREC>(g, sm, E, rows_g);
+    if (PUSH) stage_tables<PREC>(g, sm.sE, sm.sRow, E, rows_g, bk);
     int fl = 0;
     Pay<PREC, VD> p[kSortMPT], q[kSortMPT];
     int t = blockIdx.x;
@@ -506,9 +531,7 @@ __global__ __launch_bounds__(kSortThreads) void k_push(Geo g, typename MarkersOf
     extern __shared__ __align__(16) unsigned char smem[];
     ET* sE = reinterpret_cast<ET*>(smem);
     RowShift* sRow = reinterpret_cast<RowShift*>(smem + sizeof(ET) * g.nx);
-    stage_field<PREC>(g, E, sE);
-    if (PREC)
-        for (int i = threadIdx.x; i <= g.nv[0]; i += blockDim.x) sRow[i] = rows_g[i];
+    stage_tables<PREC>(g, sE, sRow, E, rows_g, bk);
     __syncthreads();
     int fl = 0;
     const int base = blockIdx.x * kSortTile;
@@ -650,7 +673,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int* __restri
 template <int PREC>
 static size_t sort_smem(const Geo& g, bool push)
 {
-    size_t e = push ? (PREC ? sizeof(float) : sizeof(double)) * g.nx : (PREC ? sizeof(float) : sizeof(double)) * g.nx;
+    (void)push;
+    size_t e = sizeof(typename MarkersOf<PREC>::E) * g.nx;
     size_t r = PREC ? sizeof(RowShift) * (g.nv[0] + 1) : 0;
     return e + r + sizeof(int) * g.hist_bins;
 }
@@ -827,7 +851,7 @@ hipError_t launch_push(const Geo& g, void* m, const double* E, const RowShift* r
 {
     if (g.n == 0) return hipSuccess;
     const int blocks = (g.n + kSortTile - 1) / kSortTile;
-    const size_t smem = (g.prec ? sizeof(float) : sizeof(double)) * g.nx + (g.prec ? sizeof(RowShift) * (g.nv[0] + 1) : 0);
+    const size_t smem = (g.prec ? sizeof(float2) : sizeof(double)) * g.nx + (g.prec ? sizeof(RowShift) * (g.nv[0] + 1) : 0);
     if (g.prec == 0 && g.vdim == 1) hipLaunchKernelGGL((k_push<0, 1>), dim3(blocks), dim3(kSortThreads), smem, st, g, *reinterpret_cast<M64*>(m), E, rows, dtk, bk, flags);
     else if (g.prec == 0) hipLaunchKernelGGL((k_push<0, 3>), dim3(blocks), dim3(kSortThreads), smem, st, g, *reinterpret_cast<M64*>(m), E, rows, dtk, bk, flags);
     else if (g.vdim == 1) hipLaunchKernelGGL((k_push<1, 1>), dim3(blocks), dim3(kSortThreads), smem, st, g, *reinterpret_cast<M32*>(m), E, rows, dtk, bk, flags);
