@@ -186,6 +186,25 @@ int avl_set_markers(avl_handle* h, const double* x, const double* v, const doubl
 /* Copy the handle's current field (nx doubles) and charge density. */
 int avl_get_field(avl_handle* h, double* E_out, double* rho_out);
 
+/* Thermodynamic and field diagnostics of the current state (the quantities
+ * the paper writes per output step, Sec. 3.4 "Thermodynamical quantities" and
+ * "Spatial output"), from the last reconstruction f, its charge density rho
+ * and the field E solved from it (AVL_ESTATE otherwise, e.g. after a push
+ * without a new reconstruction and solve).  Cell-centre velocities v_g,
+ * dV = dx * prod(dv):
+ *   out[0] Ee    = sum_i E_i^2 dx / (2 c_p)            (field energy)
+ *   out[1] Ekin  = m/2 * sum_g f_g |v_g|^2 dV          (kinetic energy)
+ *   out[2] Etot  = Ee + Ekin
+ *   out[3] N     = sum_g f_g dV                        (integral of f)
+ *   out[4] S     = sum_{g: f_g > 0} f_g log(f_g) dV    (entropy integral as the paper defines it)
+ *   out[5] P     = m * sum_g f_g v_x,g dV              (momentum)
+ * j_out (nx doubles, may be NULL): current density j_i = q prod(dv) sum_j v_x f_ij.
+ * drho_out (nx doubles, may be NULL): the field solver's residual charge
+ * (rho_i - mean(rho)) - (E_{i+1} - E_{i-1}) / (2 dx c_p) (the mean is the
+ * neutralising background; centred difference, periodic).
+ * out: 6 doubles of device memory.  Sums are FP64 in a fixed order. */
+int avl_diagnostics(avl_handle* h, double* out, double* j_out, double* drho_out);
+
 /* Number of full steps taken since the markers were loaded. */
 int64_t avl_step_count(const avl_handle* h);
 

@@ -66,6 +66,8 @@ def _load():
             lib.orc_field_energy.restype = d
             lib.orc_energy.argtypes = [g, pd, pd, pd, pd]
             lib.orc_energy.restype = None
+            lib.orc_residual.argtypes = [ctypes.c_int, d, d, pd, pd, pd]
+            lib.orc_residual.restype = None
             lib.orc_push.argtypes = [g, L, pd, pd, pd, d]
             lib.orc_push.restype = None
             lib.orc_run.argtypes = [g, L, pd, pd, pd, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -170,6 +172,13 @@ def energy(grid: Grid, fg):
     a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     lib.orc_energy(ctypes.byref(grid.c), _p(fg), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
     return a.value, b.value, c.value
+
+
+def residual(nx, L, cp, rho, E):
+    """Residual charge (rho - mean rho) - centred dE/dx / cp on the nx cells."""
+    out = np.empty(int(nx))
+    _load().orc_residual(int(nx), float(L), float(cp), _p(_f64(rho)), _p(_f64(E)), _p(out))
+    return out
 
 
 def push(grid: Grid, x, v, E, kick=1.0):

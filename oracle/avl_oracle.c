@@ -251,6 +251,23 @@ double orc_field_energy(int nx, double L, double cp, const double *E)
     return s * (L / nx) / (2.0 * cp);
 }
 
+/* Residual charge of the field solve (Sec. 3.4, spatial output): the charge
+ * density not accounted for by the field, with the divergence of E taken as
+ * a centred difference on the periodic grid and the neutralising background
+ * (minus the mean of rho) added to rho:
+ *   drho_i = (rho_i - mean(rho)) - (E_{i+1} - E_{i-1}) / (2 dx cp). */
+void orc_residual(int nx, double L, double cp, const double *rho, const double *E, double *drho)
+{
+    double dx = L / nx;
+    double mean = 0.0;
+    for (int i = 0; i < nx; ++i) mean += rho[i];
+    mean /= nx;
+    for (int i = 0; i < nx; ++i) {
+        int ip = (i + 1) % nx, im = (i + nx - 1) % nx;
+        drho[i] = (rho[i] - mean) - (E[ip] - E[im]) / (2.0 * dx * cp);
+    }
+}
+
 /* Kinetic energy, particle number and coarse-grained entropy from the grid f
  * (Sec. 3.4): Ekin = (m/2) sum |v_j|^2 f dx dV, Ntot = sum f dx dV,
  * S = sum f log f dx dV over cells with f > 0 (sign as printed). */

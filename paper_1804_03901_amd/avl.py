@@ -56,7 +56,10 @@ EXPORTS = ["avl_workspace_bytes", "avl_init", "avl_push", "avl_sort", "avl_recon
            "avl_step_count", "avl_check", "avl_set_stream", "avl_timing", "avl_kernel_time", "avl_kernel_bytes",
            "avl_copy_probe", "avl_strerror", "avl_destroy", "avl_batch_workspace_bytes", "avl_batch_init",
            "avl_batch_step", "avl_batch_instance", "avl_batch_count", "avl_batch_check", "avl_batch_destroy",
-           "avl_adjoint_workspace_bytes", "avl_adjoint"]
+           "avl_adjoint_workspace_bytes", "avl_adjoint", "avl_diagnostics"]
+
+# avl_diagnostics output slots
+DIAG_NAMES = ("Ee", "Ekin", "Etot", "N", "S", "P")
 
 
 def load(path: str = LIB_PATH):
@@ -82,6 +85,7 @@ def load(path: str = LIB_PATH):
     lib.avl_get_markers.argtypes = [vp, vp, vp, vp]
     lib.avl_set_markers.argtypes = [vp, vp, vp, vp]
     lib.avl_get_field.argtypes = [vp, vp, vp]
+    lib.avl_diagnostics.argtypes = [vp, vp, vp, vp]
     lib.avl_step_count.argtypes = [vp]
     lib.avl_step_count.restype = c.c_int64
     lib.avl_check.argtypes = [vp]
@@ -210,6 +214,10 @@ def avl_set_markers(h, x, v, f):
 
 def avl_get_field(h, E_out=None, rho_out=None):
     return _ck(load().avl_get_field(h, _ptr(E_out), _ptr(rho_out)), "avl_get_field")
+
+
+def avl_diagnostics(h, out, j_out=None, drho_out=None):
+    return _ck(load().avl_diagnostics(h, _ptr(out), _ptr(j_out), _ptr(drho_out)), "avl_diagnostics")
 
 
 def avl_step_count(h) -> int:
@@ -387,6 +395,17 @@ class Simulation:
         rho = self._empty(self.w.nx)
         avl_get_field(self.h, E, rho)
         return E, rho
+
+    def diagnostics(self, spatial: bool = False):
+        """{Ee, Ekin, Etot, N, S, P} of the current state as floats; with
+        spatial=True also the current density j(x) and the solver's residual
+        charge (device tensors of nx doubles)."""
+        out = self._empty(len(DIAG_NAMES))
+        j = self._empty(self.w.nx) if spatial else None
+        dr = self._empty(self.w.nx) if spatial else None
+        avl_diagnostics(self.h, out, j, dr)
+        vals = dict(zip(DIAG_NAMES, out.cpu().tolist()))
+        return (vals, j, dr) if spatial else vals
 
     def check(self):
         _ck(avl_check(self.h), "avl_check")

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libavl.so")
-SOURCES = ["avl_api.hip", "avl_sort.hip", "avl_recon.hip", "avl_recon3.hip", "avl_field.hip", "avl_adjoint.hip"]
+SOURCES = ["avl_api.hip", "avl_sort.hip", "avl_recon.hip", "avl_recon3.hip", "avl_field.hip", "avl_adjoint.hip", "avl_diag.hip"]
 ARCH = os.environ.get("AVL_OFFLOAD_ARCH", "gfx950")
 
 

@@ -45,6 +45,9 @@ hipError_t launch_adj_mu(int nx, const double* E, double w, double* mu_dep, doub
 int sort_blocks(const Geo& g, int phase);
 size_t sort_lds(const Geo& g);
 int scatter_blocks_per_cu(const Geo& g);
+int diag_chunks(const Geo& g);
+hipError_t launch_diag(const Geo& g, const void* fgrid, const double* rho, const double* E, double mass,
+                       double* part, double* out, double* j_out, double* drho_out, hipStream_t st);
 hipError_t launch_sort_batch(int prec, const BInst* tab, const int* pre, int ninst, int blocks, size_t smem, int cur,
                              hipStream_t st, int phase);
 hipError_t launch_recon_batch(int prec, int kahan, const BInst* tab, const int* pre, int ninst, int tasks, int cur,
@@ -64,7 +67,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
     size_t markers[2], counts, offsets, tile_sums, fgrid, rho_part, rho_slices, rho, E, tw, green, rows, diag, ctr, flags, bad,
-        scratch3, total;
+        scratch3, diag_part, total;
 };
 
 int ilog2(int v)
@@ -215,6 +218,7 @@ void make_layout(const avl_config* c, const Geo& g, Layout* L)
     L->flags = take(sizeof(int));
     L->bad = take(sizeof(int));
     L->scratch3 = take(g.vdim == 3 ? recon3_scratch_bytes(g) : 0);
+    L->diag_part = take(sizeof(double) * 4 * (size_t)g.nx * diag_chunks(g));
     L->total = off;
 }
 
@@ -787,6 +791,15 @@ int avl_get_field(avl_handle* h, double* E_out, double* rho_out)
         if (!h->have_rho) return AVL_ESTATE;
         AVL_TRY(hipMemcpyAsync(rho_out, h->rho, sizeof(double) * h->g.nx, hipMemcpyDeviceToDevice, h->st));
     }
+    return AVL_OK;
+}
+
+int avl_diagnostics(avl_handle* h, double* out, double* j_out, double* drho_out)
+{
+    if (!h || !out) return AVL_EINVAL;
+    if (!h->have_f || !h->have_rho || !h->have_E) return AVL_ESTATE;
+    AVL_TRY(launch_diag(h->g, h->fgrid, h->rho, h->E, h->cfg.m, (double*)(h->ws + h->lay.diag_part), out, j_out,
+                        drho_out, h->st));
     return AVL_OK;
 }
 

@@ -34,6 +34,8 @@ constexpr int kDiagCap = 4096;                            // per-step diagnostic
 constexpr int kFieldThreads = 1024;                      // threads of a field-solve block
 constexpr int kMaxFieldSlices = 64;                       // chunk slices of the rho reduction
 constexpr int kMaxNx = 4096;
+constexpr int kDiagThreads = 256;                        // columns per diagnostics block
+constexpr int kDiagBlocks = 1024;                        // target blocks of the diagnostics pass
 
 struct Geo {
     int vdim, prec;

@@ -264,6 +264,30 @@ def batched_scan(count: int = 64, seed: int = 4000, steps: int = 500, ppc: int =
     return out
 
 
+def paper_landau(ppc: int = 4, steps: int = 400, seed: int = 1301) -> Workload:
+    """The paper's Landau-damping test (Sec. 4.2): box L = 5 pi (longest mode
+    k = 0.4), 5% cosine density perturbation of a unit Maxwellian, Nx = 512,
+    Nv = 6600 cells on [-5, 5] (a velocity range of ten thermal speeds),
+    dt = 0.1, immobile neutralising ions."""
+    return Workload(
+        name=f"paper_landau_1d1v_nx512_nv6600_ppc{ppc}", vdim=1, nx=512, nv=(6600, 1, 1),
+        L=5.0 * math.pi, vmin=(-5.0, 0, 0), vmax=(5.0, 0, 0), ppc=ppc, dt=0.1,
+        steps=steps, seed=seed, populations=(Population(1.0),),
+        mode_numbers=(1,), mode_amplitude=0.05, random_phases=False)
+
+
+def langmuir_noise(nx: int = 256, nv: int = 256, ppc: int = 4, modes: int = 16, amplitude: float = 1e-3,
+                   steps: int = 2048, seed: int = 1214) -> Workload:
+    """A thermal plasma seeded with small density noise in its longest modes
+    (k_m = 0.05 m, m = 1..modes, random phases) for the (k, omega) spectrum of
+    Langmuir waves (Sec. 4.1); L = 40 pi, v on [-6, 6], dt = 0.1."""
+    return Workload(
+        name=f"langmuir_1d1v_nx{nx}_nv{nv}_ppc{ppc}", vdim=1, nx=nx, nv=(nv, 1, 1),
+        L=40.0 * math.pi, vmin=(-6.0, 0, 0), vmax=(6.0, 0, 0), ppc=ppc, dt=0.1,
+        steps=steps, seed=seed, populations=(Population(1.0),),
+        mode_numbers=tuple(range(1, modes + 1)), mode_amplitude=amplitude, random_phases=True)
+
+
 def adjoint_case() -> Workload:
     return bump_on_tail(nx=1024, nv=512, ppc=8, seed=5, steps=500)
 
@@ -273,4 +297,6 @@ WORKLOADS = {
     "bump_on_tail": bump_on_tail,
     "two_stream_3v": two_stream_3v,
     "adjoint": adjoint_case,
+    "paper_landau": paper_landau,
+    "langmuir": langmuir_noise,
 }
