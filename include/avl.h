@@ -103,6 +103,12 @@ typedef struct avl_config {
                             them beyond summation order):
                             [0] target velocity rows per 1D-1V reconstruction task, 1..256;
                             [1]..[3] reserved, must be 0 */
+    double B[3];         /* uniform background magnetic field (1D-3V, AVL_FP64 only; all zero
+                            otherwise): the acceleration is (q/m)(E + v x B), E along x, and
+                            the push is the Boris scheme (Sec. 2, magnetised 1D-3V: a half
+                            electric kick, a rotation about B, a half electric kick).  The
+                            gyration must take at least 2 pi steps, |q/m| |B| dt <= 1
+                            (AVL_EINVAL otherwise); AVL_ENOTSUP with AVL_FP32 */
 } avl_config;
 
 typedef struct avl_handle avl_handle;

@@ -28,7 +28,7 @@ class OrcGrid(ctypes.Structure):
         ("pad_", ctypes.c_int32),
         ("L", ctypes.c_double), ("vmin", ctypes.c_double * 3), ("vmax", ctypes.c_double * 3),
         ("dt", ctypes.c_double), ("q", ctypes.c_double), ("m", ctypes.c_double),
-        ("cp", ctypes.c_double),
+        ("cp", ctypes.c_double), ("B", ctypes.c_double * 3),
     ]
 
 
@@ -87,19 +87,20 @@ def _p(a):
 class Grid:
     """Grid and species constants, mirrored from an ``inputs.Workload`` or given directly."""
 
-    def __init__(self, vdim, nx, nv, L, vmin, vmax, dt=0.1, q=-1.0, m=1.0, cp=1.0):
+    def __init__(self, vdim, nx, nv, L, vmin, vmax, dt=0.1, q=-1.0, m=1.0, cp=1.0, B=(0.0, 0.0, 0.0)):
         nv = tuple(nv) + (1,) * (3 - len(tuple(nv)))
         vmin = tuple(vmin) + (0.0,) * (3 - len(tuple(vmin)))
         vmax = tuple(vmax) + (0.0,) * (3 - len(tuple(vmax)))
         self.vdim, self.nx, self.nv, self.L = int(vdim), int(nx), nv, float(L)
         self.vmin, self.vmax, self.dt, self.q, self.m, self.cp = vmin, vmax, float(dt), float(q), float(m), float(cp)
+        self.B = tuple(float(b) for b in B)
         self.c = OrcGrid(self.vdim, self.nx, (ctypes.c_int32 * 3)(*nv), 0, self.L,
                          (ctypes.c_double * 3)(*vmin), (ctypes.c_double * 3)(*vmax),
-                         self.dt, self.q, self.m, self.cp)
+                         self.dt, self.q, self.m, self.cp, (ctypes.c_double * 3)(*self.B))
 
     @classmethod
     def from_workload(cls, w):
-        return cls(w.vdim, w.nx, w.nv, w.L, w.vmin, w.vmax, w.dt, w.q, w.m, w.c_p)
+        return cls(w.vdim, w.nx, w.nv, w.L, w.vmin, w.vmax, w.dt, w.q, w.m, w.c_p, getattr(w, "B", (0.0, 0.0, 0.0)))
 
     @property
     def n_cells(self):

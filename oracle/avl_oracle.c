@@ -44,6 +44,7 @@ typedef struct {
     double q;          /* species charge (normalised: -1 for electrons) */
     double m;          /* species mass */
     double cp;         /* Poisson constant: 4*pi in CGS, 1 in normalised units */
+    double B[3];       /* uniform background magnetic field (1D-3V), zero otherwise */
 } orc_grid;
 
 static const double ORC_PI = 3.14159265358979323846;
@@ -311,12 +312,37 @@ void orc_push(const orc_grid *g, long n, double *x, double *v, const double *E, 
 {
     double dx = g->L / g->nx;
     double qm = g->q / g->m;
+    double tau = g->dt * kick;
+    double bmag = sqrt(g->B[0] * g->B[0] + g->B[1] * g->B[1] + g->B[2] * g->B[2]);
+    int magnetic = g->vdim == 3 && bmag > 0.0;
     for (long l = 0; l < n; ++l) {
         long i0;
         double a;
         cic_axis(x[l], 0.0, dx, &i0, &a);
         double El = (1.0 - a) * E[wrap_x(i0, g->nx)] + a * E[wrap_x(i0 + 1, g->nx)];
-        v[l] = v[l] + qm * El * (g->dt * kick);
+        if (magnetic) {
+            /* Boris (1970), the paper's magnetised push: half an electric kick,
+             * then the gyration, then the second half kick.  The exact solution
+             * of dv/dt = (q/m) v x B over tau turns v about b = B/|B| by the
+             * angle -(q/m)|B| tau; the scheme's angle is
+             * theta = -2 atan((q/m)|B| tau / 2).  Written here as a rotation
+             * (Rodrigues' formula: v cos(theta) + (b x v) sin(theta)
+             * + b (b.v)(1 - cos(theta))). */
+            double h = 0.5 * qm * El * tau;
+            double u[3] = {v[l] + h, v[n + l], v[2 * n + l]};
+            double b[3] = {g->B[0] / bmag, g->B[1] / bmag, g->B[2] / bmag};
+            double theta = -2.0 * atan(0.5 * qm * bmag * tau);
+            double c = cos(theta), s = sin(theta);
+            double bu = b[0] * u[0] + b[1] * u[1] + b[2] * u[2];
+            double bxu[3] = {b[1] * u[2] - b[2] * u[1], b[2] * u[0] - b[0] * u[2], b[0] * u[1] - b[1] * u[0]};
+            double w[3];
+            for (int d = 0; d < 3; ++d) w[d] = u[d] * c + bxu[d] * s + b[d] * bu * (1.0 - c);
+            v[l] = w[0] + h;
+            v[n + l] = w[1];
+            v[2 * n + l] = w[2];
+        } else {
+            v[l] = v[l] + qm * El * tau;
+        }
         double xn = x[l] + v[l] * g->dt;
         xn = xn - g->L * floor(xn / g->L);
         if (xn >= g->L) xn -= g->L;

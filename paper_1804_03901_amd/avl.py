@@ -42,6 +42,7 @@ class AvlConfig(ctypes.Structure):
         ("vmin", ctypes.c_double * 3), ("vmax", ctypes.c_double * 3),
         ("dt", ctypes.c_double), ("q", ctypes.c_double), ("m", ctypes.c_double), ("c_p", ctypes.c_double),
         ("tune", ctypes.c_int32 * 4),
+        ("B", ctypes.c_double * 3),
     ]
 
 
@@ -156,6 +157,8 @@ def make_config(w: "inputs.Workload", precision: int = AVL_FP64, n_markers: Opti
     c.n_markers = w.n_markers if n_markers is None else n_markers
     c.L = w.L
     c.dt, c.q, c.m, c.c_p = w.dt, w.q, w.m, w.c_p
+    for d in range(3):
+        c.B[d] = w.B[d]
     for slot, value in (tune or {}).items():
         c.tune[slot] = int(value)
     return c

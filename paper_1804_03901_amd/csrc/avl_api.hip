@@ -109,6 +109,17 @@ int make_geo(const avl_config* c, Geo* g)
     if (c->n_markers < 0 || c->n_markers >= (int64_t)INT32_MAX) return AVL_ESIZE;
     if (!finite_pos(c->L) || !finite_pos(c->dt) || !finite_pos(c->c_p)) return AVL_EINVAL;
     if (!std::isfinite(c->q) || !std::isfinite(c->m) || c->m == 0.0) return AVL_EINVAL;
+    {
+        // background magnetic field: 1D-3V only; at least 2 pi steps per gyration
+        const bool any = c->B[0] != 0.0 || c->B[1] != 0.0 || c->B[2] != 0.0;
+        if (!std::isfinite(c->B[0]) || !std::isfinite(c->B[1]) || !std::isfinite(c->B[2])) return AVL_EINVAL;
+        if (any && c->vdim != 3) return AVL_EINVAL;
+        const double wc = std::fabs(c->q / c->m) * std::sqrt(c->B[0] * c->B[0] + c->B[1] * c->B[1] + c->B[2] * c->B[2]);
+        if (wc * c->dt > 1.0) return AVL_EINVAL;
+        if (any && c->precision == AVL_FP32) return AVL_ENOTSUP;
+        g->magnetic = any ? 1 : 0;
+        for (int d = 0; d < 3; ++d) g->B[d] = c->B[d];
+    }
     g->vdim = c->vdim;
     g->prec = c->precision;
     g->kahan = (c->options & AVL_OPT_KAHAN32) ? 1 : 0;

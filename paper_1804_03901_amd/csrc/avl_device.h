@@ -52,6 +52,8 @@ struct Geo {
     int jpad, jrange;    // FP32 1D-3V: x-velocity dual index stored with offset jpad, range jrange
     int kahan;           // FP32 form: compensated FP32 accumulation instead of FP64 accumulators
     int sblocks;         // blocks of the tiled scatter (FP32 1D-1V): the resident capacity; 0 = a tile per block
+    int magnetic;        // 1D-3V FP64 with a background magnetic field: Boris push
+    double B[3];         // background magnetic field
     double L, inv_L, dx, inv_dx;
     double vmin[3], dv[3], inv_dv[3];
     double dt, qm, cp;
@@ -177,9 +179,13 @@ __device__ __forceinline__ int locate64(const Geo& g, double x, const double* vv
     return ok ? row * g.nx + ix : g.nb;
 }
 
-// Gather + kick + drift of one FP64 marker (x velocity only).
-__device__ __forceinline__ void push64(const Geo& g, const double* sE, double dtk,
-                                       double& x, double& vx)
+// Gather + kick + drift of one FP64 marker.  Without a magnetic field only
+// the x velocity changes.  With one (1D-3V), the velocity update is the Boris
+// scheme: half an electric kick h = (q/m) E dtk / 2, a rotation about B by
+// t = (q/m) B dtk / 2 (u' = u + u x t, u+ = u + (2 / (1 + |t|^2)) u' x t), and
+// the second half kick; the rotation keeps |v| and turns it by 2 atan(|t|).
+template <int VD>
+__device__ __forceinline__ void push64(const Geo& g, const double* sE, double dtk, double& x, double* v)
 {
     double s = x * g.inv_dx - 0.5;
     double fs = floor(s);
@@ -187,7 +193,22 @@ __device__ __forceinline__ void push64(const Geo& g, const double* sE, double dt
     int ia = wrap_pow2((int)fs, g.nx);
     int ib = wrap_pow2(ia + 1, g.nx);
     double El = (1.0 - a) * sE[ia] + a * sE[ib];
-    vx = vx + g.qm * El * dtk;
+    if (VD == 3 && g.magnetic) {
+        const double h = 0.5 * g.qm * El * dtk;
+        const double c = 0.5 * g.qm * dtk;
+        const double tx = c * g.B[0], ty = c * g.B[1], tz = c * g.B[2];
+        const double sc = 2.0 / (1.0 + ((tx * tx + ty * ty) + tz * tz));
+        const double ux = v[0] + h, uy = v[1], uz = v[2];
+        const double px = ux + (uy * tz - uz * ty);
+        const double py = uy + (uz * tx - ux * tz);
+        const double pz = uz + (ux * ty - uy * tx);
+        v[0] = (ux + sc * (py * tz - pz * ty)) + h;
+        v[1] = uy + sc * (pz * tx - px * tz);
+        v[2] = uz + sc * (px * ty - py * tx);
+    } else {
+        v[0] = v[0] + g.qm * El * dtk;
+    }
+    const double vx = v[0];
     double xn = x + vx * g.dt;
     xn = xn - g.L * floor(xn * g.inv_L);
     if (xn >= g.L) xn -= g.L;

@@ -45,8 +45,10 @@ template <int VD> struct Pay<0, VD> {
         if (m.id) m.id[i] = id;
     }
     __device__ void push(const Geo& g, const double* sE, const RowShift*, double dtk, float, int& flags) {
-        push64(g, sE, dtk, x, v[0]);
-        if (!isfinite(x) || !isfinite(v[0])) flags |= FLAG_NONFINITE;
+        push64<VD>(g, sE, dtk, x, v);
+        bool ok = isfinite(x) && isfinite(v[0]);
+        if (VD == 3 && g.magnetic) ok = ok && isfinite(v[1]) && isfinite(v[2]);
+        if (!ok) flags |= FLAG_NONFINITE;
     }
     __device__ int bucket(const Geo& g) const {
         int ix, jp[VD];

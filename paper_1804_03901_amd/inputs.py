@@ -91,6 +91,7 @@ class Workload:
     m: float = 1.0
     c_p: float = 1.0
     first_kick: int = 0
+    B: tuple = (0.0, 0.0, 0.0)      # uniform background magnetic field (1D-3V)
 
     @property
     def n_markers(self) -> int:
@@ -288,6 +289,21 @@ def langmuir_noise(nx: int = 256, nv: int = 256, ppc: int = 4, modes: int = 16, 
         mode_numbers=tuple(range(1, modes + 1)), mode_amplitude=amplitude, random_phases=True)
 
 
+def bernstein(nx: int = 64, nv: int = 24, ppc: int = 2, B: float = 0.5, modes: int = 16,
+              amplitude: float = 1e-3, steps: int = 2048, seed: int = 1495) -> Workload:
+    """Electron Bernstein waves (Sec. 4.4): 1D-3V electrons gyrating in a
+    uniform field along z, perpendicular to x (cyclotron frequency B for q/m =
+    -1, plasma frequency 1, thermal speed 1), seeded with small density noise
+    in modes k = 0.1 m (m = 1..modes, random phases); L = 20 pi, v on
+    [-5, 5]^3, dt = 0.1, immobile ions."""
+    return Workload(
+        name=f"bernstein_1d3v_nx{nx}_nv{nv}^3_ppc{ppc}", vdim=3, nx=nx, nv=(nv, nv, nv),
+        L=20.0 * math.pi, vmin=(-5.0, -5.0, -5.0), vmax=(5.0, 5.0, 5.0), ppc=ppc, dt=0.1,
+        steps=steps, seed=seed, populations=(Population(1.0),),
+        mode_numbers=tuple(range(1, modes + 1)), mode_amplitude=amplitude, random_phases=True,
+        B=(0.0, 0.0, B))
+
+
 def adjoint_case() -> Workload:
     return bump_on_tail(nx=1024, nv=512, ppc=8, seed=5, steps=500)
 
@@ -299,4 +315,5 @@ WORKLOADS = {
     "adjoint": adjoint_case,
     "paper_landau": paper_landau,
     "langmuir": langmuir_noise,
+    "bernstein": bernstein,
 }

@@ -101,3 +101,35 @@ def damping_rate(amp, dt, t_lo=1.5, t_hi=20.0, t_freq=15.0):
     tf = pk[(pk[:, 0] >= t_lo) & (pk[:, 0] <= t_freq), 0]
     spacing = np.polyfit(np.arange(tf.size), tf, 1)[0]
     return gamma, math.pi / spacing
+
+
+def bernstein_roots(k: float, wc: float, wp: float = 1.0, vt: float = 1.0, bands: int = 4, nmax: int = 60):
+    """Frequencies of electrostatic electron Bernstein waves (k perpendicular
+    to B, Maxwellian electrons of thermal speed vt, immobile ions), one in each
+    band (n wc, (n+1) wc) for n = 1..bands: the roots of
+    1 = (wp/wc)^2 (e^-lam / lam) sum_{n>=1} 2 n^2 I_n(lam) / ((w/wc)^2 - n^2),
+    lam = (k vt / wc)^2, found by bisection (the right side falls from +inf
+    to -inf across each band)."""
+    from scipy.special import ive
+    lam = (k * vt / wc) ** 2
+    ns = np.arange(1, nmax + 1)
+    coef = 2.0 * ns ** 2 * ive(ns, lam) / lam * (wp / wc) ** 2
+
+    def F(w):
+        return 1.0 - float(np.sum(coef / ((w / wc) ** 2 - ns ** 2)))
+
+    out = []
+    for n in range(1, bands + 1):
+        lo, hi = n * wc * (1 + 1e-12), (n + 1) * wc * (1 - 1e-12)
+        flo, fhi = F(lo), F(hi)
+        if not (flo < 0 < fhi):
+            out.append(float("nan"))
+            continue
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            if F(mid) < 0:
+                lo = mid
+            else:
+                hi = mid
+        out.append(0.5 * (lo + hi))
+    return out

@@ -154,3 +154,15 @@ def test_adjoint_workspace_rules():
     assert avl.avl_adjoint_workspace_bytes(avl.make_config(inputs.two_stream_3v(nx=16, nv=4, ppc=1)), 30, 10) == 0
     lib = avl.load()
     assert lib.avl_adjoint(None, None, None, None, 1, 1, None, 0, None, None) == -1
+
+
+def test_magnetic_field_rules():
+    """A background B is accepted for 1D-3V FP64 only, with at least 2 pi steps
+    per gyration (|q/m| |B| dt <= 1)."""
+    w3 = inputs.two_stream_3v(nx=16, nv=4, ppc=1).replace(B=(0.0, 0.0, 0.5))
+    assert avl.avl_workspace_bytes(avl.make_config(w3)) > 0
+    assert avl.avl_workspace_bytes(avl.make_config(w3, precision=avl.AVL_FP32)) == 0
+    assert avl.avl_workspace_bytes(avl.make_config(w3.replace(B=(0.0, 11.0, 0.0)))) == 0      # 1.1 rad a step
+    assert avl.avl_workspace_bytes(avl.make_config(w3.replace(B=(0.0, float("nan"), 0.0)))) == 0
+    w1 = inputs.landau_small().replace(B=(0.0, 0.0, 0.5))
+    assert avl.avl_workspace_bytes(avl.make_config(w1)) == 0

@@ -148,3 +148,37 @@ def test_3v_fp32_form_matches_oracle(case):
     assert nrel(t2n(rho_g), rho_o) <= 1e-6
     assert e_err(t2n(E_g), E_o, rho_o, w) <= 1e-6
 
+
+
+MAGNETISED = _base(nx=32, nv=8, ppc=2, seed=27).replace(name="ts3v_magnetised", nv=(10, 8, 6), B=(0.0, 0.3, 0.6))
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_3v_magnetised_step_matches_oracle(graph):
+    """Boris push with a background field across x and y: one step from the
+    same exported state; all three velocity components now change, so the
+    markers of both sides are paired by position."""
+    w = MAGNETISED
+    sim, _ = sim_for(w)
+    sim.step(3, graph=graph)
+    x, v, f = (t2n(a) for a in sim.markers())
+    E = t2n(sim.field()[0])
+    g = oracle.Grid.from_workload(w)
+    xo, vo = oracle.push(g, x, v, E)
+    _, Do, fo = oracle.reconstruct(g, xo, vo, f)
+    rho_o, _, _ = oracle.moments(g, fo)
+    E_o, _ = oracle.poisson(w.nx, w.L, w.c_p, rho_o)
+    sim.step(1, graph=graph)
+    fg, Dg = sim.reconstruct(want_D=True)
+    E_g, rho_g = sim.field()
+    sim.check()
+    assert nrel(t2n(fg), fo) <= TOL64
+    assert nrel(t2n(Dg), Do) <= TOL64
+    assert nrel(t2n(rho_g), rho_o) <= TOL64
+    assert e_err(t2n(E_g), E_o, rho_o, w) <= TOL64
+    xg, vg, _ = (t2n(a) for a in sim.markers())
+    a, b = np.argsort(xg), np.argsort(xo)
+    assert np.max(np.abs(xg[a] - xo[b])) <= TOL64 * w.L
+    assert np.max(np.abs(vg[:, a] - vo[:, b])) <= TOL64 * (w.vmax[0] - w.vmin[0])
+    # the perpendicular velocities did turn
+    assert np.max(np.abs(vo[1:] - v[1:])) > 1e-3

@@ -13,7 +13,13 @@ Langmuir: a thermal plasma seeded with 1e-3 density noise in modes k = 0.05 m
 (m = 1..16), E(x, t) recorded every step for 2048 steps; the peak of the
 (k, omega) power for each k is compared with the real part of the exact
 kinetic root (the paper compares with the Bohm-Gross curve, which the exact
-roots approach for small k)."""
+roots approach for small k).
+
+Bernstein (Sec. 4.4, 1D-3V with a background field perpendicular to x, Boris
+push): electrons with omega_p = 1 = 2 omega_c, thermal speed 1, noise-seeded;
+the spectral peaks in the bands (omega_c, 2 omega_c) and (2 omega_c, 3 omega_c)
+are compared with the roots of the electrostatic Bernstein dispersion
+relation."""
 import math
 
 import numpy as np
@@ -22,7 +28,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from paper_1804_03901_amd import avl, inputs
-from physics import damping_rate, landau_root, peaks
+from physics import bernstein_roots, damping_rate, landau_root, peaks
 
 pytestmark = pytest.mark.gpu
 
@@ -133,3 +139,48 @@ def test_langmuir_dispersion():
             assert abs(wpk - math.sqrt(1 + 3 * k * k)) <= 0.005
     ws = [g[1] for g in got]
     assert all(b > a for a, b in zip(ws, ws[1:]))       # frequency rises with k from omega_p
+
+
+def _spectrum(w, prec=avl.AVL_FP64):
+    x, v, f = inputs.markers_threaded(w)
+    print(f"[case] {w.name} n={x.size} steps={w.steps}", flush=True)
+    sim = avl.Simulation(w, x, v.reshape(-1), f, precision=prec)
+    Ex = np.empty((w.steps, w.nx))
+    for n in range(w.steps):
+        sim.step(1, diag=False)
+        Ex[n] = sim.field()[0].cpu().numpy()
+    sim.check()
+    sim.close()
+    win = np.hanning(w.steps)
+    spec = np.abs(np.fft.fft(np.fft.rfft(Ex, axis=1) * win[:, None], axis=0)) ** 2
+    return spec, 2 * math.pi * np.fft.fftfreq(w.steps, w.dt)
+
+
+def _peak(spec, om, m, lo, hi):
+    """Interpolated frequency of the largest power of mode m in (lo, hi), and
+    its ratio to the mean power there."""
+    sel = np.nonzero((om > lo) & (om < hi))[0]
+    col = spec[sel, m]
+    i = int(np.argmax(col))
+    j = sel[i]
+    y0, y1, y2 = np.log(spec[j - 1:j + 2, m])
+    dw = om[1] - om[0]
+    return om[j] + 0.5 * (y0 - y2) / (y0 - 2 * y1 + y2) * dw, float(col[i] / col.mean())
+
+
+def test_bernstein_dispersion():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    w = inputs.bernstein()
+    spec, om = _spectrum(w)
+    wc = w.B[2]                      # |q/m| B with q/m = -1
+    dw = om[1] - om[0]
+    for m in (2, 3, 5, 7, 10, 13):   # k = 0.2 .. 1.3
+        k = 2 * math.pi * m / w.L
+        roots = bernstein_roots(k, wc)
+        for n in (1, 2):
+            wpk, snr = _peak(spec, om, m, n * wc + 0.02, (n + 1) * wc - 0.02)
+            print(f"[result] k {k:.2f} band {n}: peak {wpk:.4f} root {roots[n - 1]:.4f} (power {snr:.1f}x band mean)",
+                  flush=True)
+            assert snr >= 5.0
+            assert abs(wpk - roots[n - 1]) <= dw

@@ -133,3 +133,81 @@ def test_wrap_stays_in_domain():
     v = np.array([[-1e-17, 1e-6, -1e-17, -0.5]])
     xn, _ = oracle.push(g, x, v, np.zeros(4))
     assert np.all((xn >= 0.0) & (xn < 1.0))
+
+
+def _grid3(B, dt=0.3, q=-1.0, m=1.0):
+    return oracle.Grid(3, 8, (4, 4, 4), 2 * math.pi, (-6.0,) * 3, (6.0,) * 3, dt=dt, q=q, m=m, B=B)
+
+
+def test_boris_speed_and_rotation_angle():
+    """With E = 0 the magnetised push keeps |v| and v.b, and turns the
+    perpendicular velocity about b = B/|B| by -2 atan((q/m)|B| dt/2) per step
+    (the Boris angle); for a short step the change of v points along
+    (q/m) v x B, the sense of the Lorentz force."""
+    Bv = np.array([0.0, 3.0, 4.0]) / 5.0 * 0.7
+    g = _grid3(tuple(Bv))
+    rng = np.random.default_rng(3)
+    n = 5
+    x0 = rng.uniform(0, g.L, n)
+    v0 = rng.normal(size=(3, n))
+    b = Bv / np.linalg.norm(Bv)
+    theta = -2.0 * math.atan(0.5 * (g.q / g.m) * np.linalg.norm(Bv) * g.dt)
+    xs, vs = x0, v0
+    E = np.zeros(g.nx)
+    for step in range(1, 8):
+        xs, vs = oracle.push(g, xs, vs, E)
+        assert np.allclose(np.linalg.norm(vs, axis=0), np.linalg.norm(v0, axis=0), rtol=1e-14, atol=0)
+        assert np.allclose(b @ vs, b @ v0, rtol=0, atol=1e-14)
+        p0 = v0 - np.outer(b, b @ v0)
+        p1 = vs - np.outer(b, b @ vs)
+        ang = np.arctan2(b @ np.cross(p0.T, p1.T).T, np.sum(p0 * p1, axis=0))
+        want = math.remainder(step * theta, 2 * math.pi)
+        assert np.allclose(ang, want, rtol=0, atol=1e-12)
+    g2 = _grid3(tuple(Bv), dt=1e-6)
+    _, v1 = oracle.push(g2, x0, v0, E)
+    lorentz = (g.q / g.m) * np.cross(v0.T, Bv).T * g2.dt
+    assert np.allclose(v1 - v0, lorentz, rtol=1e-5, atol=1e-16)
+
+
+def test_boris_e_cross_b_drift_is_a_fixed_point():
+    """Uniform E along x and B along z: the E x B drift velocity
+    v_d = E x B / |B|^2 = -(E/B) y_hat is reproduced exactly (a fixed point of
+    the scheme), and a gyrating marker's mean y velocity over whole turns is
+    v_d (checked over 400 steps, about 30 turns)."""
+    E0, B0 = 0.2, 0.8
+    g = _grid3((0.0, 0.0, B0), dt=0.25)
+    E = np.full(g.nx, E0)
+    x = np.array([1.0])
+    v = np.array([[0.0], [-E0 / B0], [0.3]])
+    xs, vs = x, v
+    for _ in range(50):
+        xs, vs = oracle.push(g, xs, vs, E)
+    assert np.allclose(vs, v, rtol=0, atol=1e-14)
+    assert abs(xs[0] - x[0]) <= 1e-14
+    vg = np.array([[0.9], [-E0 / B0 + 0.4], [0.0]])
+    theta = 2.0 * math.atan(0.5 * abs(g.q / g.m) * B0 * g.dt)
+    nturn = int(round(30 * 2 * math.pi / theta))
+    acc = 0.0
+    xs, vs = x, vg
+    for _ in range(nturn):
+        xs, vs = oracle.push(g, xs, vs, E)
+        acc += vs[1, 0]
+    assert abs(acc / nturn - (-E0 / B0)) <= 0.01 * E0 / B0
+
+
+def test_boris_without_field_is_the_plain_kick():
+    """B = 0 in 1D-3V leaves vy, vz untouched and kicks vx exactly as the
+    unmagnetised push."""
+    g = _grid3((0.0, 0.0, 0.0))
+    rng = np.random.default_rng(5)
+    x = rng.uniform(0, g.L, 6)
+    v = rng.normal(size=(3, 6))
+    E = rng.normal(size=g.nx)
+    xs, vs = oracle.push(g, x, v, E)
+    dx = g.L / g.nx
+    s = x / dx - 0.5
+    i0 = np.floor(s).astype(int)
+    a = s - i0
+    El = (1 - a) * E[i0 % g.nx] + a * E[(i0 + 1) % g.nx]
+    assert np.array_equal(vs[1:], v[1:])
+    assert np.allclose(vs[0], v[0] + (g.q / g.m) * El * g.dt, rtol=0, atol=1e-15)
