@@ -211,6 +211,34 @@ int avl_get_field(avl_handle* h, double* E_out, double* rho_out);
  * out: 6 doubles of device memory.  Sums are FP64 in a fixed order. */
 int avl_diagnostics(avl_handle* h, double* out, double* j_out, double* drho_out);
 
+/* ---- Several species in one self-consistent field (Sec. 2: rho is the sum
+ * over species of q_s prod(dv_s) sum_j f_s; every species is pushed by the one
+ * field; e.g. electrons and mobile ions) ---- */
+typedef struct avl_multi avl_multi;
+
+/* Device workspace bytes of a group of nspecies species on an x grid of nx
+ * cells (0 if out of range: 1..64 species). */
+size_t avl_multi_workspace_bytes(int32_t nspecies, int32_t nx);
+
+/* Group n existing handles (each with its own charge, mass, velocity grid,
+ * storage form and markers) that share nx, L, c_p, dt, first_kick and the
+ * stream (AVL_EINVAL otherwise).  The handles stay owned by the caller and
+ * must outlive the group; the field of every handle is replaced by the field
+ * of the total charge density (the neutralising background is the removed
+ * mean, as for one species).  AVL_ESTATE if a handle has no current rho. */
+int avl_multi_init(avl_handle* const* hs, int32_t n, void* workspace, size_t bytes, avl_multi** out);
+
+/* nsteps steps of every species in the shared field: push and sort each, then
+ * reconstruct each, sum the charge densities in species order, solve once and
+ * give every species the field.  diag_out (2*nsteps doubles or NULL) receives
+ * the field energy and mode-1 amplitude per step, as avl_step does.  Each
+ * handle's rho is its own species' charge density; avl_diagnostics on a handle
+ * reports that species' kinetic quantities with the total field's energy. */
+int avl_multi_step(avl_multi* m, int32_t nsteps, double* diag_out);
+
+/* Release the group (not its handles). */
+int avl_multi_destroy(avl_multi* m);
+
 /* Number of full steps taken since the markers were loaded. */
 int64_t avl_step_count(const avl_handle* h);
 

@@ -57,7 +57,8 @@ EXPORTS = ["avl_workspace_bytes", "avl_init", "avl_push", "avl_sort", "avl_recon
            "avl_step_count", "avl_check", "avl_set_stream", "avl_timing", "avl_kernel_time", "avl_kernel_bytes",
            "avl_copy_probe", "avl_strerror", "avl_destroy", "avl_batch_workspace_bytes", "avl_batch_init",
            "avl_batch_step", "avl_batch_instance", "avl_batch_count", "avl_batch_check", "avl_batch_destroy",
-           "avl_adjoint_workspace_bytes", "avl_adjoint", "avl_diagnostics"]
+           "avl_adjoint_workspace_bytes", "avl_adjoint", "avl_diagnostics", "avl_multi_workspace_bytes",
+           "avl_multi_init", "avl_multi_step", "avl_multi_destroy"]
 
 # avl_diagnostics output slots
 DIAG_NAMES = ("Ee", "Ekin", "Etot", "N", "S", "P")
@@ -87,6 +88,11 @@ def load(path: str = LIB_PATH):
     lib.avl_set_markers.argtypes = [vp, vp, vp, vp]
     lib.avl_get_field.argtypes = [vp, vp, vp]
     lib.avl_diagnostics.argtypes = [vp, vp, vp, vp]
+    lib.avl_multi_workspace_bytes.argtypes = [c.c_int32, c.c_int32]
+    lib.avl_multi_workspace_bytes.restype = c.c_size_t
+    lib.avl_multi_init.argtypes = [P(vp), c.c_int32, vp, c.c_size_t, P(vp)]
+    lib.avl_multi_step.argtypes = [vp, c.c_int32, vp]
+    lib.avl_multi_destroy.argtypes = [vp]
     lib.avl_step_count.argtypes = [vp]
     lib.avl_step_count.restype = c.c_int64
     lib.avl_check.argtypes = [vp]
@@ -113,7 +119,8 @@ def load(path: str = LIB_PATH):
     lib.avl_adjoint.argtypes = [vp, vp, vp, vp, c.c_int32, c.c_int32, vp, c.c_size_t, vp, vp]
     for name in EXPORTS:
         if name not in ("avl_workspace_bytes", "avl_step_count", "avl_kernel_bytes", "avl_strerror",
-                        "avl_batch_workspace_bytes", "avl_batch_instance", "avl_adjoint_workspace_bytes"):
+                        "avl_batch_workspace_bytes", "avl_batch_instance", "avl_adjoint_workspace_bytes",
+                        "avl_multi_workspace_bytes"):
             getattr(lib, name).restype = c.c_int
     _lib = lib
     return lib
@@ -221,6 +228,26 @@ def avl_get_field(h, E_out=None, rho_out=None):
 
 def avl_diagnostics(h, out, j_out=None, drho_out=None):
     return _ck(load().avl_diagnostics(h, _ptr(out), _ptr(j_out), _ptr(drho_out)), "avl_diagnostics")
+
+
+def avl_multi_workspace_bytes(nspecies: int, nx: int) -> int:
+    return int(load().avl_multi_workspace_bytes(int(nspecies), int(nx)))
+
+
+def avl_multi_init(handles, workspace) -> ctypes.c_void_p:
+    arr = (ctypes.c_void_p * len(handles))(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in handles])
+    m = ctypes.c_void_p()
+    _ck(load().avl_multi_init(arr, len(handles), _ptr(workspace), workspace.numel() * workspace.element_size(),
+                              ctypes.byref(m)), "avl_multi_init")
+    return m
+
+
+def avl_multi_step(m, nsteps: int, diag_out=None):
+    return _ck(load().avl_multi_step(m, int(nsteps), _ptr(diag_out)), "avl_multi_step")
+
+
+def avl_multi_destroy(m):
+    return _ck(load().avl_multi_destroy(m), "avl_multi_destroy")
 
 
 def avl_step_count(h) -> int:
@@ -500,3 +527,40 @@ class Batch:
         except Exception:
             pass
 
+
+
+class MultiSpecies:
+    """Several Simulations (species) stepped in one self-consistent field.
+
+    The Simulations share nx, L, c_p, dt and their stream; each keeps its own
+    markers, velocity grid, charge and mass.  ``step`` advances all of them;
+    each Simulation's ``field()`` then returns the common field and its own
+    species' charge density."""
+
+    def __init__(self, sims):
+        import torch
+        self.sims = list(sims)
+        nbytes = avl_multi_workspace_bytes(len(self.sims), self.sims[0].w.nx)
+        if nbytes == 0:
+            raise AvlError(-1, "avl_multi_workspace_bytes")
+        dev = self.sims[0].device
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        off = (-ws.data_ptr()) % 256
+        self.workspace = ws[off:off + nbytes]
+        self.m = avl_multi_init([s.h for s in self.sims], self.workspace)
+
+    def step(self, nsteps: int, diag: bool = True):
+        d = self.sims[0]._empty(2 * max(nsteps, 1)) if diag else None
+        avl_multi_step(self.m, nsteps, d)
+        return d[: 2 * nsteps].reshape(nsteps, 2) if diag else None
+
+    def close(self):
+        if getattr(self, "m", None):
+            avl_multi_destroy(self.m)
+            self.m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

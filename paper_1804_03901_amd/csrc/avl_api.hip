@@ -28,6 +28,9 @@ hipError_t launch_field(const Geo& g, const double* rho_part, const double* rho_
                         double* E_out, const double2* tw, const double* green, double* diag_ring,
                         long long* step_ctr, int write_diag, double* W_out, int* flags, hipStream_t st);
 int field_slices(const Geo& g);
+hipError_t launch_rho_slices(const Geo& g, const double* rho_part, double* rho_slices, hipStream_t st);
+hipError_t launch_species_rho(const Species* sp, int ns, int nx, int from_rho, double* rho_total, hipStream_t st);
+hipError_t launch_broadcast_E(const Species* sp, int ns, int nx, hipStream_t st);
 hipError_t launch_validate(const Geo& g, const double* x, const double* v, const double* f, int* bad,
                            hipStream_t st);
 hipError_t launch_to32(const Geo& g, const double* x, const double* v, const double* f, M32 m, int* flags,
@@ -1465,6 +1468,141 @@ int avl_adjoint(avl_handle* h, const double* x, const double* v, const double* f
     // field and f are current for that state
     h->have_rho = h->partials = false;
     return done(AVL_OK);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Several species in one self-consistent field
+// ---------------------------------------------------------------------------
+
+struct avl_multi {
+    std::vector<avl_handle*> hs;
+    Species* tab;          // device table, in the caller's workspace
+    double* rho_total;     // device, nx doubles
+};
+
+namespace {
+
+size_t multi_layout(int32_t n, int32_t nx, size_t* tab_off, size_t* rho_off)
+{
+    size_t off = 0;
+    *tab_off = off;
+    off = align_up(off + sizeof(Species) * (size_t)n);
+    *rho_off = off;
+    off = align_up(off + sizeof(double) * (size_t)nx);
+    return off;
+}
+
+// Total rho from the species' rho (from_rho) or their fresh slices, the
+// field from it into species 0, copied to the others.
+int multi_field(avl_multi* m, bool from_rho, bool diag)
+{
+    avl_handle* h0 = m->hs[0];
+    const int ns = (int)m->hs.size();
+    AVL_TRY(launch_species_rho(m->tab, ns, h0->g.nx, from_rho ? 1 : 0, m->rho_total, h0->st));
+    AVL_TRY(launch_field(h0->g, nullptr, m->rho_total, h0->rho_slices, h0->rho, h0->E, h0->tw, h0->green, h0->diag,
+                         h0->ctr, diag ? 1 : 0, nullptr, h0->flags, h0->st));
+    AVL_TRY(launch_broadcast_E(m->tab, ns, h0->g.nx, h0->st));
+    for (avl_handle* h : m->hs) h->have_rho = h->have_E = true;
+    return AVL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t avl_multi_workspace_bytes(int32_t nspecies, int32_t nx)
+{
+    if (nspecies < 1 || nspecies > 64 || nx < 8 || nx > kMaxNx) return 0;
+    size_t a, b;
+    return multi_layout(nspecies, nx, &a, &b);
+}
+
+int avl_multi_init(avl_handle* const* hs, int32_t n, void* workspace, size_t bytes, avl_multi** out)
+{
+    if (!out) return AVL_EINVAL;
+    *out = nullptr;
+    if (!hs || n < 1 || n > 64 || !workspace) return AVL_EINVAL;
+    for (int32_t s = 0; s < n; ++s) {
+        if (!hs[s]) return AVL_EINVAL;
+        for (int32_t r = 0; r < s; ++r)
+            if (hs[r] == hs[s]) return AVL_EINVAL;
+    }
+    const avl_handle* h0 = hs[0];
+    for (int32_t s = 1; s < n; ++s) {
+        const avl_config &a = h0->cfg, &b = hs[s]->cfg;
+        // one x grid, one field, one time step, one stream
+        if (a.nx != b.nx || a.L != b.L || a.c_p != b.c_p || a.dt != b.dt || a.first_kick != b.first_kick)
+            return AVL_EINVAL;
+        if (hs[s]->st != h0->st) return AVL_EINVAL;
+    }
+    for (int32_t s = 0; s < n; ++s)
+        if (!hs[s]->have_rho || !hs[s]->sorted) return AVL_ESTATE;
+    if ((uintptr_t)workspace % kAlign) return AVL_EALIGN;
+    size_t tab_off, rho_off;
+    if (bytes < multi_layout(n, h0->g.nx, &tab_off, &rho_off)) return AVL_ESIZE;
+    avl_multi* m = new (std::nothrow) avl_multi;
+    if (!m) return AVL_EDEVICE;
+    m->hs.assign(hs, hs + n);
+    m->tab = (Species*)((char*)workspace + tab_off);
+    m->rho_total = (double*)((char*)workspace + rho_off);
+    std::vector<Species> tab(n);
+    for (int32_t s = 0; s < n; ++s) {
+        avl_handle* h = hs[s];
+        tab[s] = Species{h->rho_slices, field_slices(h->g), h->g.q_vol, h->rho, h->E};
+    }
+    hipError_t e = hipMemcpyAsync(m->tab, tab.data(), sizeof(Species) * n, hipMemcpyHostToDevice, h0->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(h0->st);
+    if (e != hipSuccess) {
+        delete m;
+        return report(e, "species table upload", __LINE__);
+    }
+    // the initial field from the total charge density
+    int rc = multi_field(m, true, false);
+    if (rc) {
+        delete m;
+        return rc;
+    }
+    *out = m;
+    return AVL_OK;
+}
+
+int avl_multi_step(avl_multi* m, int32_t nsteps, double* diag_out)
+{
+    if (!m) return AVL_EINVAL;
+    if (nsteps < 0) return AVL_EINVAL;
+    for (avl_handle* h : m->hs)
+        if (!h->have_E || !h->sorted) return AVL_ESTATE;
+    avl_handle* h0 = m->hs[0];
+    const int64_t first = h0->steps;
+    for (int32_t step = 0; step < nsteps; ++step) {
+        int rc;
+        for (avl_handle* h : m->hs)
+            if ((rc = do_sort(h, true, kick_fraction(h)))) return rc;
+        for (avl_handle* h : m->hs) {
+            if ((rc = do_recon(h, nullptr))) return rc;
+            AVL_TRY(launch_rho_slices(h->g, h->rho_part, h->rho_slices, h->st));
+        }
+        if ((rc = multi_field(m, false, true))) return rc;
+        for (avl_handle* h : m->hs) h->steps += 1;
+        if (diag_out && ((step + 1) % kDiagCap == 0)) {
+            if ((rc = copy_diag(h0, first + step + 1 - kDiagCap, kDiagCap, diag_out + 2 * (step + 1 - kDiagCap))))
+                return rc;
+        }
+    }
+    if (diag_out) {
+        const int32_t tail = nsteps % kDiagCap;
+        if (tail) return copy_diag(h0, first + nsteps - tail, tail, diag_out + 2 * (nsteps - tail));
+    }
+    return AVL_OK;
+}
+
+int avl_multi_destroy(avl_multi* m)
+{
+    if (!m) return AVL_EINVAL;
+    delete m;
+    return AVL_OK;
 }
 
 }  // extern "C"

@@ -86,6 +86,17 @@ struct RowShift {
     float frac;
 };
 
+// One species of a multi-species step, as the shared-field kernels see it:
+// its rho slices (unscaled sums of f over chunk ranges), their count, its
+// scale q prod(dv), and its rho and E buffers.
+struct Species {
+    const double* rho_slices;
+    int nslice;
+    double q_vol;
+    double* rho;
+    double* E;
+};
+
 // One 1D-1V instance of a batch, as the batched kernels see it: its geometry
 // and the buffers of its own workspace slice (the same layout a single handle
 // uses).  Markers alternate between two buffers; the parity selects them.

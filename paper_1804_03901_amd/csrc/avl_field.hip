@@ -292,6 +292,63 @@ hipError_t launch_field_batch(const BInst* tab, const int* pre, int ninst, int r
 // Chunk slices of the rho reduction: at most 256 chunk partials per block.
 int field_slices(const Geo& g) { return std::max(1, std::min(kMaxFieldSlices, (g.nchunk + 255) / 256)); }
 
+// ---------------------------------------------------------------------------
+// Several species in one field (Sec. 2: rho is the sum over species of
+// q_s times the velocity integral of f_s; one field pushes every species).
+// ---------------------------------------------------------------------------
+
+// Per column: each species' rho (its slices in slice order, or its rho when
+// from_rho is set, times q prod(dv)), and the total in species order.
+__global__ void k_species_rho(const Species* __restrict__ sp, int ns, int nx, int from_rho,
+                              double* __restrict__ rho_total)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nx; i += gridDim.x * blockDim.x) {
+        double tot = 0.0;
+        for (int s = 0; s < ns; ++s) {
+            double r;
+            if (from_rho) {
+                r = sp[s].rho[i];
+            } else {
+                r = 0.0;
+                for (int k = 0; k < sp[s].nslice; ++k) r += sp[s].rho_slices[(size_t)k * nx + i];
+                r *= sp[s].q_vol;
+                sp[s].rho[i] = r;
+            }
+            tot += r;
+        }
+        rho_total[i] = tot;
+    }
+}
+
+// The field solved into species 0's buffer, copied to the others.
+__global__ void k_broadcast_E(const Species* __restrict__ sp, int ns, int nx)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nx; i += gridDim.x * blockDim.x) {
+        const double e = sp[0].E[i];
+        for (int s = 1; s < ns; ++s) sp[s].E[i] = e;
+    }
+}
+
+hipError_t launch_rho_slices(const Geo& g, const double* rho_part, double* rho_slices, hipStream_t st)
+{
+    const int nslice = field_slices(g);
+    hipLaunchKernelGGL(k_rho, dim3(((g.nx + 63) / 64) * nslice), dim3(kFT), 0, st, g, rho_part, rho_slices, nslice);
+    return hipGetLastError();
+}
+
+hipError_t launch_species_rho(const Species* sp, int ns, int nx, int from_rho, double* rho_total, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_species_rho, dim3((nx + 255) / 256), dim3(256), 0, st, sp, ns, nx, from_rho, rho_total);
+    return hipGetLastError();
+}
+
+hipError_t launch_broadcast_E(const Species* sp, int ns, int nx, hipStream_t st)
+{
+    if (ns < 2) return hipSuccess;
+    hipLaunchKernelGGL(k_broadcast_E, dim3((nx + 255) / 256), dim3(256), 0, st, sp, ns, nx);
+    return hipGetLastError();
+}
+
 hipError_t launch_field(const Geo& g, const double* rho_part, const double* rho_in, double* rho_slices, double* rho,
                         double* E_out, const double2* tw, const double* green, double* diag_ring,
                         long long* step_ctr, int write_diag, double* W_out, int* flags, hipStream_t st)

@@ -304,6 +304,26 @@ def bernstein(nx: int = 64, nv: int = 24, ppc: int = 2, B: float = 0.5, modes: i
         B=(0.0, 0.0, B))
 
 
+def ion_acoustic(nx: int = 32, nv_e: int = 1024, nv_i: int = 128, ppc: int = 4, mass_ratio: float = 100.0,
+                 ti: float = 0.25, amplitude: float = 1e-2, steps: int = 3000, seed: int = 1418):
+    """Electrons (T_e = 1) and mobile ions (charge +1, mass ``mass_ratio``,
+    temperature ``ti``) carrying the same cosine density perturbation of the
+    longest mode (k = 0.5, L = 4 pi), so the start is neutral and the ions'
+    response is an ion-acoustic wave; dt = 0.1.  The electron grid resolves
+    the slow resonant electrons (v ~ 0.1) and keeps the grid recurrence time
+    2 pi / (k dv) beyond the run.  Returns (electrons, ions)."""
+    L = 4.0 * math.pi
+    vti = math.sqrt(ti / mass_ratio)
+    common = dict(vdim=1, nx=nx, L=L, ppc=ppc, dt=0.1, steps=steps,
+                  mode_numbers=(1,), mode_amplitude=amplitude, random_phases=False)
+    e = Workload(name=f"ion_acoustic_electrons_nx{nx}_nv{nv_e}", nv=(nv_e, 1, 1), vmin=(-6.0, 0, 0),
+                 vmax=(6.0, 0, 0), seed=seed, populations=(Population(1.0),), q=-1.0, m=1.0, **common)
+    i = Workload(name=f"ion_acoustic_ions_nx{nx}_nv{nv_i}_mr{mass_ratio:g}", nv=(nv_i, 1, 1),
+                 vmin=(-14.0 * vti, 0, 0), vmax=(14.0 * vti, 0, 0), seed=seed + 1,
+                 populations=(Population(1.0, vth=(vti, 1.0, 1.0)),), q=1.0, m=mass_ratio, **common)
+    return e, i
+
+
 def adjoint_case() -> Workload:
     return bump_on_tail(nx=1024, nv=512, ppc=8, seed=5, steps=500)
 

@@ -90,11 +90,11 @@ def peaks(amp, dt, half_window=1.0):
     return np.array(out)
 
 
-def damping_rate(amp, dt, t_lo=1.5, t_hi=20.0, t_freq=15.0):
+def damping_rate(amp, dt, t_lo=1.5, t_hi=20.0, t_freq=15.0, half_window=1.0):
     """(gamma, omega) from peaks of |E_1|: slope of log peaks over [t_lo, t_hi],
     and pi / (regression slope of peak time on peak index) over [t_lo, t_freq]
     (|E_1| peaks twice per wave period; late peaks sit near the noise floor)."""
-    pk = peaks(amp, dt)
+    pk = peaks(amp, dt, half_window)
     sel = (pk[:, 0] >= t_lo) & (pk[:, 0] <= t_hi)
     A = np.vstack([np.ones(sel.sum()), pk[sel, 0]]).T
     gamma = np.linalg.lstsq(A, pk[sel, 1], rcond=None)[0][1]
@@ -133,3 +133,31 @@ def bernstein_roots(k: float, wc: float, wp: float = 1.0, vt: float = 1.0, bands
                 hi = mid
         out.append(0.5 * (lo + hi))
     return out
+
+
+def multi_species_root(k: float, species, guess: complex) -> complex:
+    """Complex frequency of an electrostatic mode of several drifting
+    Maxwellian species (normalised units, c_p = 1): the root near ``guess`` of
+    1 + sum_s n_s q_s^2 / (T_s k^2) (1 + zeta_s Z(zeta_s)) = 0 with
+    zeta_s = (omega - k u_s) / (sqrt(2) k v_s), v_s = sqrt(T_s / m_s);
+    ``species`` holds (n, q, m, T, u) per species."""
+    from scipy.special import wofz
+
+    def eps(w):
+        tot = 1.0 + 0j
+        for n, q, m, T, u in species:
+            vs = math.sqrt(T / m)
+            z = (w - k * u) / (math.sqrt(2.0) * k * vs)
+            Z = 1j * math.sqrt(math.pi) * wofz(z)
+            tot += n * q * q / (T * k * k) * (1.0 + z * Z)
+        return tot
+
+    w = complex(guess)
+    for _ in range(200):
+        h = 1e-8 * max(1.0, abs(w))
+        d = (eps(w + h) - eps(w - h)) / (2 * h)
+        step = eps(w) / d
+        w -= step
+        if abs(step) < 1e-14 * max(1.0, abs(w)):
+            break
+    return w

@@ -166,3 +166,14 @@ def test_magnetic_field_rules():
     assert avl.avl_workspace_bytes(avl.make_config(w3.replace(B=(0.0, float("nan"), 0.0)))) == 0
     w1 = inputs.landau_small().replace(B=(0.0, 0.0, 0.5))
     assert avl.avl_workspace_bytes(avl.make_config(w1)) == 0
+
+
+def test_multi_species_workspace_rules():
+    assert avl.avl_multi_workspace_bytes(2, 64) > 0
+    assert avl.avl_multi_workspace_bytes(0, 64) == 0
+    assert avl.avl_multi_workspace_bytes(65, 64) == 0
+    assert avl.avl_multi_workspace_bytes(2, 4) == 0
+    lib = avl.load()
+    assert lib.avl_multi_step(None, 1, None) == -1
+    assert lib.avl_multi_destroy(None) == -1
+    assert lib.avl_multi_init(None, 0, None, 0, None) == -1
