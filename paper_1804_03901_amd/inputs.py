@@ -324,6 +324,29 @@ def ion_acoustic(nx: int = 32, nv_e: int = 1024, nv_i: int = 128, ppc: int = 4, 
     return e, i
 
 
+def current_driven(nx: int = 32, nv_e: int = 1024, nv_i: int = 128, ppc: int = 4, mass_ratio: float = 100.0,
+                   ti: float = 0.1, drift: float = 1.5, amplitude: float = 1e-3, steps: int = 3000,
+                   seed: int = 1457):
+    """Current-driven ion-acoustic instability (Sec. 4.3): electrons (T_e = 1)
+    drifting by ``drift`` relative to ions (charge +1, mass ``mass_ratio``,
+    temperature ``ti``), the centre of mass at rest, both species carrying the
+    same small cosine density perturbation of the longest mode (k = 0.5,
+    L = 4 pi); dt = 0.1.  Returns (electrons, ions)."""
+    L = 4.0 * math.pi
+    vti = math.sqrt(ti / mass_ratio)
+    ue = drift * mass_ratio / (mass_ratio + 1.0)
+    ui = -drift / (mass_ratio + 1.0)
+    common = dict(vdim=1, nx=nx, L=L, ppc=ppc, dt=0.1, steps=steps,
+                  mode_numbers=(1,), mode_amplitude=amplitude, random_phases=False)
+    e = Workload(name=f"cdiai_electrons_nx{nx}_nv{nv_e}", nv=(nv_e, 1, 1), vmin=(ue - 6.5, 0, 0),
+                 vmax=(ue + 6.5, 0, 0), seed=seed, populations=(Population(1.0, (ue, 0, 0)),), q=-1.0, m=1.0,
+                 **common)
+    i = Workload(name=f"cdiai_ions_nx{nx}_nv{nv_i}_mr{mass_ratio:g}", nv=(nv_i, 1, 1),
+                 vmin=(ui - 14.0 * vti, 0, 0), vmax=(ui + 14.0 * vti, 0, 0), seed=seed + 1,
+                 populations=(Population(1.0, (ui, 0, 0), (vti, 1.0, 1.0)),), q=1.0, m=mass_ratio, **common)
+    return e, i
+
+
 def adjoint_case() -> Workload:
     return bump_on_tail(nx=1024, nv=512, ppc=8, seed=5, steps=500)
 
