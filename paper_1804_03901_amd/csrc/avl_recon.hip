@@ -105,6 +105,17 @@ struct Corners {
 };
 
 
+// Lane l receives lane l-1's value (lane 0 receives 0): a DPP shift of the
+// whole wavefront by one lane, two 32-bit moves for a double.
+__device__ __forceinline__ double from_left(double v)
+{
+    constexpr int kWaveShr1 = 0x138;
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, kWaveShr1, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), kWaveShr1, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ void wave_sync_lds()
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -290,10 +301,11 @@ struct Seg {
 __device__ __forceinline__ Seg make_seg(int beg, int end, int first_lane, int last_lane, bool wrapped)
 {
     Seg s;
-    s.lo = __shfl(beg, first_lane, kWave);
-    const int hi = __shfl(end, last_lane, kWave);
-    s.wbeg = __shfl(beg, 0, kWave);
-    const int wend = __shfl(end, 0, kWave);
+    // the lanes are wave-uniform: scalar reads of one lane each
+    s.lo = __builtin_amdgcn_readlane(beg, first_lane);
+    const int hi = __builtin_amdgcn_readlane(end, last_lane);
+    s.wbeg = __builtin_amdgcn_readlane(beg, 0);
+    const int wend = __builtin_amdgcn_readlane(end, 0);
     s.nmain = hi - s.lo;
     s.wlen = wrapped ? wend - s.wbeg : 0;
     return s;
@@ -321,9 +333,13 @@ __device__ __forceinline__ void prefetch(const typename RT<PREC>::M& m, const Se
     const int off = lane * V * esz;
 #pragma unroll
     for (int u = 0; u < KU / V; ++u) r[u] = src.loadv(off, u * kWave * V * esz);
-    Src<PREC> ws;
-    ws.init(m, __builtin_amdgcn_readfirstlane(s.wbeg), __builtin_amdgcn_readfirstlane(fit ? s.wlen : 0));
-    w = ws.load(lane * esz, 0);
+    // the wrapped run exists for the first strip only (a wave-uniform test)
+    const int wl = __builtin_amdgcn_readfirstlane(fit ? s.wlen : 0);
+    if (wl > 0) {
+        Src<PREC> ws;
+        ws.init(m, __builtin_amdgcn_readfirstlane(s.wbeg), wl);
+        w = ws.load(lane * esz, 0);
+    }
 }
 
 // Register prefetch depth: rows of markers in flight per wave while one row
@@ -452,10 +468,10 @@ __device__ __forceinline__ void recon_task(const Geo& g, const typename RT<PREC>
         c.from(M, len);
 
         // corner partials of the left neighbour run (lane - 1)
-        const double n10l = __shfl_up(c.n10, 1, kWave);
-        const double d10l = __shfl_up(c.d10, 1, kWave);
-        const double n11l = __shfl_up(c.n11, 1, kWave);
-        const double d11l = __shfl_up(c.d11, 1, kWave);
+        const double n10l = from_left(c.n10);
+        const double d10l = from_left(c.d10);
+        const double n11l = from_left(c.n11);
+        const double d11l = from_left(c.d11);
 
         // target row j = ((up01 + up11 of dual row j-1) + down00) + down10 of
         // dual row j, in this order in both walk directions
