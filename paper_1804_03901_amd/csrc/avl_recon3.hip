@@ -6,37 +6,55 @@
 // (x, vx) part -- the 1D-1V corner weights -- and a (vy, vz) part
 // w = (1-by or by)(1-bz or bz).  A target (vy, vz) plane therefore receives
 // from four dual planes (jy-cy, jz-cz), cy, cz in {0, 1}, each contributing a
-// 1D-1V-like (x, vx) reconstruction with per-marker weight w.  One wave owns
-// a strip of 63 target x columns and all vx rows of one target plane; for
-// every vx row it walks the four dual planes in a fixed order, staging each
-// row segment through LDS (the next segment is prefetched into registers while
-// the current one is summed), and sums per run eight moments of (a, bx)
-// weighted by f w and by w (product-sums as fused multiply-adds).  Sums are
-// FP64 and in a fixed order: no atomics.
+// 1D-1V-like (x, vx) reconstruction with per-marker weight w.
 //
-// Neighbouring target planes read the same dual planes; tasks are dealt so
-// that each XCD takes consecutive target planes (vy fastest), which keeps the
-// re-reads in its L2 or in the memory-side cache.
+// One wave owns a strip of 63 target x columns, all vx rows, and a 2x2 block
+// of target (vy, vz) planes; the block draws on a 3x3 block of dual planes.
+// For every dual vx row the wave walks the nine dual-plane row segments; each
+// is loaded from memory once into registers (the next segment's loads are in
+// flight meanwhile) and serves every target plane of the block it reaches
+// (one, two or four): per (segment, target) pass it is staged through LDS with
+// that target's w, and one lane per run sums eight moments of (a, bx)
+// weighted by f w and by w (product-sums as fused multiply-adds).  The
+// corners of the runs go to the target rows jd (lower) and jd + 1 (upper, kept
+// until the next dual row).  Sums are FP64 and in a fixed order: no atomics.
+//
+// A dual plane is still read by up to four blocks, 2.25 times on average
+// instead of four times with one target plane per wave; tasks are dealt so
+// that each XCD takes consecutive blocks (vy fastest), which keeps most of
+// these re-reads in its L2 or in the memory-side cache.
 #include "avl_device.h"
 
 namespace avl {
 
-constexpr int kKU3 = 8;                       // prefetched markers per lane (segment up to 512)
-constexpr int kCap3 = kWave * kKU3;
-
 template <int PREC> struct R3;
+// KU: markers per lane held in registers (a segment of up to 64 KU markers is
+// staged); SLOTS: staged markers in LDS, main range and wrapped run together;
+// WAVES: waves per SIMD the register budget is fitted to.
 template <> struct R3<0> {
     using M = M64;
     using T = double;
+    static constexpr int KU = 6, SLOTS = KU * kWave + kWave, WAVES = 2;
 };
 template <> struct R3<1> {
     using M = M32;
     using T = float;
+    static constexpr int KU = 5, SLOTS = 352, WAVES = 3;   // 11 KB of LDS
 };
 
 // One staged marker: (x, vx) offsets, and the (vy, vz) weight w and f w.
 struct St3 {
     double a, b, w, fw;
+};
+
+// The (vy, vz) corner of a pass as w = (sy by + oy)(sz bz + oz): (s, o) is
+// (1, 0) for the upper neighbour (weight b) and (-1, 1) for the lower (1 - b);
+// either form is exact, so w is the product of the two factors as written.
+struct Wsel {
+    double sy, oy, sz, oz;
+    __device__ Wsel(int cy, int cz)
+        : sy(cy ? 1.0 : -1.0), oy(cy ? 0.0 : 1.0), sz(cz ? 1.0 : -1.0), oz(cz ? 0.0 : 1.0) {}
+    __device__ double w(double by, double bz) const { return __fma_rn(sy, by, oy) * __fma_rn(sz, bz, oz); }
 };
 
 // Raw marker fields as loaded.
@@ -50,7 +68,7 @@ template <> struct Raw3<0> {
         vz = m.v[2 * (size_t)g.np + q];
         f = m.f[q];
     }
-    __device__ St3 stage(const Geo& g, int cy, int cz) const {
+    __device__ St3 stage(const Geo& g, const Wsel& ws) const {
         int ix, jp[3];
         double a, b[3];
         double vv[3] = {vx, vy, vz};
@@ -58,7 +76,7 @@ template <> struct Raw3<0> {
         St3 s;
         s.a = a;
         s.b = b[0];
-        s.w = (cy ? b[1] : 1.0 - b[1]) * (cz ? b[2] : 1.0 - b[2]);
+        s.w = ws.w(b[1], b[2]);
         s.fw = f * s.w;
         return s;
     }
@@ -72,16 +90,26 @@ template <> struct Raw3<1> {
         bz = m.b[2 * (size_t)g.np + q];
         f = m.f[q];
     }
-    __device__ St3 stage(const Geo&, int cy, int cz) const {
-        const double y = by, zz = bz;
+    __device__ St3 stage(const Geo&, const Wsel& ws) const {
         St3 s;
         s.a = a;
         s.b = bx;
-        s.w = (cy ? y : 1.0 - y) * (cz ? zz : 1.0 - zz);
+        s.w = ws.w(by, bz);
         s.fw = (double)f * s.w;
         return s;
     }
 };
+
+// Lane l receives lane l-1's value (lane 0 receives 0): a DPP shift of the
+// whole wavefront by one lane, two 32-bit moves for a double.
+__device__ __forceinline__ double from_left3(double v)
+{
+    constexpr int kWaveShr1 = 0x138;
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, kWaveShr1, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), kWaveShr1, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
 
 __device__ __forceinline__ void wave_sync_lds3()
 {
@@ -94,21 +122,28 @@ struct Seg3 {
 };
 
 template <int PREC>
-__global__ __launch_bounds__(kWave) void k_recon_3v(Geo g, typename R3<PREC>::M m, const int* __restrict__ offsets,
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(R3<PREC>::WAVES))) void k_recon_3v(Geo g, typename R3<PREC>::M m, const int* __restrict__ offsets,
                                                     typename R3<PREC>::T* __restrict__ fgrid,
                                                     typename R3<PREC>::T* __restrict__ Dgrid,
                                                     double* __restrict__ rho_part, int tasks_per_xcd)
 {
     using T = typename R3<PREC>::T;
-    __shared__ St3 st[kCap3 + kWave];
+    constexpr int KU = R3<PREC>::KU, CAP = KU * kWave, SLOTS = R3<PREC>::SLOTS;
+    __shared__ St3 st[SLOTS];
     const int lane = threadIdx.x;
-    const int ntask = g.nstrip * g.nv[1] * g.nv[2];
+    const int nby = (g.nv[1] + 1) >> 1, nbz = (g.nv[2] + 1) >> 1;
+    const int ntask = g.nstrip * nby * nbz;
     const int task = (blockIdx.x & 7) * tasks_per_xcd + (blockIdx.x >> 3);
     if ((blockIdx.x >> 3) >= tasks_per_xcd || task >= ntask) return;
-    // task = (strip * nvz + jz) * nvy + jy: consecutive tasks are neighbouring planes
-    const int jy = task % g.nv[1];
-    const int jz = (task / g.nv[1]) % g.nv[2];
-    const int strip = task / (g.nv[1] * g.nv[2]);
+    // task = (strip * nbz + bz) * nby + by: consecutive tasks are neighbouring blocks
+    const int by = task % nby;
+    const int bz = (task / nby) % nbz;
+    const int strip = task / (nby * nbz);
+    // target planes (jy0 + ty, jz0 + tz), ty < nyt, tz < nzt; dual planes
+    // (jy0 - 1 + iy, jz0 - 1 + iz), iy < ndy = nyt + 1, iz < ndz = nzt + 1
+    const int jy0 = 2 * by, jz0 = 2 * bz;
+    const int nyt = min(2, g.nv[1] - jy0), nzt = min(2, g.nv[2] - jz0);
+    const int ndy = nyt + 1, ndz = nzt + 1;
     const int nx = g.nx, nvx = g.nv[0];
     const int col = strip * kReconCols - 1 + lane;
     const bool run_ok = col < nx;
@@ -120,16 +155,26 @@ __global__ __launch_bounds__(kWave) void k_recon_3v(Geo g, typename R3<PREC>::M 
     const int last_lane = last_col - (strip * kReconCols - 1);
     const int rowsy = g.nv[1] + 1, rowsx = nvx + 1;
 
-    // segment s = (dual x-velocity row jd in [-1, nvx-1]) * 4 + (vy, vz) corner p;
-    // p = cz * 2 + cy names the dual plane (jy - cy, jz - cz)
-    const int nseg = (nvx + 1) * 4;
-    auto seg_bounds = [&](int s, int& beg, int& end) {
+    // Segments are visited row by row (dual vx row r = jd + 1 in [0, nvx]),
+    // and within a row plane by plane (iy fastest).  A cursor names a
+    // segment; run bounds are fetched two segments ahead, markers one.
+    struct Cur {
+        int r, iy, iz;
+    };
+    auto advance = [&](Cur& c) {
+        if (++c.iy == ndy) {
+            c.iy = 0;
+            if (++c.iz == ndz) {
+                c.iz = 0;
+                ++c.r;
+            }
+        }
+    };
+    auto seg_bounds = [&](const Cur& c, int& beg, int& end) {
         beg = 0;
         end = 0;
-        if (s < nseg && run_ok) {
-            const int jd = s / 4 - 1, p = s & 3;
-            const int jyd = jy - (p & 1), jzd = jz - (p >> 1);
-            const int row = ((jzd + 1) * rowsy + (jyd + 1)) * rowsx + (jd + 1);
+        if (c.r <= nvx && run_ok) {
+            const int row = ((jz0 + c.iz) * rowsy + (jy0 + c.iy)) * rowsx + c.r;
             const int bk = row * nx + colw;
             beg = offsets[bk];
             end = offsets[bk + 1];
@@ -137,127 +182,134 @@ __global__ __launch_bounds__(kWave) void k_recon_3v(Geo g, typename R3<PREC>::M 
     };
     auto make = [&](int beg, int end) {
         Seg3 s;
-        s.lo = __shfl(beg, first_lane, kWave);
-        const int hi = __shfl(end, last_lane, kWave);
-        s.wbeg = __shfl(beg, 0, kWave);
-        const int wend = __shfl(end, 0, kWave);
+        s.lo = __builtin_amdgcn_readlane(beg, first_lane);
+        const int hi = __builtin_amdgcn_readlane(end, last_lane);
+        s.wbeg = __builtin_amdgcn_readlane(beg, 0);
+        const int wend = __builtin_amdgcn_readlane(end, 0);
         s.nmain = hi - s.lo;
         s.wlen = wrapped ? wend - s.wbeg : 0;
         return s;
     };
-    auto fits = [&](const Seg3& s) { return s.nmain <= kCap3 && s.wlen <= kWave; };
+    auto fits = [&](const Seg3& s) { return s.nmain <= CAP && s.wlen <= kWave && s.nmain + s.wlen <= SLOTS; };
 
-    Raw3<PREC> regs[kKU3], wreg;
+    Raw3<PREC> regs[KU], wreg;
     auto prefetch = [&](const Seg3& s) {
         if (!fits(s)) return;
 #pragma unroll
-        for (int k = 0; k < kKU3; ++k) {
+        for (int k = 0; k < KU; ++k) {
             const int p = lane + k * kWave;
             if (p < s.nmain) regs[k].load(m, g, s.lo + p);
         }
         if (lane < s.wlen) wreg.load(m, g, s.wbeg + lane);
     };
 
+    Cur cur{0, 0, 0}, ahead{0, 0, 0};
     int beg, end, nbeg, nend;
-    seg_bounds(0, beg, end);
+    seg_bounds(ahead, beg, end);
     Seg3 seg = make(beg, end);
     prefetch(seg);
-    seg_bounds(1, nbeg, nend);
+    advance(ahead);
+    seg_bounds(ahead, nbeg, nend);
+    advance(ahead);
 
-    double upN[4] = {0.0, 0.0, 0.0, 0.0}, upD[4] = {0.0, 0.0, 0.0, 0.0};
-    double rowN = 0.0, rowD = 0.0;
-    double rp = 0.0;
+    // per target plane t = tz * 2 + ty: row jd so far (cN) and row jd + 1 (uN)
+    double cN[4] = {0.0, 0.0, 0.0, 0.0}, cD[4] = {0.0, 0.0, 0.0, 0.0};
+    double uN[4] = {0.0, 0.0, 0.0, 0.0}, uD[4] = {0.0, 0.0, 0.0, 0.0};
+    double rp[4] = {0.0, 0.0, 0.0, 0.0};
 
-    for (int s = 0; s < nseg; ++s) {
-        const int jd = s / 4 - 1, p = s & 3;
-        const int cy = p & 1, cz = p >> 1;
+    while (cur.r <= nvx) {
+        const int iy = cur.iy, iz = cur.iz;
         const bool staged = fits(seg);
-        if (staged) {
-#pragma unroll
-            for (int k = 0; k < kKU3; ++k) {
-                const int q = lane + k * kWave;
-                if (q < seg.nmain) st[q] = regs[k].stage(g, cy, cz);
-            }
-            if (lane < seg.wlen) st[seg.nmain + lane] = wreg.stage(g, cy, cz);
-        }
-        wave_sync_lds3();
         const int p0 = staged ? ((wrapped && lane == 0) ? seg.nmain : beg - seg.lo) : beg;
         const int len = end - beg;
-        Seg3 nseg_ = make(nbeg, nend);
-        if (s + 1 < nseg) prefetch(nseg_);
-        int nnbeg, nnend;
-        seg_bounds(s + 2, nnbeg, nnend);
+        const Seg3 nxt = make(nbeg, nend);
+        // the last target plane this dual plane reaches; the next segment's
+        // loads go out once its staging no longer needs the registers
+        const int tlast = min(iz, nzt - 1) * 2 + min(iy, nyt - 1);
 
-        // moments of (a, b) weighted by w and by f w
-        double Sw = 0, Saw = 0, Sbw = 0, Sabw = 0, Sf = 0, Saf = 0, Sbf = 0, Sabf = 0;
-        if (staged) {
-            for (int k = 0; k < len; ++k) {
-                const St3 e = st[p0 + k];
-                const double ab = e.a * e.b;
-                Sw += e.w;
-                Saw = __fma_rn(e.a, e.w, Saw);
-                Sbw = __fma_rn(e.b, e.w, Sbw);
-                Sabw = __fma_rn(ab, e.w, Sabw);
-                Sf += e.fw;
-                Saf = __fma_rn(e.a, e.fw, Saf);
-                Sbf = __fma_rn(e.b, e.fw, Sbf);
-                Sabf = __fma_rn(ab, e.fw, Sabf);
-            }
-        } else {
-            for (int k = 0; k < len; ++k) {
-                Raw3<PREC> r;
-                r.load(m, g, p0 + k);
-                const St3 e = r.stage(g, cy, cz);
-                const double ab = e.a * e.b;
-                Sw += e.w;
-                Saw = __fma_rn(e.a, e.w, Saw);
-                Sbw = __fma_rn(e.b, e.w, Sbw);
-                Sabw = __fma_rn(ab, e.w, Sabw);
-                Sf += e.fw;
-                Saf = __fma_rn(e.a, e.fw, Saf);
-                Sbf = __fma_rn(e.b, e.fw, Sbf);
-                Sabf = __fma_rn(ab, e.fw, Sabf);
-            }
-        }
-        wave_sync_lds3();
-        const double n11 = Sabf, n10 = Saf - Sabf, n01 = Sbf - Sabf, n00 = (Sf - Saf) - n01;
-        const double d11 = Sabw, d10 = Saw - Sabw, d01 = Sbw - Sabw, d00 = (Sw - Saw) - d01;
-        const double n10l = __shfl_up(n10, 1, kWave);
-        const double d10l = __shfl_up(d10, 1, kWave);
-        const double n11l = __shfl_up(n11, 1, kWave);
-        const double d11l = __shfl_up(d11, 1, kWave);
-
-        // target row jd of this plane: the carry from dual row jd-1 plus this row
-        double cN = 0.0, cD = 0.0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (q == p) {
-                cN = upN[q];
-                cD = upD[q];
-                upN[q] = n01 + n11l;
-                upD[q] = d01 + d11l;
+        for (int t = 0; t < 4; ++t) {
+            const int ty = t & 1, tz = t >> 1;
+            const int cy = ty - iy + 1, cz = tz - iz + 1;     // corner of the dual plane
+            if (ty >= nyt || tz >= nzt || cy < 0 || cy > 1 || cz < 0 || cz > 1) continue;
+            const Wsel ws(cy, cz);
+            if (staged) {
+#pragma unroll
+                for (int k = 0; k < KU; ++k) {
+                    if (k * kWave >= seg.nmain) break;         // wave-uniform
+                    const int q = lane + k * kWave;
+                    if (q < seg.nmain) st[q] = regs[k].stage(g, ws);
+                }
+                if (lane < seg.wlen) st[seg.nmain + lane] = wreg.stage(g, ws);
             }
-        rowN += (cN + n00) + n10l;
-        rowD += (cD + d00) + d10l;
-        if (p == 3) {
-            if (jd >= 0 && tgt_ok) {
-                const double fv = rowD > 0.0 ? rowN / rowD : 0.0;
-                const size_t gi = (((size_t)jz * g.nv[1] + jy) * nvx + jd) * nx + col;
-                fgrid[gi] = (T)fv;
-                if (Dgrid) Dgrid[gi] = (T)rowD;
-                rp += (double)(T)fv;
+            if (t == tlast) prefetch(nxt);
+            wave_sync_lds3();
+            // moments of (a, b) weighted by w and by f w
+            double Sw = 0, Saw = 0, Sbw = 0, Sabw = 0, Sf = 0, Saf = 0, Sbf = 0, Sabf = 0;
+            auto acc = [&](const St3& e) {
+                const double ab = e.a * e.b;
+                Sw += e.w;
+                Saw = __fma_rn(e.a, e.w, Saw);
+                Sbw = __fma_rn(e.b, e.w, Sbw);
+                Sabw = __fma_rn(ab, e.w, Sabw);
+                Sf += e.fw;
+                Saf = __fma_rn(e.a, e.fw, Saf);
+                Sbf = __fma_rn(e.b, e.fw, Sbf);
+                Sabf = __fma_rn(ab, e.fw, Sabf);
+            };
+            if (staged) {
+#pragma unroll 2
+                for (int k = 0; k < len; ++k) acc(st[p0 + k]);
+            } else {
+                for (int k = 0; k < len; ++k) {
+                    Raw3<PREC> rr;
+                    rr.load(m, g, p0 + k);
+                    acc(rr.stage(g, ws));
+                }
             }
-            rowN = 0.0;
-            rowD = 0.0;
+            wave_sync_lds3();
+            const double n11 = Sabf, n10 = Saf - Sabf, n01 = Sbf - Sabf, n00 = (Sf - Saf) - n01;
+            const double d11 = Sabw, d10 = Saw - Sabw, d01 = Sbw - Sabw, d00 = (Sw - Saw) - d01;
+            cN[t] += n00 + from_left3(n10);
+            cD[t] += d00 + from_left3(d10);
+            uN[t] += n01 + from_left3(n11);
+            uD[t] += d01 + from_left3(d11);
         }
 
+        if (iy == ndy - 1 && iz == ndz - 1) {
+            // target row jd = r - 1 of every plane of the block is complete
+            const int jd = cur.r - 1;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int ty = t & 1, tz = t >> 1;
+                if (ty < nyt && tz < nzt && jd >= 0 && tgt_ok) {
+                    const double fv = cD[t] > 0.0 ? cN[t] / cD[t] : 0.0;
+                    const size_t gi = (((size_t)(jz0 + tz) * g.nv[1] + (jy0 + ty)) * nvx + jd) * nx + col;
+                    fgrid[gi] = (T)fv;
+                    if (Dgrid) Dgrid[gi] = (T)cD[t];
+                    rp[t] += (double)(T)fv;
+                }
+                cN[t] = uN[t];
+                cD[t] = uD[t];
+                uN[t] = 0.0;
+                uD[t] = 0.0;
+            }
+        }
+
+        advance(cur);
         beg = nbeg;
         end = nend;
-        nbeg = nnbeg;
-        nend = nnend;
-        seg = nseg_;
+        seg = nxt;
+        seg_bounds(ahead, nbeg, nend);
+        advance(ahead);
     }
-    if (tgt_ok) rho_part[((size_t)jz * g.nv[1] + jy) * nx + col] = rp;
+    if (tgt_ok) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int ty = t & 1, tz = t >> 1;
+            if (ty < nyt && tz < nzt) rho_part[((size_t)(jz0 + tz) * g.nv[1] + (jy0 + ty)) * nx + col] = rp[t];
+        }
+    }
 }
 
 size_t recon3_scratch_bytes(const Geo&) { return 0; }
@@ -265,7 +317,7 @@ size_t recon3_scratch_bytes(const Geo&) { return 0; }
 hipError_t launch_recon3(const Geo& g, void* m, const int* offsets, void* fgrid, void* Dgrid, double* rho_part,
                          void*, hipStream_t st)
 {
-    const int tasks = g.nstrip * g.nv[1] * g.nv[2];
+    const int tasks = g.nstrip * ((g.nv[1] + 1) / 2) * ((g.nv[2] + 1) / 2);
     const int per_xcd = (tasks + 7) / 8;
     const int blocks = per_xcd * 8;
     if (g.prec == 0)
