@@ -185,7 +185,8 @@ int make_geo(const avl_config* c, Geo* g)
         g->nchunk = (c->nv[0] + rc - 1) / rc;
         g->cap = recon_capacity(c->precision);
     } else {
-        // 1D-3V FP32 encoding of the x-velocity dual index
+        // 1D-3V FP32 encoding of the x-velocity dual index: jrange is a power
+        // of two (the kernels decode it with a mask and a shift)
         int jr = 1;
         while (jr < c->nv[0] + 1 + 64) jr <<= 1;
         g->jrange = jr;

@@ -236,8 +236,9 @@ __device__ __forceinline__ int bucket32(const Geo& g, int cell)
     if (VD == 1) return (cell >= 0 && cell < g.nb) ? cell : g.nb;
     int ix = cell & (g.nx - 1);
     int r = cell >> g.lognx;
-    int jx = (r % g.jrange) - g.jpad;
-    int yz = r / g.jrange;
+    // jrange is a power of two (a wave-uniform shift, no integer division)
+    int jx = (r & (g.jrange - 1)) - g.jpad;
+    int yz = r >> __builtin_ctz(g.jrange);
     if (cell < 0 || jx < 0 || jx > g.nv[0]) return g.nb;
     return (yz * (g.nv[0] + 1) + jx) * g.nx + ix;
 }
@@ -257,7 +258,7 @@ __device__ __forceinline__ void push32(const Geo& g, const float2* sE, const Row
     int r = cell >> g.lognx;
     int jx, rest;
     if (VD == 1) { jx = r; rest = 0; }
-    else { jx = (r % g.jrange) - g.jpad; rest = r / g.jrange; }
+    else { jx = (r & (g.jrange - 1)) - g.jpad; rest = r >> __builtin_ctz(g.jrange); }
     const float2 e = sE[ix];
     float bn = b + (e.x + a * e.y);
     float fl = floorf(bn);

@@ -434,8 +434,8 @@ __global__ void k_to64(Geo g, M32 m, double* __restrict__ x, double* __restrict_
         if (g.vdim == 1) {
             jp[0] = r;
         } else {
-            jp[0] = (r % g.jrange) - g.jpad;
-            const int yz = r / g.jrange;
+            jp[0] = (r & (g.jrange - 1)) - g.jpad;
+            const int yz = r >> __builtin_ctz(g.jrange);
             jp[1] = yz % (g.nv[1] + 1);
             jp[2] = yz / (g.nv[1] + 1);
         }

@@ -182,3 +182,47 @@ def test_3v_magnetised_step_matches_oracle(graph):
     assert np.max(np.abs(vg[:, a] - vo[:, b])) <= TOL64 * (w.vmax[0] - w.vmin[0])
     # the perpendicular velocities did turn
     assert np.max(np.abs(vo[1:] - v[1:])) > 1e-3
+
+
+def test_full_size_two_stream_3v_sampled_planes():
+    """The 1D-3V benchmark workload at full size (nx = 512, 64^3 velocity
+    cells, 4 markers per cell: 536,870,912 markers, FP32 form), stepped as a
+    replayed graph as the benchmark does.  One step from the exported state is
+    checked on sampled target (vy, vz) planes -- two corners of the velocity
+    grid and an interior plane -- against the oracle's push and reconstruction
+    of the markers whose clouds reach those planes (selected from the exported
+    state by their own vy, vz; without a magnetic field the push keeps both),
+    at the FP32 form's bounds (1e-5 on f, 1e-6 on D, normwise per plane)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    w = inputs.two_stream_3v()
+    x, v, f = inputs.markers_threaded(w)
+    print(f"[case] {w.name} prec=fp32 n={x.size}", flush=True)
+    sim = avl.Simulation(w, x, v.reshape(-1), f, precision=avl.AVL_FP32)
+    del x, v, f
+    sim.step(2, graph=True, diag=False)
+    xt, vt, ft = sim.markers()
+    E = t2n(sim.field()[0])
+    planes = [(0, 0), (31, 17), (w.nv[1] - 1, w.nv[2] - 1)]
+    # dual-plane indices of every marker's cloud in vy and vz
+    jd = [torch.floor((vt[d] - w.vmin[d]) / ((w.vmax[d] - w.vmin[d]) / w.nv[d]) - 0.5) for d in (1, 2)]
+    keep = torch.zeros_like(ft, dtype=torch.bool)
+    for jy, jz in planes:
+        keep |= ((jd[0] == jy - 1) | (jd[0] == jy)) & ((jd[1] == jz - 1) | (jd[1] == jz))
+    xs, vs, fs = t2n(xt[keep]), t2n(vt[:, keep]), t2n(ft[keep])
+    del xt, vt, ft, jd, keep
+    print(f"[case] {xs.size} markers reach the sampled planes", flush=True)
+    sim.step(1, graph=True, diag=False)
+    fg, Dg = sim.reconstruct(want_D=True)
+    fg, Dg = fg.reshape(w.nv[2], w.nv[1], w.nv[0], w.nx), Dg.reshape(w.nv[2], w.nv[1], w.nv[0], w.nx)
+    sim.check()
+    g = oracle.Grid.from_workload(w)
+    xo, vo = oracle.push(g, xs, vs, E)
+    _, Do, fo = oracle.reconstruct(g, xo, vo, fs)
+    for jy, jz in planes:
+        ef = nrel(t2n(fg[jz, jy]), fo[jz, jy])
+        eD = nrel(t2n(Dg[jz, jy]), Do[jz, jy])
+        print(f"[result] plane (vy {jy}, vz {jz}): f {ef:.2e} D {eD:.2e}", flush=True)
+        assert ef <= 1e-5
+        assert eD <= 1e-6
+    sim.close()
