@@ -11,10 +11,11 @@
 // One wave owns a strip of 63 target x columns, all vx rows, and a 2x2 block
 // of target (vy, vz) planes; the block draws on a 3x3 block of dual planes.
 // For every dual vx row the wave walks the nine dual-plane row segments; each
-// is loaded from memory once into registers (the next segment's loads are in
-// flight meanwhile) and serves every target plane of the block it reaches
-// (one, two or four): per (segment, target) pass it is staged through LDS with
-// that target's w, and one lane per run sums eight moments of (a, bx)
+// is loaded from memory once into registers (the next segment's loads go out
+// once the last staging of the current one has read them) and serves every
+// target plane of the block it reaches (one, two or four): per (segment,
+// target) pass it is staged through LDS with that target's w, and one lane
+// per run sums eight moments of (a, bx)
 // weighted by f w and by w (product-sums as fused multiply-adds).  The
 // corners of the runs go to the target rows jd (lower) and jd + 1 (upper, kept
 // until the next dual row).  Sums are FP64 and in a fixed order: no atomics.
