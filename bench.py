@@ -90,8 +90,11 @@ def run_form(avl, inputs, w, x, v, f, form, steps, warmup):
     kt = {}
     for k, name in enumerate(avl.KERNEL_NAMES):
         tot, cnt = avl.avl_kernel_time(sim.h, k)
-        kt[name] = {"ms_avg": tot / cnt if cnt else None, "launches": cnt,
-                    "bytes_per_launch": avl.avl_kernel_bytes(sim.h, k)}
+        nbytes = avl.avl_kernel_bytes(sim.h, k)
+        ms_avg = tot / cnt if cnt else None
+        # algorithmic bytes per launch over the launch's mean duration, against the HBM peak
+        frac = nbytes / (ms_avg * 1e-3) / 1e9 / HBM_PEAK_GBS if ms_avg else None
+        kt[name] = {"ms_avg": ms_avg, "launches": cnt, "bytes_per_launch": nbytes, "hbm_frac": frac}
     avl.avl_timing(sim.h, False)
     sim.check()
     sim.close()
