@@ -26,6 +26,11 @@ CASES = {
     "landau": inputs.landau_small(),
     "ragged": inputs.bump_on_tail(nx=128, nv=100, ppc=7, seed=11),
     "stress": inputs.bump_on_tail(nx=256, nv=96, ppc=5, seed=12, weights="logu"),
+    # row segments of about 63 x 30 markers, past what a reconstruction wave
+    # stages in LDS (summed from global memory instead)
+    "long_rows": inputs.bump_on_tail(nx=64, nv=8, ppc=30, seed=14).replace(name="long_rows_nx64_nv8_ppc30"),
+    # one strip whose wrapped run (the column at x = L) exceeds a wavefront
+    "wrap": inputs.bump_on_tail(nx=8, nv=4, ppc=80, seed=15).replace(name="wrap_nx8_nv4_ppc80"),
 }
 
 

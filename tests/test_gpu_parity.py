@@ -64,6 +64,11 @@ CASES = {
     "tiny": inputs.landau_small().replace(name="tiny_nx8_nv2", nx=8, nv=(2, 1, 1), ppc=3),
     "stress": inputs.bump_on_tail(nx=256, nv=96, ppc=5, seed=12, weights="logu"),
     "wide_x": inputs.bump_on_tail(nx=1024, nv=16, ppc=6, seed=13),
+    # row segments of about 63 x 30 markers, past what a reconstruction wave
+    # stages in LDS (summed from global memory instead)
+    "long_rows": inputs.bump_on_tail(nx=64, nv=8, ppc=30, seed=14).replace(name="long_rows_nx64_nv8_ppc30"),
+    # one strip whose wrapped run (the column at x = L) exceeds a wavefront
+    "wrap": inputs.bump_on_tail(nx=8, nv=4, ppc=80, seed=15).replace(name="wrap_nx8_nv4_ppc80"),
 }
 
 
