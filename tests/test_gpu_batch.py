@@ -33,9 +33,13 @@ def t2n(t):
 
 
 def small_scan():
-    """Five uneven instances (one strip to three, ragged rows) and an empty one."""
+    """Five uneven instances (one strip to three, ragged rows), an empty one, and
+    two whose reconstruction sums from global memory: row segments past the LDS
+    capacity, and a wrapped run longer than a wavefront."""
     ws = inputs.batched_scan(count=5, seed=77, ppc=3, nx_choices=(16, 64, 128), nv_choices=(8, 30, 100))
     ws.append(inputs.bump_on_tail(nx=32, nv=16, ppc=0, seed=1).replace(name="empty_instance"))
+    ws.append(inputs.bump_on_tail(nx=64, nv=8, ppc=30, seed=14).replace(name="long_rows_instance"))
+    ws.append(inputs.bump_on_tail(nx=8, nv=4, ppc=80, seed=15).replace(name="wrap_instance"))
     return ws
 
 
