@@ -69,6 +69,11 @@ CASES = {
     "long_rows": inputs.bump_on_tail(nx=64, nv=8, ppc=30, seed=14).replace(name="long_rows_nx64_nv8_ppc30"),
     # one strip whose wrapped run (the column at x = L) exceeds a wavefront
     "wrap": inputs.bump_on_tail(nx=8, nv=4, ppc=80, seed=15).replace(name="wrap_nx8_nv4_ppc80"),
+    # the largest grid the single-block field solve takes; the last of its 66
+    # column strips holds one column.  (The FP32 form's x update adds b gamma,
+    # gamma = dv dt / dx, in FP32, so its position error grows with gamma: here
+    # about one cell per unit b, at the benchmark size 0.025.)
+    "max_nx": inputs.bump_on_tail(nx=4096, nv=96, ppc=2, seed=16).replace(name="max_nx4096_nv96_ppc2"),
 }
 
 
