@@ -117,6 +117,11 @@ def test_fp32_landau_damping_rate(opt):
     r = oracle.run(oracle.Grid.from_workload(w), x, v, f, w.steps)
     gam_o, _ = damping_rate(r["diag"][:, 1], w.dt)
     assert abs(gam_g - gam_o) <= 0.01 * abs(gam_o)
+    # the field-energy history of the whole run against the FP64 oracle's
+    W_g, W_o = d[:, 0], r["diag"][:, 0]
+    dW = float(np.max(np.abs(W_g - W_o)) / np.max(W_o))
+    print(f"[result] {opt}: damping rate {gam_g:.5f} (oracle {gam_o:.5f}), field energy history {dW:.2e}", flush=True)
+    assert dW <= 1e-5
 
 
 def test_fp32_export_round_trip():

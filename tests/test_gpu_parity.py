@@ -274,8 +274,20 @@ def test_full_size_bump_on_tail_step(precision):
     sim.step(1, graph=True, diag=False)
     fg, Dg = sim.reconstruct(want_D=True)
     E_g, rho_g = sim.field()
+    W_g = sim.diagnostics()["Ee"]
     sim.check()
+    W_o = oracle.field_energy(w.nx, w.L, w.c_p, E_o)
+    print(f"[result] {precision}: f {nrel(t2n(fg), fo):.2e} D {nrel(t2n(Dg), Do):.2e} rho {nrel(t2n(rho_g), rho_o):.2e} "
+          f"E {e_err(t2n(E_g), E_o, rho_o, w):.2e} W {abs(W_g - W_o) / W_o:.2e}", flush=True)
     assert nrel(t2n(fg), fo) <= tol_f
     assert nrel(t2n(Dg), Do) <= tol_r
     assert nrel(t2n(rho_g), rho_o) <= tol_r
     assert e_err(t2n(E_g), E_o, rho_o, w) <= tol_r
+    # field energy W = sum E^2 dx / (2 c_P): the FP64 bound follows from E's,
+    # |dW| <= max|dE| max|E| L / c_P with max|dE| <= TOL64 times the field scale;
+    # the FP32 form is held to 1e-5 of W itself
+    if precision == avl.AVL_FP64:
+        scale = w.c_p * np.max(np.abs(rho_o)) * w.L / (2 * math.pi)
+        assert abs(W_g - W_o) <= TOL64 * scale * np.max(np.abs(E_o)) * w.L / w.c_p
+    else:
+        assert abs(W_g - W_o) <= 1e-5 * W_o
