@@ -613,6 +613,19 @@ __device__ __forceinline__ void scan_tile(const int* __restrict__ counts, int nb
 {
     __shared__ int s_w[kScanThreads / kWave + 1];
     __shared__ int s_pre;
+    // the tile's counts first, so their loads overlap the tile-start sum
+    const int base = tile * kScanTile + threadIdx.x * kScanItems;
+    int c[kScanItems];
+    if (base + kScanItems <= nbt) {
+#pragma unroll
+        for (int k = 0; k < kScanItems; k += 4) {
+            const int4 v = *reinterpret_cast<const int4*>(counts + base + k);
+            c[k] = v.x; c[k + 1] = v.y; c[k + 2] = v.z; c[k + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) c[k] = (base + k < nbt) ? counts[base + k] : 0;
+    }
     // tile start
     int pre;
     if (scanned) {
@@ -626,18 +639,6 @@ __device__ __forceinline__ void scan_tile(const int* __restrict__ counts, int nb
     if (threadIdx.x == 0) {
         s_pre = pre;
         tsum_next[tile] = 0;
-    }
-    const int base = tile * kScanTile + threadIdx.x * kScanItems;
-    int c[kScanItems];
-    if (base + kScanItems <= nbt) {
-#pragma unroll
-        for (int k = 0; k < kScanItems; k += 4) {
-            const int4 v = *reinterpret_cast<const int4*>(counts + base + k);
-            c[k] = v.x; c[k + 1] = v.y; c[k + 2] = v.z; c[k + 3] = v.w;
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < kScanItems; ++k) c[k] = (base + k < nbt) ? counts[base + k] : 0;
     }
     int s = 0;
 #pragma unroll
