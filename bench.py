@@ -178,6 +178,47 @@ def cpu_baseline(inputs, w, x, v, f, steps):
     return x.size * steps / dt, dt
 
 
+def cpu_child(args):
+    """One copy of the all-core CPU baseline: generate the workload's markers,
+    solve once, report ready, wait for the go line on stdin, time
+    ``--cpu-steps`` oracle steps and print the rate.  Imports no GPU module."""
+    import oracle
+    from paper_1804_03901_amd import inputs
+    w = inputs.bump_on_tail(nx=args.nx, nv=args.nv, ppc=args.ppc)
+    x, v, f = inputs.markers(w)
+    g = oracle.Grid.from_workload(w)
+    r0 = oracle.run(g, x, v, f, 0)
+    print("ready", flush=True)
+    sys.stdin.readline()
+    t = time.perf_counter()
+    oracle.run(g, x, v, f, args.cpu_steps, E=r0["E"])
+    dt = time.perf_counter() - t
+    print(json.dumps({"rate": x.size * args.cpu_steps / dt, "seconds": dt}), flush=True)
+
+
+def cpu_baseline_all_cores(args, procs):
+    """The oracle on every core at once: ``procs`` independent copies of the
+    workload (child processes of their own, started together), each timing
+    ``--cpu-steps`` steps; the aggregate is the sum of their rates."""
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-child", "--nx", str(args.nx), "--nv", str(args.nv),
+           "--ppc", str(args.ppc), "--cpu-steps", str(args.cpu_steps)]
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    kids = [subprocess.Popen(cmd, stdin=subprocess.PIPE, stdout=subprocess.PIPE, text=True, env=env)
+            for _ in range(procs)]
+    try:
+        for k in kids:
+            if k.stdout.readline().strip() != "ready":
+                raise RuntimeError("a CPU baseline child did not start")
+        for k in kids:
+            k.stdin.write("go\n")
+            k.stdin.flush()
+        res = [json.loads(k.stdout.readline()) for k in kids]
+    finally:
+        for k in kids:
+            k.wait(timeout=300)
+    return sum(r["rate"] for r in res), max(r["seconds"] for r in res)
+
+
 def cpu_model():
     try:
         out = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
@@ -205,7 +246,13 @@ def main():
     ap.add_argument("--no-probe", action="store_true")
     ap.add_argument("--batch", type=int, default=64, help="instances of the batched parameter scan (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--cpu-cores", type=int, default=16,
+                    help="processes of the all-core CPU baseline (at most the host's cores; 0: skip)")
+    ap.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_child:
+        cpu_child(args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
         sys.exit(2)
@@ -285,6 +332,17 @@ def main():
                                "sample": f"{args.cpu_steps} steps of the full {w.n_markers}-marker workload "
                                          f"after the initial solve ({secs:.1f} s), FP64, single thread",
                                "cpu": cpu_model()}
+        procs = min(args.cpu_cores, os.cpu_count() or 1)
+        if procs > 1:
+            steps_all = max(1, args.cpu_steps // 8)
+            log(f"cpu baseline, all cores: {procs} oracle processes, {steps_all} steps each")
+            a = argparse.Namespace(**vars(args))
+            a.cpu_steps = steps_all
+            rate_all, secs_all = cpu_baseline_all_cores(a, procs)
+            out["cpu_baseline_all_cores"] = {
+                "value": rate_all, "unit": "marker-steps/s", "cores": procs, "kind": "oracle",
+                "sample": f"{procs} independent copies of the full {w.n_markers}-marker workload, "
+                          f"{steps_all} steps each after the initial solve ({secs_all:.1f} s), FP64, one thread each"}
     print(json.dumps(out), flush=True)
 
 
