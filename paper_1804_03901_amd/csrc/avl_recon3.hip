@@ -123,10 +123,9 @@ struct Seg3 {
 };
 
 template <int PREC>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(R3<PREC>::WAVES))) void k_recon_3v(Geo g, typename R3<PREC>::M m, const int* __restrict__ offsets,
-                                                    typename R3<PREC>::T* __restrict__ fgrid,
-                                                    typename R3<PREC>::T* __restrict__ Dgrid,
-                                                    double* __restrict__ rho_part, int tasks_per_xcd)
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(R3<PREC>::WAVES)))
+void k_recon_3v(Geo g, typename R3<PREC>::M m, const int* __restrict__ offsets, typename R3<PREC>::T* __restrict__ fgrid,
+                typename R3<PREC>::T* __restrict__ Dgrid, double* __restrict__ rho_part, int tasks_per_xcd)
 {
     using T = typename R3<PREC>::T;
     constexpr int KU = R3<PREC>::KU, CAP = KU * kWave, SLOTS = R3<PREC>::SLOTS;
