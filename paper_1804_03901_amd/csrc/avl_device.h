@@ -24,8 +24,11 @@ constexpr int kWave = 64;
 constexpr int kSortThreads = 256;
 constexpr int kSortMPT = 8;                               // markers per thread, scatter pass
 constexpr int kSortTile = kSortThreads * kSortMPT;
-constexpr int kCountMPT = 16;                             // markers per thread, count pass
-constexpr int kCountTile = kSortThreads * kCountMPT;
+constexpr int kCountMPT = 16;                             // markers per thread, count pass, FP32 form
+constexpr int kCountMPT64 = 12;                           // the same for the FP64 path (more registers a marker)
+constexpr int kCountTile = kSortThreads * kCountMPT;      // the larger count tile (window sizing)
+template <int PREC> constexpr int count_mpt() { return PREC ? kCountMPT : kCountMPT64; }
+constexpr int count_tile_size(int prec) { return kSortThreads * (prec ? kCountMPT : kCountMPT64); }
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;

@@ -268,11 +268,11 @@ struct Agg {
 // [first, first+K) of the tile [base, last] is in grp (previous order), the
 // field and drift table staged in LDS.
 template <int PREC, int VD, bool PUSH>
-__device__ __forceinline__ void count_tile(const Geo& g, const SortSmem<PREC>& sm, Group<PREC, VD, kCountMPT>& grp,
+__device__ __forceinline__ void count_tile(const Geo& g, const SortSmem<PREC>& sm, Group<PREC, VD, count_mpt<PREC>()>& grp,
                                            double dtk, float bk, int* __restrict__ counts, int* __restrict__ tsum,
                                            int base, int last, int* s_b, int* s_lo, int* s_nb, int* s_tile, int& fl)
 {
-    constexpr int K = kCountMPT;
+    constexpr int K = count_mpt<PREC>();
     const int first = base + threadIdx.x * K;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -327,9 +327,14 @@ __device__ __forceinline__ void count_tile(const Geo& g, const SortSmem<PREC>& s
     if (threadIdx.x < ntile_win && s_tile[threadIdx.x]) atomicAdd(&tsum[tlo + threadIdx.x], s_tile[threadIdx.x]);
 }
 
-// Tile t of the count pass covers markers [t*kCountTile, ...); in the FP32
-// form the push needs the velocity offset b[0] only.
-__device__ __forceinline__ int count_tile_last(const Geo& g, int t) { return min(t * kCountTile + kCountTile, g.n) - 1; }
+// Tile t of the count pass covers markers [t*T, ...), T = count_tile_size; in
+// the FP32 form the push needs the velocity offset b[0] only.
+template <int PREC>
+__device__ __forceinline__ int count_tile_last(const Geo& g, int t)
+{
+    constexpr int T = kSortThreads * count_mpt<PREC>();
+    return min(t * T + T, g.n) - 1;
+}
 
 // count pass of one block over one tile
 template <int PREC, int VD, bool PUSH>
@@ -343,12 +348,13 @@ __device__ __forceinline__ void count_block(const Geo& g, const typename Markers
     __shared__ int s_b[2], s_lo, s_nb, s_flags, s_tile[8];
     if (threadIdx.x == 0) s_flags = 0;
     if (PUSH) stage_tables<PREC>(g, sm.sE, sm.sRow, E, rows_g, bk);
-    Group<PREC, VD, kCountMPT> grp;
-    const int base = blk * kCountTile;
-    grp.load(m, g, base + threadIdx.x * kCountMPT, count_tile_last(g, blk), false, PREC ? 1 : VD);
+    constexpr int K = count_mpt<PREC>();
+    Group<PREC, VD, K> grp;
+    const int base = blk * (kSortThreads * K);
+    const int last = count_tile_last<PREC>(g, blk);
+    grp.load(m, g, base + threadIdx.x * K, last, false, PREC ? 1 : VD);
     int fl = 0;
-    count_tile<PREC, VD, PUSH>(g, sm, grp, dtk, bk, counts, tsum, base, count_tile_last(g, blk), s_b, &s_lo, &s_nb,
-                               s_tile, fl);
+    count_tile<PREC, VD, PUSH>(g, sm, grp, dtk, bk, counts, tsum, base, last, s_b, &s_lo, &s_nb, s_tile, fl);
     if (fl) atomicOr(&s_flags, fl);
     __syncthreads();
     if (threadIdx.x == 0 && s_flags) atomicOr(flags, s_flags);
@@ -695,7 +701,7 @@ static hipError_t launch_sort_t(const Geo& g, void* src, void* dst, const double
     // current one); the other forms hold more registers per marker and use
     // one tile per block.
     constexpr bool tiled = PREC == 1 && VD == 1;
-    const int cblocks = (g.n + kCountTile - 1) / kCountTile;
+    const int cblocks = (g.n + count_tile_size(PREC) - 1) / count_tile_size(PREC);
     const int stiles = (g.n + kSortTile - 1) / kSortTile;
     const int sblocks = tiled && g.sblocks > 0 ? std::min(stiles, g.sblocks) : stiles;
     const size_t smem = sort_smem<PREC>(g, push);
@@ -798,7 +804,7 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter_b(const BInst* __restr
 // Blocks of a batched pass for one instance (host side).
 int sort_blocks(const Geo& g, int phase)
 {
-    if (phase == 0) return (g.n + kCountTile - 1) / kCountTile;
+    if (phase == 0) return (g.n + count_tile_size(g.prec) - 1) / count_tile_size(g.prec);
     if (phase == 1) return (g.nb + 1 + kScanTile - 1) / kScanTile;
     return (g.n + kSortTile - 1) / kSortTile;
 }
