@@ -32,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PAPER_RATE_PER_CORE = 1.0e7      # marker updates per second on one CPU core, as the paper states it
 
 
 def log(msg):
@@ -311,6 +312,11 @@ def main():
                       "ms_per_step_direct": r[0], "marker_steps_per_s_direct": w.n_markers / (r[0] * 1e-3),
                       "kernels": r[2]} for k, r in results.items()},
     }
+    # the paper's own throughput figure (Sec. Performance and Parallelization), quoted with its
+    # hardware: context next to the measured rate, not a target (its workload is not stated)
+    out["paper_figure"] = {"value": PAPER_RATE_PER_CORE, "unit": "marker-steps/s per core",
+                           "hardware": "Intel Xeon E5-2650 @ 2.6 GHz, one core", "precision": "FP64 (inferred)",
+                           "source": "Sec. Performance and Parallelization", "workload": "not stated"}
     if "fp32" in results and "fp64" in results:
         out["fp32_speedup_over_fp64"] = results["fp64"][1] / results["fp32"][1]
     if args.batch and not three_v:
