@@ -48,6 +48,7 @@ hipError_t launch_adj_mu(int nx, const double* E, double w, double* mu_dep, doub
 int sort_blocks(const Geo& g, int phase);
 size_t sort_lds(const Geo& g);
 int scatter_blocks_per_cu(const Geo& g);
+int count_blocks_per_cu(const Geo& g);
 int diag_chunks(const Geo& g);
 hipError_t launch_diag(const Geo& g, const void* fgrid, const double* rho, const double* E, double mass,
                        double* part, double* out, double* j_out, double* drho_out, hipStream_t st);
@@ -609,6 +610,7 @@ int avl_init(const avl_config* cfg, void* workspace, size_t ws_bytes, void* stre
         set_lds_limit(lds);
         fit_lds(&h->g, lds);
         h->g.sblocks = scatter_blocks_per_cu(h->g) * device_cus();
+        h->g.cblocks = count_blocks_per_cu(h->g) * device_cus();
         if (debug_on())
             std::fprintf(stderr, "[avl] lds limit %d B, recon cap %d, hist bins %d, rc %d, chunks %d, strips %d\n", lds,
                          h->g.cap, h->g.hist_bins, h->g.rc, h->g.nchunk, h->g.nstrip);

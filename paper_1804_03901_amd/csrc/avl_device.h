@@ -55,6 +55,7 @@ struct Geo {
     int jpad, jrange;    // FP32 1D-3V: x-velocity dual index stored with offset jpad, range jrange
     int kahan;           // FP32 form: compensated FP32 accumulation instead of FP64 accumulators
     int sblocks;         // blocks of the tiled scatter (FP32 1D-1V): the resident capacity; 0 = a tile per block
+    int cblocks;         // blocks of the count pass: its resident capacity; 0 = a tile per block
     int magnetic;        // 1D-3V FP64 with a background magnetic field: Boris push
     double B[3];         // background magnetic field
     double L, inv_L, dx, inv_dx;

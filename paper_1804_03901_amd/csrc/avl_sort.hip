@@ -336,7 +336,8 @@ __device__ __forceinline__ int count_tile_last(const Geo& g, int t)
     return min(t * T + T, g.n) - 1;
 }
 
-// count pass of one block over one tile
+// count pass of one block over one tile (the batched kernel and the forms
+// without a tiled kernel)
 template <int PREC, int VD, bool PUSH>
 __device__ __forceinline__ void count_block(const Geo& g, const typename MarkersOf<PREC>::T& m,
                                             const double* __restrict__ E, const RowShift* __restrict__ rows_g,
@@ -369,6 +370,37 @@ __global__ __launch_bounds__(kSortThreads) void k_count(Geo g, typename MarkersO
                                                          int* __restrict__ flags)
 {
     count_block<PREC, VD, PUSH>(g, m, E, rows_g, dtk, bk, counts, tsum, flags, blockIdx.x);
+}
+
+// Tiled count pass: each block takes tiles blockIdx.x, blockIdx.x + gridDim.x,
+// ... (one block per resident slot), so the field and drift table are staged
+// once per block instead of once per tile.
+template <int PREC, int VD, bool PUSH>
+__global__ __launch_bounds__(kSortThreads) void k_count_tiled(Geo g, typename MarkersOf<PREC>::T m,
+                                                         const double* __restrict__ E,
+                                                         const RowShift* __restrict__ rows_g,
+                                                         double dtk, float bk,
+                                                         int* __restrict__ counts, int* __restrict__ tsum,
+                                                         int* __restrict__ flags)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    SortSmem<PREC> sm(smem, g);
+    __shared__ int s_b[2], s_lo, s_nb, s_flags, s_tile[8];
+    constexpr int K = count_mpt<PREC>();
+    constexpr int T = kSortThreads * K;
+    const int ntiles = (g.n + T - 1) / T;
+    if (threadIdx.x == 0) s_flags = 0;
+    if (PUSH) stage_tables<PREC>(g, sm.sE, sm.sRow, E, rows_g, bk);
+    int fl = 0;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        Group<PREC, VD, K> grp;
+        const int last = count_tile_last<PREC>(g, t);
+        grp.load(m, g, t * T + threadIdx.x * K, last, false, PREC ? 1 : VD);
+        count_tile<PREC, VD, PUSH>(g, sm, grp, dtk, bk, counts, tsum, t * T, last, s_b, &s_lo, &s_nb, s_tile, fl);
+    }
+    if (fl) atomicOr(&s_flags, fl);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_flags) atomicOr(flags, s_flags);
 }
 
 // ---------------------------------------------------------------------------
@@ -696,12 +728,13 @@ static hipError_t launch_sort_t(const Geo& g, void* src, void* dst, const double
     using MT = typename MarkersOf<PREC>::T;
     MT s = *reinterpret_cast<MT*>(src);
     MT d = dst ? *reinterpret_cast<MT*>(dst) : s;
-    // The FP32 1D-1V form uses the tiled scatter (one block per resident slot,
-    // each walking several tiles and loading the next while working on the
-    // current one); the other forms hold more registers per marker and use
-    // one tile per block.
+    // The FP32 1D-1V form uses the tiled count and scatter (one block per
+    // resident slot, each walking several tiles; the scatter loads the next
+    // while working on the current one); the other forms hold more registers
+    // per marker and use one tile per block.
     constexpr bool tiled = PREC == 1 && VD == 1;
-    const int cblocks = (g.n + count_tile_size(PREC) - 1) / count_tile_size(PREC);
+    const int ctiles = (g.n + count_tile_size(PREC) - 1) / count_tile_size(PREC);
+    const int cblocks = tiled && g.cblocks > 0 ? std::min(ctiles, g.cblocks) : ctiles;
     const int stiles = (g.n + kSortTile - 1) / kSortTile;
     const int sblocks = tiled && g.sblocks > 0 ? std::min(stiles, g.sblocks) : stiles;
     const size_t smem = sort_smem<PREC>(g, push);
@@ -709,12 +742,14 @@ static hipError_t launch_sort_t(const Geo& g, void* src, void* dst, const double
     static int granted[4] = {0, 0, 0, 0};
     {
         const void* fns[4];
-        fns[0] = (const void*)k_count<PREC, VD, true>;
-        fns[1] = (const void*)k_count<PREC, VD, false>;
         if constexpr (tiled) {
+            fns[0] = (const void*)k_count_tiled<PREC, VD, true>;
+            fns[1] = (const void*)k_count_tiled<PREC, VD, false>;
             fns[2] = (const void*)k_scatter<PREC, VD, true>;
             fns[3] = (const void*)k_scatter<PREC, VD, false>;
         } else {
+            fns[0] = (const void*)k_count<PREC, VD, true>;
+            fns[1] = (const void*)k_count<PREC, VD, false>;
             fns[2] = (const void*)k_scatter1<PREC, VD, true>;
             fns[3] = (const void*)k_scatter1<PREC, VD, false>;
         }
@@ -725,8 +760,13 @@ static hipError_t launch_sort_t(const Geo& g, void* src, void* dst, const double
     }
     const dim3 bl(kSortThreads);
     if (phase == 0) {
-        if (push) hipLaunchKernelGGL((k_count<PREC, VD, true>), dim3(cblocks), bl, smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags);
-        else hipLaunchKernelGGL((k_count<PREC, VD, false>), dim3(cblocks), bl, smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags);
+        if constexpr (tiled) {
+            if (push) hipLaunchKernelGGL((k_count_tiled<PREC, VD, true>), dim3(cblocks), bl, smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags);
+            else hipLaunchKernelGGL((k_count_tiled<PREC, VD, false>), dim3(cblocks), bl, smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags);
+        } else {
+            if (push) hipLaunchKernelGGL((k_count<PREC, VD, true>), dim3(cblocks), bl, smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags);
+            else hipLaunchKernelGGL((k_count<PREC, VD, false>), dim3(cblocks), bl, smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags);
+        }
     } else if (phase == 1) {
         // tile_sums: this sort's totals; tile_next: the other parity, cleared here
         const int nbt = g.nb + 1;
@@ -811,6 +851,24 @@ int sort_blocks(const Geo& g, int phase)
 
 // Blocks of the tiled scatter that fit on one CU at once for g's LDS size
 // (0 where the form has no tiled scatter); host side.
+// Resident blocks per CU of the tiled count pass (FP32 1D-1V) for this
+// geometry's LDS; 0 (a tile per block) for the other forms.
+int count_blocks_per_cu(const Geo& g)
+{
+    if (!(g.prec == 1 && g.vdim == 1)) return 0;
+    const size_t smem = sort_smem<1>(g, true);
+    static int granted = 0;
+    int per_cu = 0;
+    if (ensure_lds((const void*)k_count_tiled<1, 1, true>, smem, granted) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_count_tiled<1, 1, true>, kSortThreads,
+                                                     smem) != hipSuccess ||
+        per_cu <= 0) {
+        (void)hipGetLastError();
+        per_cu = 0;
+    }
+    return per_cu;
+}
+
 int scatter_blocks_per_cu(const Geo& g)
 {
     if (!(g.prec == 1 && g.vdim == 1)) return 0;
