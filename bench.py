@@ -307,7 +307,9 @@ def main():
                      "traffic_unit": "bytes per launch (PMC, calibrated)", "kernel": recon_kernel,
                      "bytes_per_launch": rk["bytes_per_launch"], "ms_per_launch": rk["ms_avg"]},
         "timing": "value: HIP-graph replay of the step, events around the whole timed region; kernels: a "
-                  "second timed region of direct launches with events around every kernel",
+                  "second timed region of direct launches; count, scatter and reconstruction carry HIP events "
+                  "attached to their own dispatch (the kernel's start and end), scan and field have events "
+                  "recorded around their launches",
         "forms": {k: {"ms_per_step": r[1], "marker_steps_per_s": w.n_markers / (r[1] * 1e-3),
                       "ms_per_step_direct": r[0], "marker_steps_per_s_direct": w.n_markers / (r[0] * 1e-3),
                       "kernels": r[2]} for k, r in results.items()},

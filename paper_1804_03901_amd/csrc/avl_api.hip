@@ -330,11 +330,29 @@ int report(hipError_t e, const char* what, int line)
         if (e_ != hipSuccess) return report(e_, #expr, __LINE__); \
     } while (0)
 
+}  // namespace
+
+namespace avl {
+KernelEvents& pending_events()
+{
+    static thread_local KernelEvents e{nullptr, nullptr};
+    return e;
+}
+}  // namespace avl
+
+namespace {
+
+// Events around one phase of a step on the library's stream.  A phase that is
+// one kernel launched through launch() (attach) hands its pair to that launch,
+// which then records the kernel's own start and end; if no launch took the
+// pair (nothing to do), both are recorded at once.
 struct Timer {
     avl_handle* h;
     int k;
-    hipEvent_t stop;
-    Timer(avl_handle* hh, int kk) : h(hh), k(kk), stop(nullptr)
+    hipEvent_t start, stop;
+    bool attach;
+    Timer(avl_handle* hh, int kk, bool single_kernel = false)
+        : h(hh), k(kk), start(nullptr), stop(nullptr), attach(single_kernel)
     {
         if (!h->timing) return;
         std::vector<hipEvent_t>& v = h->ev[k];
@@ -345,13 +363,22 @@ struct Timer {
                 v.push_back(e);
             }
         }
-        (void)hipEventRecord(v[h->ev_used[k]], h->st);
+        start = v[h->ev_used[k]];
         stop = v[h->ev_used[k] + 1];
         h->ev_used[k] += 2;
+        if (attach) pending_events() = KernelEvents{start, stop};
+        else (void)hipEventRecord(start, h->st);
     }
     ~Timer()
     {
-        if (stop) (void)hipEventRecord(stop, h->st);
+        if (!stop) return;
+        if (attach) {
+            KernelEvents& pe = pending_events();
+            if (pe.start != start) return;          // taken by the phase's kernel
+            pe = KernelEvents{nullptr, nullptr};
+            (void)hipEventRecord(start, h->st);
+        }
+        (void)hipEventRecord(stop, h->st);
     }
 };
 
@@ -409,7 +436,7 @@ int do_sort(avl_handle* h, bool push, double kick)
     int* tcur = h->tile_sums + (size_t)h->cur * tstride;
     int* tnext = h->tile_sums + (size_t)(1 - h->cur) * tstride;
     {
-        Timer t(h, AVL_K_PUSH_COUNT);
+        Timer t(h, AVL_K_PUSH_COUNT, true);
         AVL_TRY(launch_sort(g, src, dst, h->E, h->rows, dtk, bk, h->counts, h->offsets, tcur, tnext, h->flags,
                             push, h->st, 0));
     }
@@ -419,7 +446,7 @@ int do_sort(avl_handle* h, bool push, double kick)
                             push, h->st, 1));
     }
     {
-        Timer t(h, AVL_K_SCATTER);
+        Timer t(h, AVL_K_SCATTER, true);
         AVL_TRY(launch_sort(g, src, dst, h->E, h->rows, dtk, bk, h->counts, h->offsets, tcur, tnext, h->flags,
                             push, h->st, 2));
     }
@@ -437,7 +464,7 @@ int do_sort(avl_handle* h, bool push, double kick)
 int do_recon(avl_handle* h, void* Dgrid)
 {
     {
-        Timer t(h, AVL_K_RECONSTRUCT);
+        Timer t(h, AVL_K_RECONSTRUCT, true);
         if (h->g.vdim == 1)
             AVL_TRY(launch_recon(h->g, marker_view(h, h->cur), h->offsets, h->fgrid, Dgrid, h->rho_part, h->st));
         else

@@ -13,6 +13,7 @@
 //    that miss the velocity grid entirely go to one overflow bucket (index nb),
 //    which the reconstruction ignores.  Bucket rows therefore have nx entries.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -297,6 +298,28 @@ __device__ __forceinline__ void push32(const Geo& g, const float2* sE, const Row
     if (!(an + bn == an + bn)) flags |= FLAG_NONFINITE;
     a = an;
     b = bn;
+}
+
+// Host side: kernel launches that can carry timing events.  The library's
+// timer may leave a (start, stop) pair here for the next launch made through
+// launch() on this host thread; the pair then records that kernel's own start
+// and end (hipExtLaunchKernel), without the gaps around the dispatch.
+struct KernelEvents {
+    hipEvent_t start, stop;
+};
+KernelEvents& pending_events();
+
+template <typename F, typename... A>
+inline void launch(F kernel, dim3 grid, dim3 block, size_t smem, hipStream_t st, A... args)
+{
+    KernelEvents& pe = pending_events();
+    if (pe.start == nullptr) {
+        kernel<<<grid, block, smem, st>>>(args...);
+        return;
+    }
+    const KernelEvents ev = pe;
+    pe = KernelEvents{nullptr, nullptr};
+    hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)smem, st, ev.start, ev.stop, 0u, args...);
 }
 
 }  // namespace avl

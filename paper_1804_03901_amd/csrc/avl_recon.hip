@@ -584,13 +584,13 @@ hipError_t launch_recon(const Geo& g, void* m, const int* offsets, void* fgrid, 
     hipError_t e = ensure_lds(fns[var], smem, granted[var]);
     if (e != hipSuccess) return e;
     if (var == 0)
-        hipLaunchKernelGGL((k_recon_1v<0, false>), dim3(blocks), dim3(kWave), smem, st, g, *reinterpret_cast<M64*>(m),
+        launch(k_recon_1v<0, false>, dim3(blocks), dim3(kWave), smem, st, g, *reinterpret_cast<M64*>(m),
                            offsets, (double*)fgrid, (double*)Dgrid, rho_part, per_xcd);
     else if (var == 1)
-        hipLaunchKernelGGL((k_recon_1v<1, false>), dim3(blocks), dim3(kWave), smem, st, g, *reinterpret_cast<M32*>(m),
+        launch(k_recon_1v<1, false>, dim3(blocks), dim3(kWave), smem, st, g, *reinterpret_cast<M32*>(m),
                            offsets, (float*)fgrid, (float*)Dgrid, rho_part, per_xcd);
     else
-        hipLaunchKernelGGL((k_recon_1v<1, true>), dim3(blocks), dim3(kWave), smem, st, g, *reinterpret_cast<M32*>(m),
+        launch(k_recon_1v<1, true>, dim3(blocks), dim3(kWave), smem, st, g, *reinterpret_cast<M32*>(m),
                            offsets, (float*)fgrid, (float*)Dgrid, rho_part, per_xcd);
     return hipGetLastError();
 }

@@ -321,10 +321,10 @@ hipError_t launch_recon3(const Geo& g, void* m, const int* offsets, void* fgrid,
     const int per_xcd = (tasks + 7) / 8;
     const int blocks = per_xcd * 8;
     if (g.prec == 0)
-        hipLaunchKernelGGL(k_recon_3v<0>, dim3(blocks), dim3(kWave), 0, st, g, *reinterpret_cast<M64*>(m), offsets,
+        launch(k_recon_3v<0>, dim3(blocks), dim3(kWave), 0, st, g, *reinterpret_cast<M64*>(m), offsets,
                            (double*)fgrid, (double*)Dgrid, rho_part, per_xcd);
     else
-        hipLaunchKernelGGL(k_recon_3v<1>, dim3(blocks), dim3(kWave), 0, st, g, *reinterpret_cast<M32*>(m), offsets,
+        launch(k_recon_3v<1>, dim3(blocks), dim3(kWave), 0, st, g, *reinterpret_cast<M32*>(m), offsets,
                            (float*)fgrid, (float*)Dgrid, rho_part, per_xcd);
     return hipGetLastError();
 }

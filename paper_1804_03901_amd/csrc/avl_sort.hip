@@ -761,11 +761,11 @@ static hipError_t launch_sort_t(const Geo& g, void* src, void* dst, const double
     const dim3 bl(kSortThreads);
     if (phase == 0) {
         if constexpr (tiled) {
-            if (push) hipLaunchKernelGGL((k_count_tiled<PREC, VD, true>), dim3(cblocks), bl, smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags);
-            else hipLaunchKernelGGL((k_count_tiled<PREC, VD, false>), dim3(cblocks), bl, smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags);
+            if (push) launch(k_count_tiled<PREC, VD, true>, dim3(cblocks), bl, smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags);
+            else launch(k_count_tiled<PREC, VD, false>, dim3(cblocks), bl, smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags);
         } else {
-            if (push) hipLaunchKernelGGL((k_count<PREC, VD, true>), dim3(cblocks), bl, smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags);
-            else hipLaunchKernelGGL((k_count<PREC, VD, false>), dim3(cblocks), bl, smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags);
+            if (push) launch(k_count<PREC, VD, true>, dim3(cblocks), bl, smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags);
+            else launch(k_count<PREC, VD, false>, dim3(cblocks), bl, smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags);
         }
     } else if (phase == 1) {
         // tile_sums: this sort's totals; tile_next: the other parity, cleared here
@@ -780,11 +780,11 @@ static hipError_t launch_sort_t(const Geo& g, void* src, void* dst, const double
                            tile_next, offsets);
     } else {
         if constexpr (tiled) {
-            if (push) hipLaunchKernelGGL((k_scatter<PREC, VD, true>), dim3(sblocks), bl, smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags);
-            else hipLaunchKernelGGL((k_scatter<PREC, VD, false>), dim3(sblocks), bl, smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags);
+            if (push) launch(k_scatter<PREC, VD, true>, dim3(sblocks), bl, smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags);
+            else launch(k_scatter<PREC, VD, false>, dim3(sblocks), bl, smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags);
         } else {
-            if (push) hipLaunchKernelGGL((k_scatter1<PREC, VD, true>), dim3(sblocks), bl, smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags);
-            else hipLaunchKernelGGL((k_scatter1<PREC, VD, false>), dim3(sblocks), bl, smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags);
+            if (push) launch(k_scatter1<PREC, VD, true>, dim3(sblocks), bl, smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags);
+            else launch(k_scatter1<PREC, VD, false>, dim3(sblocks), bl, smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags);
         }
     }
     return hipGetLastError();
