@@ -54,7 +54,8 @@ hipError_t launch_diag(const Geo& g, const void* fgrid, const double* rho, const
                        double* part, double* out, double* j_out, double* drho_out, hipStream_t st);
 hipError_t launch_sort_batch(int prec, const BInst* tab, const int* pre, int ninst, int blocks, size_t smem, int cur,
                              hipStream_t st, int phase);
-hipError_t launch_recon_batch(int prec, int kahan, const BInst* tab, const int* pre, int ninst, int tasks, int cur,
+bool recon_sparse(const Geo& g);
+hipError_t launch_recon_batch(int prec, int kahan, int sparse, const BInst* tab, const int* pre, int ninst, int tasks, int cur,
                               hipStream_t st);
 hipError_t launch_field_batch(const BInst* tab, const int* pre, int ninst, int rho_blocks, int max_nx, int write_diag,
                               hipStream_t st);
@@ -1021,7 +1022,12 @@ int batch_launch(avl_batch* b, int cur, hipStream_t st)
     AVL_TRY(launch_sort_batch(b->prec, b->tab, b->pre, b->n, b->tot[BPRE_COUNT], b->lds, cur, st, 0));
     AVL_TRY(launch_sort_batch(b->prec, b->tab, b->pre, b->n, b->tot[BPRE_SCAN], b->lds, cur, st, 1));
     AVL_TRY(launch_sort_batch(b->prec, b->tab, b->pre, b->n, b->tot[BPRE_SCATTER], b->lds, cur, st, 2));
-    AVL_TRY(launch_recon_batch(b->prec, b->kahan, b->tab, b->pre, b->n, b->tot[BPRE_RECON], 1 - cur, st));
+    // the sparse-row kernels when every instance with markers has sparse rows
+    bool sparse = true;
+    for (avl_handle* hi : b->h)
+        if (hi->g.n > 0 && !recon_sparse(hi->g)) sparse = false;
+    AVL_TRY(launch_recon_batch(b->prec, b->kahan, sparse ? 1 : 0, b->tab, b->pre, b->n, b->tot[BPRE_RECON], 1 - cur,
+                               st));
     AVL_TRY(launch_field_batch(b->tab, b->pre, b->n, b->tot[BPRE_RHO], b->max_nx, 1, st));
     return AVL_OK;
 }
