@@ -184,8 +184,11 @@ void orc_moments(const orc_grid *g, const double *fg, double *rho, double *jx, d
  *   E_hat_{nx/2} = 0 (Nyquist; kappa vanishes there analytically)
  *   E_i = (1/nx) sum_m E_hat_m exp(+2 pi i m i / nx)   (real part)
  * The transform is an O(nx^2) direct sum; twiddle angles use the exact integer
- * reduction (m*i mod nx).  mode1 (optional) receives (2/nx)|DFT(E)_1|, the
- * amplitude of the longest-wavelength mode of E.
+ * reduction (m*i mod nx).  Since E_hat_0 = 0, a constant added to rho cannot
+ * change E; the mean of rho is subtracted before the sum, so that a large
+ * mean (the charge of the neutralised species) does not leak into the other
+ * modes through the rounding of the twiddles.  mode1 (optional) receives
+ * (2/nx)|DFT(E)_1|, the amplitude of the longest-wavelength mode of E.
  * ------------------------------------------------------------------------- */
 static double sinc(double y) { return y == 0.0 ? 1.0 : sin(y) / y; }
 
@@ -201,12 +204,15 @@ int orc_poisson(int nx, double L, double cp, const double *rho, double *E, doubl
         cs[r] = cos(2.0 * ORC_PI * r / nx);
         sn[r] = sin(2.0 * ORC_PI * r / nx);
     }
+    double mean = 0.0;
+    for (int i = 0; i < nx; ++i) mean += rho[i];
+    mean /= nx;
     for (int m = 0; m < nx; ++m) {
         double re = 0.0, im = 0.0;
         for (int i = 0; i < nx; ++i) {
             int r = (int)(((long)m * i) % nx);
-            re += rho[i] * cs[r];
-            im -= rho[i] * sn[r];
+            re += (rho[i] - mean) * cs[r];
+            im -= (rho[i] - mean) * sn[r];
         }
         if (m == 0 || 2 * m == nx) {
             er[m] = 0.0;

@@ -211,3 +211,30 @@ def test_boris_without_field_is_the_plain_kick():
     El = (1 - a) * E[i0 % g.nx] + a * E[(i0 + 1) % g.nx]
     assert np.array_equal(vs[1:], v[1:])
     assert np.allclose(vs[0], v[0] + (g.q / g.m) * El * g.dt, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("nx", [64, 1024, 4096])
+def test_constant_offset_leaves_field_unchanged(nx):
+    """E_hat_0 = 0 (Eq. (poissonk)): adding a constant to rho cannot change E.
+    The constant here is the size of the neutralised charge and far larger than
+    the fluctuation, as in every plasma run (rho ~ -1 + 1e-4 modes); the offset
+    values are chosen on a 2^-52 grid so that 1 + r is exact in FP64.  A solve
+    that lets the mean leak into the other modes through rounded twiddles
+    misses this by ~1e-11 of max|E|."""
+    rng = np.random.default_rng(nx + 7)
+    L, cp = 20.0 * math.pi, 1.0
+    xi = (np.arange(nx) + 0.5) * (L / nx)
+    r = sum(1e-4 * np.cos(0.1 * m * xi + rng.uniform(0, 2 * math.pi)) for m in range(1, 17))
+    r = np.round(r * 2.0 ** 52) * 2.0 ** -52
+    E_small, _ = oracle.poisson(nx, L, cp, r)
+    for dc in (-1.0, 1.0, 1.5):
+        big = dc + r
+        assert np.array_equal(big - dc, r)            # the offset is exact
+        E_big, _ = oracle.poisson(nx, L, cp, big)
+        assert np.max(np.abs(E_big - E_small)) <= 1e-14 * np.max(np.abs(E_small))
+    # and the offset-free solve itself is the finite-difference one
+    rhat = np.fft.fft(r)
+    rhat[nx // 2] = 0.0
+    rr = np.fft.ifft(rhat).real
+    E_rr, _ = oracle.poisson(nx, L, cp, rr)
+    assert np.max(np.abs(E_rr - _fd_solve(rr, L / nx, cp))) <= 1e-12 * np.max(np.abs(E_rr))
