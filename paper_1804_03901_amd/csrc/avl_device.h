@@ -300,6 +300,75 @@ __device__ __forceinline__ void push32(const Geo& g, const float2* sE, const Row
     b = bn;
 }
 
+// ---------------------------------------------------------------------------
+// Order-independent sums over a run of markers.
+//
+// The markers of one cell arrive in an order set by the sort's integer
+// atomics, which varies from run to run.  To make every reconstruction sum a
+// function of the run's multiset alone, each term is rounded down onto a grid
+// of spacing q = 2^e, chosen per run from an order-free bound (the run length
+// times the largest magnitude of its terms), and the grid points are added
+// exactly:
+//  * the accumulator starts at C = 3 * 2^51 * q; every value within 2^51 q of
+//    C is an FP64 number whose spacing is exactly q;
+//  * with the FP64 rounding mode set toward -infinity, acc + t (or a fused
+//    acc + x*y) then yields C + (m + floor(t/q)) q exactly;
+//  * so acc - C = q * sum floor(t/q) over the run, in any order.
+// The error is below q per term, i.e. below len * 2^-51 of the bound.  Code
+// between fixsum_round_down() and fixsum_round_nearest() must only add terms
+// to such accumulators; the values that cross either switch go through
+// fixsum_pin(), which keeps the compiler from moving their arithmetic across
+// it.  Where a loop also needs ordinary FP64 arithmetic (locating an FP64
+// marker), fixsum_floor() rounds a term onto the grid explicitly instead.
+// ---------------------------------------------------------------------------
+struct FixGrid {
+    double q;       // grid spacing 2^e
+    double inv_q;   // 2^-e
+    double C;       // accumulator origin 3 * 2^51 * q
+};
+
+// Power of two 2^e as an FP64 number, for e in the normal range.
+__device__ __forceinline__ double fix_pow2(int e) { return __longlong_as_double((long long)(e + 1023) << 52); }
+
+// Grid for len terms of magnitude below 2^(emax + 1).  The exponent is kept
+// where q, 1/q and C are all normal numbers (a coarser grid for terms below
+// 2^-900 still bounds them).
+__device__ __forceinline__ FixGrid fix_grid(int emax, int len)
+{
+    const int lg = len > 1 ? 32 - __builtin_clz((unsigned)(len - 1)) : 0;     // ceil(log2(len))
+    const int e = min(max(emax + 1 + lg - 51, -960), 960);
+    FixGrid gr;
+    gr.q = fix_pow2(e);
+    gr.inv_q = fix_pow2(-e);
+    gr.C = 3.0 * fix_pow2(e + 51);
+    return gr;
+}
+
+// floor(log2 |x|) bounds from the raw bits: |x| < 2^(e + 1) with e the
+// returned value (denormals and zero give the smallest normal exponent - 1).
+__device__ __forceinline__ int fix_exp_bits(float x) { return (int)((__float_as_uint(x) >> 23) & 0xff) - 127; }
+__device__ __forceinline__ int fix_exp_bits(double x)
+{
+    return (int)(((unsigned)(__double_as_longlong(x) >> 32) >> 20) & 0x7ff) - 1023;
+}
+
+__device__ __forceinline__ void fixsum_pin(double& v) { asm volatile("" : "+v"(v)); }
+
+// FP64 rounding mode (MODE register, FP_ROUND bits 3:2): toward -infinity, and
+// back to the default nearest-even.  The FP32 rounding bits are left alone.
+// Written as inline assembly on purpose: the compiler's mode-register pass
+// treats a mode it knows to be non-default as something to undo, and inserts
+// a switch back to nearest-even in front of instructions such as v_mul_f64,
+// which would silently end the region.  The switch is ordered against the
+// accumulators by fixsum_pin() (volatile asm statements keep their order); the
+// s_nop gives the new mode time to reach the vector pipeline.
+__device__ __forceinline__ void fixsum_round_down() { asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2\n\ts_nop 3"); }
+__device__ __forceinline__ void fixsum_round_nearest() { asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0\n\ts_nop 3"); }
+
+// floor(t / q) * q added to an accumulator that holds a multiple of q (used
+// in the default rounding mode; the multiplication by 2^-e is exact).
+__device__ __forceinline__ double fixsum_floor(const FixGrid& gr, double t) { return floor(t * gr.inv_q) * gr.q; }
+
 // Host side: kernel launches that can carry timing events.  The library's
 // timer may leave a (start, stop) pair here for the next launch made through
 // launch() on this host thread; the pair then records that kernel's own start

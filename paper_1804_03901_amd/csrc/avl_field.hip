@@ -182,18 +182,35 @@ __device__ __forceinline__ void solve_block(const Geo& g, const double* __restri
             if (i < half_n) twv[q] = tw[i];
         }
     }
+    // The k = 0 mode is dropped (E_hat_0 = 0), so the mean of rho cannot
+    // change E; it is subtracted before the transform so that a large mean
+    // (the neutralised charge) does not leak into the other modes through the
+    // rounding of the butterflies.  The mean is a fixed-order block sum.
+    __shared__ double s_sum[kFT / kWave];
+    double part = 0.0;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int i = tid + q * kFT;
         if (i < nx) {
-            double r = rv[q];
             if (!rho_in) {
-                r *= g.q_vol;
-                rho[i] = r;
+                rv[q] *= g.q_vol;
+                rho[i] = rv[q];
             }
-            z[i] = make_double2(r, 0.0);
+            part += rv[q];
             if (i < half_n) stw[i] = twv[q];
         }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, kWave);
+    if ((tid & (kWave - 1)) == 0) s_sum[tid / kWave] = part;
+    __syncthreads();
+    double total = 0.0;
+    for (int w = 0; w < kFT / kWave; ++w) total += s_sum[w];
+    const double mean = total / nx;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int i = tid + q * kFT;
+        if (i < nx) z[i] = make_double2(rv[q] - mean, 0.0);
     }
     __syncthreads();
     // rho_hat_m = sum_i rho_i exp(-2 pi i m i / nx)

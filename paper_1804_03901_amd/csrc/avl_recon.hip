@@ -20,8 +20,10 @@
 //   ((up01(i, j-1) + up11(i-1, j-1)) + S00(i, j)) + S10(i-1, j)
 // in both walk directions, where the (i-1) terms come from the neighbouring
 // lane by a shuffle and the terms of the previous dual row of the walk are
-// carried in registers.  Every sum has a fixed order given the sorted input:
-// no float atomics anywhere.
+// carried in registers.  A run's own sums do not depend on the order of its
+// markers (FixGrid in avl_device.h), and everything above them is added in a
+// fixed order, so the grid is a function of the marker multiset alone: no
+// float atomics anywhere.
 //
 // rho: each lane also sums f over the rows of its chunk for its column and
 // writes one partial per (chunk, column); the field kernel adds the chunk
@@ -44,54 +46,80 @@ template <typename T> struct Kahan {
     __device__ T value() const { return s - c; }
 };
 
-// Plain FP64 accumulator with the same interface.
-struct Plain {
-    double s;
-    __device__ void zero() { s = 0.0; }
-    __device__ void add(double x) { s = s + x; }
-    __device__ double value() const { return s; }
-};
-
 // Per-run moments of the marker offsets: with them the four cloud-in-cell
 // corner sums of a run are
 //   N11 = S_abf, N10 = S_af - S_abf, N01 = S_bf - S_abf, N00 = S_f - S_af - S_bf + S_abf
 //   D11 = S_ab,  D10 = S_a - S_ab,   D01 = S_b - S_ab,   D00 = n - S_a - S_b + S_ab
 // (expanding (1-a)(1-b) etc.), so a marker costs four products and seven
 // accumulations instead of eight weighted sums.  The accumulators are FP64
-// (A = Plain) or compensated FP32 (A = Kahan<float>).
-template <typename A> struct Moments {
-    A f, af, bf, abf, a, b, ab;
-    __device__ void zero() { f.zero(); af.zero(); bf.zero(); abf.zero(); a.zero(); b.zero(); ab.zero(); }
-    template <typename T> __device__ void add(T a_, T b_, T f_) {
-        const T af_ = a_ * f_, bf_ = b_ * f_, ab_ = a_ * b_, abf_ = ab_ * f_;
-        f.add(f_); af.add(af_); bf.add(bf_); abf.add(abf_);
-        a.add(a_); b.add(b_); ab.add(ab_);
-    }
-};
-// FP64 accumulators: the product-sums as fused multiply-adds (one rounding
-// per term instead of two, and eleven FP64 operations a marker instead of
-// fourteen).
-template <> struct Moments<Plain> {
+// and order-independent (FixGrid in avl_device.h): S_f, S_af, S_bf and S_abf
+// on a grid fitted to the run's largest |f|, S_a, S_b and S_ab on the grid of
+// a run whose largest f is 1 (their terms lie in [0, 1)).
+struct FixMoments {
     double f, af, bf, abf, a, b, ab;
-    __device__ void zero() { f = af = bf = abf = a = b = ab = 0.0; }
-    __device__ void add(double a_, double b_, double f_) {
+    double Cf, Cd;
+    __device__ void init(const FixGrid& gf, const FixGrid& gd) {
+        Cf = gf.C;
+        Cd = gd.C;
+        f = af = bf = abf = Cf;
+        a = b = ab = Cd;
+    }
+    // FP64 rounding toward -infinity: each operation adds floor(term / q) q
+    __device__ void add_rd(double a_, double b_, double f_) {
         const double ab_ = a_ * b_;
         f += f_;
         a += a_;
         b += b_;
-        af = __fma_rn(a_, f_, af);
-        bf = __fma_rn(b_, f_, bf);
-        ab = __fma_rn(a_, b_, ab);
-        abf = __fma_rn(ab_, f_, abf);
+        af = fma(a_, f_, af);
+        bf = fma(b_, f_, bf);
+        ab = fma(a_, b_, ab);
+        abf = fma(ab_, f_, abf);
+    }
+    // default rounding: each term is rounded down onto its grid explicitly
+    __device__ void add_floor(const FixGrid& gf, const FixGrid& gd, double a_, double b_, double f_) {
+        const double ab_ = a_ * b_;
+        f += fixsum_floor(gf, f_);
+        a += fixsum_floor(gd, a_);
+        b += fixsum_floor(gd, b_);
+        af += fixsum_floor(gf, a_ * f_);
+        bf += fixsum_floor(gf, b_ * f_);
+        ab += fixsum_floor(gd, ab_);
+        abf += fixsum_floor(gf, ab_ * f_);
+    }
+    __device__ void pin() {
+        fixsum_pin(f); fixsum_pin(af); fixsum_pin(bf); fixsum_pin(abf);
+        fixsum_pin(a); fixsum_pin(b); fixsum_pin(ab);
+    }
+};
+
+// Compensated FP32 corner sums (the AVL_OPT_KAHAN32 form): the four corner
+// weights (1-a)(1-b), a(1-b), (1-a)b, ab are formed per marker and N and D of
+// each corner are summed directly.  Every term is non-negative for f >= 0, so
+// no corner is a difference of larger sums: a corner whose weights are all
+// small keeps its own relative accuracy.
+struct CornerKahan32 {
+    Kahan<float> n00, n10, n01, n11, d00, d10, d01, d11;
+    __device__ void zero() {
+        n00.zero(); n10.zero(); n01.zero(); n11.zero();
+        d00.zero(); d10.zero(); d01.zero(); d11.zero();
+    }
+    __device__ void add(float a_, float b_, float f_) {
+        const float oa = 1.0f - a_, ob = 1.0f - b_;
+        const float w00 = oa * ob, w10 = a_ * ob, w01 = oa * b_, w11 = a_ * b_;
+        n00.add(w00 * f_); n10.add(w10 * f_); n01.add(w01 * f_); n11.add(w11 * f_);
+        d00.add(w00); d10.add(w10); d01.add(w01); d11.add(w11);
     }
 };
 
 struct Corners {
     double n00, n10, n01, n11, d00, d10, d01, d11;
-    template <typename A> __device__ void from(const Moments<A>& M, int len) {
-        set(M.f.value(), M.af.value(), M.bf.value(), M.abf.value(), M.a.value(), M.b.value(), M.ab.value(), len);
+    __device__ void from(const FixMoments& M, int len) {
+        set(M.f - M.Cf, M.af - M.Cf, M.bf - M.Cf, M.abf - M.Cf, M.a - M.Cd, M.b - M.Cd, M.ab - M.Cd, len);
     }
-    __device__ void from(const Moments<Plain>& M, int len) { set(M.f, M.af, M.bf, M.abf, M.a, M.b, M.ab, len); }
+    __device__ void from(const CornerKahan32& K) {
+        n00 = K.n00.value(); n10 = K.n10.value(); n01 = K.n01.value(); n11 = K.n11.value();
+        d00 = K.d00.value(); d10 = K.d10.value(); d01 = K.d01.value(); d11 = K.d11.value();
+    }
     __device__ void set(double Sf, double Saf, double Sbf, double Sabf, double Sa, double Sb, double Sab, int len) {
         n11 = Sabf;
         n10 = Saf - Sabf;
@@ -360,7 +388,6 @@ __device__ __forceinline__ void recon_task(const Geo& g, const typename RT<PREC>
                                            int task)
 {
     using T = typename RT<PREC>::T;
-    using A = typename std::conditional<KAHAN, Kahan<float>, Plain>::type;
     using Raw = typename Src<PREC>::Raw;
     using Vec = typename Src<PREC>::Vec;
     constexpr int V = Src<PREC>::V;
@@ -451,29 +478,64 @@ __device__ __forceinline__ void recon_task(const Geo& g, const typename RT<PREC>
         sg[DEPTH] = make_seg(rb[DEPTH], re[DEPTH], first_lane, last_lane, wrapped);
         prefetch<PREC, SPARSE>(m, sg[DEPTH], lane, R, W);
 
-        // Two separate loops: a single loop with a per-iteration choice makes
-        // the compiler fall back to generic (flat) loads, whose waits would also
-        // stall on the prefetch of the next rows.
-        Moments<A> M;
-        M.zero();
-        if (staged) {
-            for (int u = 0; u < len; ++u) {
-                T a, b, f;
-                lds.get(p0 + u, a, b, f);
-                if constexpr (KAHAN) M.add(a, b, f);
-                else M.add((double)a, (double)b, (double)f);
+        // Separate loops for staged and global rows: a single loop with a
+        // per-iteration choice makes the compiler fall back to generic (flat)
+        // loads, whose waits would also stall on the prefetch of the next rows.
+        Corners c;
+        if constexpr (KAHAN) {
+            CornerKahan32 K;
+            K.zero();
+            if (staged) {
+                for (int u = 0; u < len; ++u) {
+                    T a, b, f;
+                    lds.get(p0 + u, a, b, f);
+                    K.add(a, b, f);
+                }
+            } else {
+                for (int u = 0; u < len; ++u) {
+                    T a, b, f;
+                    load_global<PREC>(g, m, p0 + u, a, b, f);
+                    K.add(a, b, f);
+                }
             }
+            c.from(K);
         } else {
-            for (int u = 0; u < len; ++u) {
-                T a, b, f;
-                load_global<PREC>(g, m, p0 + u, a, b, f);
-                if constexpr (KAHAN) M.add(a, b, f);
-                else M.add((double)a, (double)b, (double)f);
+            // the run's grids from order-free bounds: its largest |f| and its
+            // length.  The offset sums take the grid of terms below 2^1 (the
+            // largest weight, 1, taken as f = 1): for f = c = 2^k on every
+            // marker the f grid is then c times the offset grid, every N sum is
+            // c times its D sum, and f = c comes out exactly
+            int emax = -1100;
+            if (staged) {
+                for (int u = 0; u < len; ++u) emax = max(emax, fix_exp_bits(lds.f[p0 + u]));
+            } else {
+                for (int u = 0; u < len; ++u) emax = max(emax, fix_exp_bits(m.f[p0 + u]));
             }
+            const FixGrid gf = fix_grid(emax, len), gd = fix_grid(0, len);
+            FixMoments M;
+            M.init(gf, gd);
+            if (staged) {
+                fixsum_round_down();
+                M.pin();
+                for (int u = 0; u < len; ++u) {
+                    T a, b, f;
+                    lds.get(p0 + u, a, b, f);
+                    M.add_rd((double)a, (double)b, (double)f);
+                }
+                M.pin();
+                fixsum_round_nearest();
+                M.pin();
+            } else {
+                // the FP64 form locates each marker here, in the default rounding
+                for (int u = 0; u < len; ++u) {
+                    T a, b, f;
+                    load_global<PREC>(g, m, p0 + u, a, b, f);
+                    M.add_floor(gf, gd, (double)a, (double)b, (double)f);
+                }
+            }
+            c.from(M, len);
         }
         wave_sync_lds();
-        Corners c;
-        c.from(M, len);
 
         // corner partials of the left neighbour run (lane - 1)
         const double n10l = from_left(c.n10);

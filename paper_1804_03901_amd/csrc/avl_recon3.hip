@@ -18,7 +18,9 @@
 // per run sums eight moments of (a, bx)
 // weighted by f w and by w (product-sums as fused multiply-adds).  The
 // corners of the runs go to the target rows jd (lower) and jd + 1 (upper, kept
-// until the next dual row).  Sums are FP64 and in a fixed order: no atomics.
+// until the next dual row).  Sums are FP64: a run's sums are independent of
+// the order of its markers (FixGrid in avl_device.h) and everything above
+// them is added in a fixed order, with no atomics.
 //
 // A dual plane is still read by up to four blocks, 2.25 times on average
 // instead of four times with one target plane per wave; tasks are dealt so
@@ -244,30 +246,74 @@ void k_recon_3v(Geo g, typename R3<PREC>::M m, const int* __restrict__ offsets, 
             }
             if (t == tlast) prefetch(nxt);
             wave_sync_lds3();
-            // moments of (a, b) weighted by w and by f w
-            double Sw = 0, Saw = 0, Sbw = 0, Sabw = 0, Sf = 0, Saf = 0, Sbf = 0, Sabf = 0;
-            auto acc = [&](const St3& e) {
-                const double ab = e.a * e.b;
-                Sw += e.w;
-                Saw = __fma_rn(e.a, e.w, Saw);
-                Sbw = __fma_rn(e.b, e.w, Sbw);
-                Sabw = __fma_rn(ab, e.w, Sabw);
-                Sf += e.fw;
-                Saf = __fma_rn(e.a, e.fw, Saf);
-                Sbf = __fma_rn(e.b, e.fw, Sbf);
-                Sabf = __fma_rn(ab, e.fw, Sabf);
-            };
+            // moments of (a, b) weighted by w and by f w, order-independent
+            // (FixGrid in avl_device.h): the w sums on a grid fitted to the
+            // run's largest w, the f w sums on one fitted to its largest |f w|.
+            // For f = c = 2^k on every marker every f w is c w exactly, the two
+            // grids differ by exactly c, and f = c comes out exactly
+            int ew = -1100, ef = -1100;
             if (staged) {
-#pragma unroll 2
-                for (int k = 0; k < len; ++k) acc(st[p0 + k]);
+                for (int k = 0; k < len; ++k) {
+                    const St3 e = st[p0 + k];
+                    ew = max(ew, fix_exp_bits(e.w));
+                    ef = max(ef, fix_exp_bits(e.fw));
+                }
             } else {
                 for (int k = 0; k < len; ++k) {
                     Raw3<PREC> rr;
                     rr.load(m, g, p0 + k);
-                    acc(rr.stage(g, ws));
+                    const St3 e = rr.stage(g, ws);
+                    ew = max(ew, fix_exp_bits(e.w));
+                    ef = max(ef, fix_exp_bits(e.fw));
+                }
+            }
+            const FixGrid gf = fix_grid(ef, len), gd = fix_grid(ew, len);
+            double Sw = gd.C, Saw = gd.C, Sbw = gd.C, Sabw = gd.C;
+            double Sf = gf.C, Saf = gf.C, Sbf = gf.C, Sabf = gf.C;
+            auto pin8 = [&]() {
+                fixsum_pin(Sw); fixsum_pin(Saw); fixsum_pin(Sbw); fixsum_pin(Sabw);
+                fixsum_pin(Sf); fixsum_pin(Saf); fixsum_pin(Sbf); fixsum_pin(Sabf);
+            };
+            if (staged) {
+                // FP64 rounding toward -infinity: each operation adds floor(term / q) q
+                fixsum_round_down();
+                pin8();
+#pragma unroll 2
+                for (int k = 0; k < len; ++k) {
+                    const St3 e = st[p0 + k];
+                    const double ab = e.a * e.b;
+                    Sw += e.w;
+                    Saw = fma(e.a, e.w, Saw);
+                    Sbw = fma(e.b, e.w, Sbw);
+                    Sabw = fma(ab, e.w, Sabw);
+                    Sf += e.fw;
+                    Saf = fma(e.a, e.fw, Saf);
+                    Sbf = fma(e.b, e.fw, Sbf);
+                    Sabf = fma(ab, e.fw, Sabf);
+                }
+                pin8();
+                fixsum_round_nearest();
+                pin8();
+            } else {
+                // the FP64 form locates each marker here, in the default rounding
+                for (int k = 0; k < len; ++k) {
+                    Raw3<PREC> rr;
+                    rr.load(m, g, p0 + k);
+                    const St3 e = rr.stage(g, ws);
+                    const double ab = e.a * e.b;
+                    Sw += fixsum_floor(gd, e.w);
+                    Saw += fixsum_floor(gd, e.a * e.w);
+                    Sbw += fixsum_floor(gd, e.b * e.w);
+                    Sabw += fixsum_floor(gd, ab * e.w);
+                    Sf += fixsum_floor(gf, e.fw);
+                    Saf += fixsum_floor(gf, e.a * e.fw);
+                    Sbf += fixsum_floor(gf, e.b * e.fw);
+                    Sabf += fixsum_floor(gf, ab * e.fw);
                 }
             }
             wave_sync_lds3();
+            Sw -= gd.C; Saw -= gd.C; Sbw -= gd.C; Sabw -= gd.C;
+            Sf -= gf.C; Saf -= gf.C; Sbf -= gf.C; Sabf -= gf.C;
             const double n11 = Sabf, n10 = Saf - Sabf, n01 = Sbf - Sabf, n00 = (Sf - Saf) - n01;
             const double d11 = Sabw, d10 = Saw - Sabw, d01 = Sbw - Sabw, d00 = (Sw - Saw) - d01;
             cN[t] += n00 + from_left3(n10);

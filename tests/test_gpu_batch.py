@@ -1,31 +1,20 @@
 """GPU parity of the batched path: independent 1D-1V instances of uneven size
 stepped by batched launches, each instance compared with the FP64 oracle
-(1e-12 per step for the FP64 path, 1e-5 on f for the FP32 form) and with the
-same instance stepped alone (agreement to rounding: within-run marker order
-follows integer atomics)."""
-import math
-
+(1e-12 per step for the FP64 path, 1e-5 on f for the FP32 form; f also cell
+by cell, the field at its own scale, ``checks``) and with the same instance
+stepped alone (agreement to rounding: the batch and a single handle may split
+the reconstruction's velocity rows into different chunks, which changes the
+order in which the charge density's chunk partials are added)."""
 import numpy as np
 import pytest
 
 torch = pytest.importorskip("torch")
 
 import oracle
+from checks import cell_rel, check_field, nrel
 from paper_1804_03901_amd import avl, inputs
 
 pytestmark = pytest.mark.gpu
-
-
-def nrel(a, b):
-    a = np.asarray(a, dtype=np.float64).ravel()
-    b = np.asarray(b, dtype=np.float64).ravel()
-    s = np.max(np.abs(b))
-    return float(np.max(np.abs(a - b)) / s) if s > 0 else float(np.max(np.abs(a - b)))
-
-
-def e_err(E_g, E_o, rho_o, w):
-    scale = w.c_p * np.max(np.abs(rho_o)) * w.L / (2 * math.pi)
-    return float(np.max(np.abs(np.asarray(E_g) - np.asarray(E_o))) / scale)
 
 
 def t2n(t):
@@ -79,11 +68,10 @@ def test_batch_step_matches_oracle_per_instance(precision):
             assert float(fg.abs().max()) == 0.0 and float(E_g.abs().max()) == 0.0
             continue
         assert nrel(t2n(fg), fo) <= tol_f, w.name
+        assert cell_rel(t2n(fg), fo, Do) <= (1e-10 if precision == avl.AVL_FP64 else tol_f), w.name
         assert nrel(t2n(Dg), Do) <= tol_r, w.name
         assert nrel(t2n(rho_g), rho_o) <= tol_r, w.name
-        assert e_err(t2n(E_g), E_o, rho_o, w) <= tol_r, w.name
-        Eg = t2n(E_g)
-        assert abs(d[i, 0, 0] - oracle.field_energy(w.nx, w.L, w.c_p, Eg)) <= 1e-13 * d[i, 0, 0] + 1e-300
+        check_field(w, t2n(rho_g), t2n(E_g), rho_o, E_o, W_g=d[i, 0, 0], label=w.name)
 
 
 def test_batch_agrees_with_single_instances():
@@ -96,8 +84,11 @@ def test_batch_agrees_with_single_instances():
         sim = avl.Simulation(w, x, v.reshape(-1), f, precision=avl.AVL_FP32)
         ds = t2n(sim.step(6, graph=True))
         E_s, rho_s = sim.field()
-        E_b, _ = b.instance(i).field()
-        assert e_err(t2n(E_b), t2n(E_s), t2n(rho_s), w) <= 1e-9, w.name
+        E_b, rho_b = b.instance(i).field()
+        # the charge densities agree to the rounding of their chunk sums; the
+        # fields then within the Poisson gain times that difference
+        assert nrel(t2n(rho_b), t2n(rho_s)) <= 1e-12, w.name
+        check_field(w, t2n(rho_b), t2n(E_b), t2n(rho_s), t2n(E_s), label=w.name)
         assert np.allclose(db[i], ds, rtol=1e-6, atol=1e-300), w.name
         sim.close()
 
