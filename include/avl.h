@@ -17,8 +17,9 @@
  * ---------------------------------------
  *  - Every array argument is DEVICE memory owned by the caller unless its name
  *    ends in _host.  libavl never allocates or frees device memory; all of its
- *    device state lives in the caller's workspace.  The handle itself is a
- *    small host object owned by libavl and released by avl_destroy.
+ *    device state lives in the caller's workspace (avl_reconstruct_noalloc
+ *    alone uses a static device array of the library instead).  The handle
+ *    itself is a small host object owned by libavl and released by avl_destroy.
  *  - Work is enqueued on the handle's HIP stream (hipStream_t passed as void*,
  *    NULL = legacy default stream) and is asynchronous unless stated; results
  *    are valid after the stream is synchronised.  Calls on one handle are not
@@ -78,10 +79,15 @@ typedef enum { AVL_FP64 = 0, AVL_FP32 = 1 } avl_precision;
 /* Options.  The reconstruction sums, per run of markers sharing a cell, the
  * moments S_f, S_af, S_bf, S_abf, S_a, S_b, S_ab of the offsets (from which
  * the four cloud-in-cell corner sums follow exactly); by default these
- * accumulate in FP64 in both forms.
- *  AVL_OPT_KAHAN32: FP32 form of 1D-1V only: accumulate them in FP32 with
- *                   compensated (Kahan) summation instead (AVL_ENOTSUP for
- *                   1D-3V, whose reconstruction always sums in FP64). */
+ * accumulate in FP64 in both forms, each term rounded down onto a grid fitted
+ * to the run, so that the sums do not depend on the order of the run's markers
+ * and every result is reproducible bit for bit.
+ *  AVL_OPT_KAHAN32: FP32 form of 1D-1V only: accumulate the four corner sums
+ *                   of N and D directly in FP32 with compensated (Kahan)
+ *                   summation instead (reproducible to rounding, not bit for
+ *                   bit: the order of a run's markers varies from run to run;
+ *                   AVL_ENOTSUP for 1D-3V, whose reconstruction always sums in
+ *                   FP64). */
 typedef enum { AVL_OPT_KAHAN32 = 1 } avl_option;
 
 typedef struct avl_config {
@@ -346,6 +352,42 @@ size_t avl_adjoint_workspace_bytes(const avl_config* cfg, int32_t nsteps, int32_
  * AVL_ENOTSUP for 1D-3V; AVL_ESTATE while kernel timing is enabled. */
 int avl_adjoint(avl_handle* h, const double* x, const double* v, const double* f, int32_t nsteps, int32_t every,
                 void* rec, size_t rec_bytes, double* J_out, double* grad_f);
+
+/* ---------------------------------------------------------------------------
+ * For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the
+ * reconstruction of avl_reconstruct for a marker set given directly (loaded
+ * and sorted as avl_init does it), with no handle and no workspace.
+ * ------------------------------------------------------------------------- */
+
+/* Size of the library's static scratch array per GPU (64 MiB): it holds the
+ * two marker buffers, the per-cell counts and offsets, the sort's tile totals
+ * and the reconstruction's charge partials of one call. */
+#define AVL_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* Markers x, v, f (FP64, SoA as for avl_init; x in [0, L), all finite) are
+ * converted to cfg's storage form, sorted by cell and reconstructed:
+ * f_out (required) and D_out (may be NULL) receive G = nx*prod(nv) values in
+ * the storage precision (double for AVL_FP64, float for AVL_FP32), equal bit
+ * for bit to what avl_init followed by avl_reconstruct gives for the same
+ * markers and configuration.  Every step is a kernel launched on `stream`
+ * (a hipStream_t); the call allocates nothing (no hipMalloc, no host
+ * allocation), copies nothing from the host and does not synchronise, so it
+ * may be captured into a HIP graph.  The inputs are not validated on the
+ * device (avl_init's checks need a synchronisation): values outside the rules
+ * above give meaningless output, never out-of-bounds accesses.
+ * All scratch lives in one static device array per GPU, kept until the
+ * process ends: every call on a GPU shares it, so calls that overlap on one
+ * GPU (two streams, two host threads, or a graph replayed while another call
+ * runs) race and must be serialised by the caller.  The first call on each
+ * device looks up the array's device address (not a stream operation).
+ * Errors: avl_init's configuration errors; AVL_EINVAL for a NULL f_out or a
+ * missing marker array; AVL_EALIGN for arrays not 8-byte aligned; AVL_ESIZE
+ * when the configuration needs more than AVL_NOALLOC_SCRATCH_BYTES (about
+ * 1.3 million FP64 1D-1V markers); AVL_EDEVICE if a launch or the lookup
+ * fails. */
+int avl_reconstruct_noalloc(const avl_config* cfg, void* stream, const double* x, const double* v,
+                            const double* f, void* f_out, void* D_out);
 
 #if defined(__GNUC__)
 #pragma GCC visibility pop

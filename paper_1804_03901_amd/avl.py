@@ -58,7 +58,10 @@ EXPORTS = ["avl_workspace_bytes", "avl_init", "avl_push", "avl_sort", "avl_recon
            "avl_copy_probe", "avl_strerror", "avl_destroy", "avl_batch_workspace_bytes", "avl_batch_init",
            "avl_batch_step", "avl_batch_instance", "avl_batch_count", "avl_batch_check", "avl_batch_destroy",
            "avl_adjoint_workspace_bytes", "avl_adjoint", "avl_diagnostics", "avl_multi_workspace_bytes",
-           "avl_multi_init", "avl_multi_step", "avl_multi_destroy"]
+           "avl_multi_init", "avl_multi_step", "avl_multi_destroy", "avl_reconstruct_noalloc"]
+
+# size of the static scratch array avl_reconstruct_noalloc uses per GPU
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 # avl_diagnostics output slots
 DIAG_NAMES = ("Ee", "Ekin", "Etot", "N", "S", "P")
@@ -117,6 +120,7 @@ def load(path: str = LIB_PATH):
     lib.avl_adjoint_workspace_bytes.argtypes = [P(AvlConfig), c.c_int32, c.c_int32]
     lib.avl_adjoint_workspace_bytes.restype = c.c_size_t
     lib.avl_adjoint.argtypes = [vp, vp, vp, vp, c.c_int32, c.c_int32, vp, c.c_size_t, vp, vp]
+    lib.avl_reconstruct_noalloc.argtypes = [P(AvlConfig), vp, vp, vp, vp, vp, vp]
     for name in EXPORTS:
         if name not in ("avl_workspace_bytes", "avl_step_count", "avl_kernel_bytes", "avl_strerror",
                         "avl_batch_workspace_bytes", "avl_batch_instance", "avl_adjoint_workspace_bytes",
@@ -196,6 +200,11 @@ def avl_sort(h):
 
 def avl_reconstruct(h, f_out=None, D_out=None):
     return _ck(load().avl_reconstruct(h, _ptr(f_out), _ptr(D_out)), "avl_reconstruct")
+
+
+def avl_reconstruct_noalloc(cfg: AvlConfig, stream, x, v, f, f_out, D_out=None):
+    return _ck(load().avl_reconstruct_noalloc(ctypes.byref(cfg), _stream_ptr(stream), _ptr(x), _ptr(v), _ptr(f),
+                                              _ptr(f_out), _ptr(D_out)), "avl_reconstruct_noalloc")
 
 
 def avl_moments(h, rho_out=None):

@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1642,3 +1643,151 @@ int avl_multi_destroy(avl_multi* m)
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Reconstruction without allocation (avl_reconstruct_noalloc).
+//
+// Callers that cannot allocate device memory (code under HIP graph capture,
+// serving loops, harnesses that forbid it) get the load, sort and
+// reconstruction of avl_init + avl_reconstruct with every scratch buffer in
+// one file-scope device array.  In host code `scratch` only names the array:
+// its device address comes from hipGetSymbolAddress, looked up once per
+// device with that device current, and only that address is ever handed to
+// kernels.  Every call on a GPU shares the array.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[AVL_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call there); null on failure.
+void* scratch_address()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+__global__ void k_fill_int(int* __restrict__ p, int n, int value)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = value;
+}
+
+__global__ void k_copy_f64(const double* __restrict__ src, double* __restrict__ dst, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
+hipError_t fill_int(int* p, size_t n, int value, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_int, dim3(blocks), dim3(256), 0, st, p, (int)n, value);
+    return hipGetLastError();
+}
+
+hipError_t copy_f64(const double* src, double* dst, size_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    const int blocks = (int)std::min<size_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_copy_f64, dim3(blocks), dim3(256), 0, st, src, dst, (int)n);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" int avl_reconstruct_noalloc(const avl_config* cfg, void* stream, const double* x, const double* v,
+                                       const double* f, void* f_out, void* D_out)
+{
+    Geo g;
+    int rc = make_geo(cfg, &g);
+    if (rc) return rc;
+    if (!f_out) return AVL_EINVAL;
+    if (g.n > 0 && (!x || !v || !f)) return AVL_EINVAL;
+    if (((uintptr_t)x | (uintptr_t)v | (uintptr_t)f) & 7) return AVL_EALIGN;
+    if (((uintptr_t)f_out | (uintptr_t)D_out) & 7) return AVL_EALIGN;
+    // the slice of the handle layout this call needs: two marker buffers,
+    // counts, offsets, per-scan-tile totals, the rho partials and the flags
+    const size_t np = (size_t)g.np;
+    const size_t mbytes = (g.prec == AVL_FP64 ? sizeof(double) * np * (2 + g.vdim) : 4 * np * (3 + g.vdim)) +
+                          64 * (3 + g.vdim);
+    const size_t nbt = (size_t)g.nb + 1;
+    const size_t ntiles = (nbt + kScanTile - 1) / kScanTile;
+    const size_t tstride = ntiles + 64;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+    const size_t o_m0 = take(mbytes), o_m1 = take(mbytes);
+    const size_t o_counts = take(sizeof(int) * nbt), o_offsets = take(sizeof(int) * (nbt + 1));
+    const size_t o_tsum = take(sizeof(int) * 2 * tstride);
+    const size_t o_rho = take(sizeof(double) * (size_t)std::max(1, g.nchunk) * g.nx);
+    const size_t o_flags = take(sizeof(int));
+    if (off > (size_t)AVL_NOALLOC_SCRATCH_BYTES) return AVL_ESIZE;
+    char* base = (char*)scratch_address();
+    if (!base) return AVL_EDEVICE;
+    const hipStream_t st = (hipStream_t)stream;
+    // launch shapes as avl_init sets them (device attributes and occupancy only)
+    {
+        int dev = 0, lds = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return AVL_EDEVICE;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess || lds <= 0)
+            if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) lds = 65536;
+        set_lds_limit(lds);
+        fit_lds(&g, lds);
+        g.sblocks = scatter_blocks_per_cu(g) * device_cus();
+        g.cblocks = count_blocks_per_cu(g) * device_cus();
+    }
+    M64 m64[2];
+    M32 m32[2];
+    for (int b = 0; b < 2; ++b) {
+        char* p = base + (b ? o_m1 : o_m0);
+        if (g.prec == AVL_FP64) {
+            double* d = reinterpret_cast<double*>(p);
+            m64[b] = M64{d, d + np, d + np * (1 + g.vdim), nullptr};
+        } else {
+            int* c = reinterpret_cast<int*>(p);
+            m32[b] = M32{c, reinterpret_cast<float*>(c + np), reinterpret_cast<float*>(c + 2 * np),
+                         reinterpret_cast<float*>(c + np * (2 + g.vdim)), nullptr};
+        }
+    }
+    int* counts = (int*)(base + o_counts);
+    int* offsets = (int*)(base + o_offsets);
+    int* tsum = (int*)(base + o_tsum);
+    double* rho_part = (double*)(base + o_rho);
+    int* flags = (int*)(base + o_flags);
+    // the array keeps the previous call's contents: clear what the passes
+    // accumulate into (counts, both halves of the tile totals, flags) and set
+    // the end offset, all with kernels (no memset or host copy)
+    AVL_TRY(fill_int(counts, nbt, 0, st));
+    AVL_TRY(fill_int(tsum, 2 * tstride, 0, st));
+    AVL_TRY(fill_int(flags, 1, 0, st));
+    AVL_TRY(fill_int(offsets + nbt, 1, g.n, st));
+    const size_t n = (size_t)g.n;
+    if (g.prec == AVL_FP64) {
+        AVL_TRY(copy_f64(x, m64[0].x, n, st));
+        for (int d = 0; d < g.vdim; ++d) AVL_TRY(copy_f64(v + (size_t)d * n, m64[0].v + (size_t)d * np, n, st));
+        AVL_TRY(copy_f64(f, m64[0].f, n, st));
+    } else {
+        AVL_TRY(launch_to32(g, x, v, f, m32[0], flags, st));
+    }
+    void* src = g.prec == AVL_FP64 ? (void*)&m64[0] : (void*)&m32[0];
+    void* dst = g.prec == AVL_FP64 ? (void*)&m64[1] : (void*)&m32[1];
+    for (int phase = 0; phase < 3; ++phase)
+        AVL_TRY(launch_sort(g, src, dst, nullptr, nullptr, g.dt, g.bscale, counts, offsets, tsum, tsum + tstride,
+                            flags, false, st, phase));
+    if (g.vdim == 1) AVL_TRY(launch_recon(g, dst, offsets, f_out, D_out, rho_part, st));
+    else AVL_TRY(launch_recon3(g, dst, offsets, f_out, D_out, rho_part, nullptr, st));
+    return AVL_OK;
+}
