@@ -17,7 +17,8 @@
 namespace avl {
 hipError_t launch_sort(const Geo& g, void* src, void* dst, const double* E, const RowShift* rows, double dtk,
                        float bk, int* counts, int* offsets, int* tile_sums, int* tile_next, int* flags, bool push,
-                       hipStream_t st, int phase);
+                       hipStream_t st, int phase, const int* off_old, const int* tf_old, int* tf_new);
+hipError_t launch_cells(const Geo& g, const int* offsets, int* cell, hipStream_t st);
 hipError_t launch_push(const Geo& g, void* m, const double* E, const RowShift* rows, double dtk, float bk,
                        int* flags, hipStream_t st);
 hipError_t launch_recon(const Geo& g, void* m, const int* offsets, void* fgrid, void* Dgrid, double* rho_part,
@@ -72,7 +73,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
-    size_t markers[2], counts, offsets, tile_sums, fgrid, rho_part, rho_slices, rho, E, tw, green, rows, diag, ctr, flags, bad,
+    size_t markers[2], counts, offsets[2], tfirst[2], tile_sums, fgrid, rho_part, rho_slices, rho, E, tw, green, rows, diag, ctr, flags, bad,
         scratch3, diag_part, total;
 };
 
@@ -221,7 +222,11 @@ void make_layout(const avl_config* c, const Geo& g, Layout* L)
     L->markers[0] = take(mbytes + 64 * (3 + g.vdim));
     L->markers[1] = take(mbytes + 64 * (3 + g.vdim));
     L->counts = take(sizeof(int) * nbt);
-    L->offsets = take(sizeof(int) * (nbt + 1));
+    // run offsets and tile-start buckets of each marker buffer's order
+    L->offsets[0] = take(sizeof(int) * (nbt + 1));
+    L->offsets[1] = take(sizeof(int) * (nbt + 1));
+    L->tfirst[0] = take(sizeof(int) * (n / 2048 + 2));
+    L->tfirst[1] = take(sizeof(int) * (n / 2048 + 2));
     L->tile_sums = take(sizeof(int) * 2 * (ntiles + 64));   // two parities of per-tile totals
     L->fgrid = take(esz * cells);
     L->rho_part = take(sizeof(double) * (size_t)std::max(1, g.nchunk) * g.nx);
@@ -263,6 +268,8 @@ struct avl_handle {
     M32 m32[2];
     int cur;
     int *counts, *offsets, *tile_sums, *flags, *bad;
+    int *offs[2], *tfirst[2];   // run offsets / tile-start buckets of each marker buffer's order; offsets = offs[cur]
+    bool cells_ok;      // FP32 1D-1V: every stored cell index is current (else implied by offs[cur])
     void* fgrid;
     double *rho_part, *rho_slices, *rho, *E, *green, *diag;
     double2* tw;
@@ -426,6 +433,19 @@ int upload_tables(avl_handle* h)
     return AVL_OK;
 }
 
+bool implied_cells(const avl_handle* h) { return h->g.prec == AVL_FP32 && h->g.vdim == 1; }
+
+// FP32 1D-1V: write the cell index of every marker of a sorted order (the
+// sort stores it only for the overflow bucket), before anything that reads
+// the cells outside a sort (export, an order-preserving push, a raw copy).
+int ensure_cells(avl_handle* h)
+{
+    if (!implied_cells(h) || h->cells_ok) return AVL_OK;
+    AVL_TRY(launch_cells(h->g, h->offsets, h->m32[h->cur].cell, h->st));
+    h->cells_ok = true;
+    return AVL_OK;
+}
+
 int do_sort(avl_handle* h, bool push, double kick)
 {
     const Geo& g = h->g;
@@ -437,22 +457,30 @@ int do_sort(avl_handle* h, bool push, double kick)
     const size_t tstride = ((size_t)g.nb + 1 + kScanTile - 1) / kScanTile + 64;
     int* tcur = h->tile_sums + (size_t)h->cur * tstride;
     int* tnext = h->tile_sums + (size_t)(1 - h->cur) * tstride;
+    // FP32 1D-1V markers in a sorted order carry implied cells
+    const bool impl = implied_cells(h) && h->sorted;
+    const int* off_old = impl ? h->offs[h->cur] : nullptr;
+    const int* tf_old = impl ? h->tfirst[h->cur] : nullptr;
+    int* off_new = h->offs[1 - h->cur];
+    int* tf_new = h->tfirst[1 - h->cur];
     {
         Timer t(h, AVL_K_PUSH_COUNT, true);
-        AVL_TRY(launch_sort(g, src, dst, h->E, h->rows, dtk, bk, h->counts, h->offsets, tcur, tnext, h->flags,
-                            push, h->st, 0));
+        AVL_TRY(launch_sort(g, src, dst, h->E, h->rows, dtk, bk, h->counts, off_new, tcur, tnext, h->flags,
+                            push, h->st, 0, off_old, tf_old, tf_new));
     }
     {
         Timer t(h, AVL_K_SCAN);
-        AVL_TRY(launch_sort(g, src, dst, h->E, h->rows, dtk, bk, h->counts, h->offsets, tcur, tnext, h->flags,
-                            push, h->st, 1));
+        AVL_TRY(launch_sort(g, src, dst, h->E, h->rows, dtk, bk, h->counts, off_new, tcur, tnext, h->flags,
+                            push, h->st, 1, off_old, tf_old, tf_new));
     }
     {
         Timer t(h, AVL_K_SCATTER, true);
-        AVL_TRY(launch_sort(g, src, dst, h->E, h->rows, dtk, bk, h->counts, h->offsets, tcur, tnext, h->flags,
-                            push, h->st, 2));
+        AVL_TRY(launch_sort(g, src, dst, h->E, h->rows, dtk, bk, h->counts, off_new, tcur, tnext, h->flags,
+                            push, h->st, 2, off_old, tf_old, tf_new));
     }
     h->cur = 1 - h->cur;
+    h->offsets = h->offs[h->cur];
+    h->cells_ok = !implied_cells(h);
     h->sorted = true;
     if (push) {
         h->kicked = true;
@@ -539,7 +567,8 @@ int load_markers(avl_handle* h, const double* x, const double* v, const double* 
         const size_t ntiles = (nbt + kScanTile - 1) / kScanTile;
         AVL_TRY(hipMemsetAsync(h->tile_sums, 0, sizeof(int) * 2 * (ntiles + 64), h->st));
     }
-    AVL_TRY(hipMemcpyAsync(h->offsets + nbt, &total, sizeof(int), hipMemcpyHostToDevice, h->st));
+    AVL_TRY(hipMemcpyAsync(h->offs[0] + nbt, &total, sizeof(int), hipMemcpyHostToDevice, h->st));
+    AVL_TRY(hipMemcpyAsync(h->offs[1] + nbt, &total, sizeof(int), hipMemcpyHostToDevice, h->st));
     if (fresh) AVL_TRY(hipMemsetAsync(h->ctr, 0, sizeof(long long), h->st));
     AVL_TRY(hipStreamSynchronize(h->st));
     if (fresh) {
@@ -547,6 +576,8 @@ int load_markers(avl_handle* h, const double* x, const double* v, const double* 
         h->kicked = false;
     }
     h->sorted = false;
+    h->cells_ok = true;
+    h->offsets = h->offs[0];
     h->have_f = h->have_rho = h->have_E = h->partials = false;
     int rc;
     if ((rc = do_sort(h, false, 1.0))) return rc;
@@ -613,7 +644,12 @@ int avl_init(const avl_config* cfg, void* workspace, size_t ws_bytes, void* stre
     h->ws = (char*)workspace;
     set_views(h);
     h->counts = (int*)(h->ws + lay.counts);
-    h->offsets = (int*)(h->ws + lay.offsets);
+    for (int b = 0; b < 2; ++b) {
+        h->offs[b] = (int*)(h->ws + lay.offsets[b]);
+        h->tfirst[b] = (int*)(h->ws + lay.tfirst[b]);
+    }
+    h->offsets = h->offs[0];
+    h->cells_ok = true;
     h->tile_sums = (int*)(h->ws + lay.tile_sums);
     h->fgrid = h->ws + lay.fgrid;
     h->rho_part = (double*)(h->ws + lay.rho_part);
@@ -662,6 +698,8 @@ int avl_push(avl_handle* h, const double* E)
     if (!h) return AVL_EINVAL;
     if (!E && !h->have_E) return AVL_ESTATE;
     const double kick = kick_fraction(h);
+    int rc0 = ensure_cells(h);
+    if (rc0) return rc0;
     {
         Timer t(h, AVL_K_PUSH_COUNT);
         AVL_TRY(launch_push(h->g, marker_view(h, h->cur), E ? E : h->E, h->rows, h->g.dt * kick,
@@ -768,6 +806,7 @@ int avl_step_graph(avl_handle* h, int32_t nsteps, double* diag_out)
             h->st = user_st;
             h->cur = saved_cur;
             h->steps = saved_steps;
+            h->offsets = h->offs[h->cur];
             if (e != hipSuccess) return report(e, "hipStreamBeginCapture", __LINE__);
             if (e2 != hipSuccess) return report(e2, "hipStreamEndCapture", __LINE__);
             if (rc) return rc;
@@ -783,6 +822,8 @@ int avl_step_graph(avl_handle* h, int32_t nsteps, double* diag_out)
     for (; s < nsteps; ++s) {
         AVL_TRY(hipGraphLaunch(h->gexec[h->cur], h->st));
         h->cur = 1 - h->cur;
+        h->offsets = h->offs[h->cur];
+        h->cells_ok = !implied_cells(h);
         h->steps += 1;
         if (diag_out && ((s + 1) % kDiagCap == 0)) {
             int rc = copy_diag(h, first + s + 1 - kDiagCap, kDiagCap, diag_out + 2 * (s + 1 - kDiagCap));
@@ -816,6 +857,8 @@ int avl_get_markers(avl_handle* h, double* x, double* v, double* f)
         AVL_TRY(hipMemcpyAsync(f, m.f, sizeof(double) * n, hipMemcpyDeviceToDevice, h->st));
         return AVL_OK;
     }
+    const int rc = ensure_cells(h);
+    if (rc) return rc;
     return hip_status(launch_to64(g, h->m32[h->cur], x, v, f, h->st));
 }
 
@@ -1038,6 +1081,8 @@ void batch_advance(avl_batch* b)
 {
     for (avl_handle* h : b->h) {
         h->cur = 1 - h->cur;
+        h->offsets = h->offs[h->cur];
+        h->cells_ok = !implied_cells(h);
         h->steps += 1;
         h->sorted = h->kicked = true;
         h->have_f = h->have_rho = h->have_E = h->partials = true;
@@ -1115,7 +1160,10 @@ int avl_batch_init(const avl_config* cfgs, int32_t count, void* workspace, size_
         I.E = h->E;
         I.rows = h->rows;
         I.counts = h->counts;
-        I.offsets = h->offsets;
+        for (int p = 0; p < 2; ++p) {
+            I.offsets[p] = h->offs[p];
+            I.tfirst[p] = h->tfirst[p];
+        }
         const size_t tstride = ((size_t)g.nb + 1 + kScanTile - 1) / kScanTile + 64;
         I.tsum[0] = h->tile_sums;
         I.tsum[1] = h->tile_sums + tstride;
@@ -1326,6 +1374,14 @@ void set_ids(avl_handle* h, int b, int* p)
 int adj_checkpoint(avl_handle* h, char* C, const AdjLayout& A, bool restore)
 {
     char* mk = h->ws + h->lay.markers[h->cur];
+    if (!restore) {
+        // the copy must hold every cell index: it is reloaded as an unsorted buffer
+        const int rc = ensure_cells(h);
+        if (rc) return rc;
+    } else {
+        h->sorted = false;
+        h->cells_ok = true;
+    }
     int* id = id_of(h, h->cur);
     const size_t n = (size_t)h->g.np;
     if (restore) {
@@ -1353,6 +1409,8 @@ int adj_save(avl_handle* h, char* S, const AdjLayout& A, double* f_tmp)
         AVL_TRY(hipMemcpyAsync(S + A.st_v, m.v, 8 * n, hipMemcpyDeviceToDevice, h->st));
         AVL_TRY(hipMemcpyAsync(S + A.st_id, m.id, 4 * n, hipMemcpyDeviceToDevice, h->st));
     } else {
+        const int rc = ensure_cells(h);
+        if (rc) return rc;
         const M32& m = h->m32[h->cur];
         if (n) AVL_TRY(launch_to64(g, m, (double*)(S + A.st_x), (double*)(S + A.st_v), f_tmp, h->st));
         AVL_TRY(hipMemcpyAsync(S + A.st_id, m.id, 4 * n, hipMemcpyDeviceToDevice, h->st));
@@ -1786,7 +1844,7 @@ extern "C" int avl_reconstruct_noalloc(const avl_config* cfg, void* stream, cons
     void* dst = g.prec == AVL_FP64 ? (void*)&m64[1] : (void*)&m32[1];
     for (int phase = 0; phase < 3; ++phase)
         AVL_TRY(launch_sort(g, src, dst, nullptr, nullptr, g.dt, g.bscale, counts, offsets, tsum, tsum + tstride,
-                            flags, false, st, phase));
+                            flags, false, st, phase, nullptr, nullptr, nullptr));
     if (g.vdim == 1) AVL_TRY(launch_recon(g, dst, offsets, f_out, D_out, rho_part, st));
     else AVL_TRY(launch_recon3(g, dst, offsets, f_out, D_out, rho_part, nullptr, st));
     return AVL_OK;

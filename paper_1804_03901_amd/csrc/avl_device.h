@@ -112,7 +112,8 @@ struct BInst {
     double* E;                 // the field (read by the push, written by the solve)
     const RowShift* rows;
     int* counts;
-    int* offsets;
+    int* offsets[2];           // run offsets of the order of marker buffer p
+    int* tfirst[2];            // bucket of every 2048th position of that order (implied FP32 cells)
     int* tsum[2];              // per-scan-tile totals, by buffer parity
     void* fgrid;
     double* rho_part;

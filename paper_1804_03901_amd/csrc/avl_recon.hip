@@ -613,7 +613,7 @@ __global__ __launch_bounds__(kWave) void k_recon_b(const BInst* __restrict__ tab
     if (task < 0) return;
     const int i = find_inst(pr, ninst, task);
     const BInst& I = tab[i];
-    recon_task<PREC, KAHAN, SPARSE>(I.g, rmark<PREC>(I, cur), I.offsets, (typename RT<PREC>::T*)I.fgrid, nullptr,
+    recon_task<PREC, KAHAN, SPARSE>(I.g, rmark<PREC>(I, cur), I.offsets[cur], (typename RT<PREC>::T*)I.fgrid, nullptr,
                             I.rho_part, task - pr[i]);
 }
 

@@ -16,6 +16,18 @@
 // that window (large velocity jumps) use one global atomic each.  The scatter
 // uses the counts array itself as a descending cursor, which leaves it zeroed
 // for the next step.
+//
+// Implied cells (FP32 1D-1V).  In that form a marker's cell index equals its
+// bucket whenever its cloud touches the grid, and once sorted, a marker's
+// bucket is the run its position falls in.  So the scatter stores the cell
+// index only for markers of the overflow bucket, and the next sort recovers
+// every other cell from the previous run offsets: per tile, the starts of the
+// runs inside it are marked in LDS and a block-wide running maximum fills in
+// the rest (the scan also records the bucket of every kTfStride-th position,
+// where each tile starts).  That is 4 bytes a marker less to read in the count
+// and the scatter and to write in the scatter.
+#include <algorithm>
+
 #include "avl_device.h"
 
 namespace avl {
@@ -30,14 +42,14 @@ template <int PREC, int VD> struct Pay;
 template <int VD> struct Pay<0, VD> {
     double x, v[VD], f;
     int id;
-    __device__ void load(const M64& m, const Geo& g, int i, bool with_f) {
+    __device__ void load(const M64& m, const Geo& g, int i, bool with_f, int = VD, bool = true) {
         x = m.x[i];
 #pragma unroll
         for (int d = 0; d < VD; ++d) v[d] = m.v[(size_t)d * g.np + i];
         f = with_f ? m.f[i] : 0.0;
         id = (with_f && m.id) ? m.id[i] : 0;
     }
-    __device__ void store(const M64& m, const Geo& g, int i) const {
+    __device__ void store(const M64& m, const Geo& g, int i, bool = true) const {
         m.x[i] = x;
 #pragma unroll
         for (int d = 0; d < VD; ++d) m.v[(size_t)d * g.np + i] = v[d];
@@ -61,17 +73,21 @@ template <int VD> struct Pay<1, VD> {
     int cell;
     float a, b[VD], f;
     int id;
-    // nvel < VD loads only the first nvel velocity offsets
-    __device__ void load(const M32& m, const Geo& g, int i, bool with_f, int nvel = VD) {
-        cell = m.cell[i];
+    // nvel < VD loads only the first nvel velocity offsets; with_cell false
+    // leaves the cell index to be filled in from the previous run offsets
+    __device__ void load(const M32& m, const Geo& g, int i, bool with_f, int nvel = VD, bool with_cell = true) {
+        cell = with_cell ? m.cell[i] : 0;
         a = m.a[i];
 #pragma unroll
         for (int d = 0; d < VD; ++d) b[d] = d < nvel ? m.b[(size_t)d * g.np + i] : 0.0f;
         f = with_f ? m.f[i] : 0.0f;
         id = (with_f && m.id) ? m.id[i] : 0;
     }
-    __device__ void store(const M32& m, const Geo& g, int i) const {
-        m.cell[i] = cell;
+    // all_cells false (the sort's output in 1D-1V): the cell index is written
+    // only for markers of the overflow bucket, the others being implied by
+    // the run offsets of the new order
+    __device__ void store(const M32& m, const Geo& g, int i, bool all_cells = true) const {
+        if (all_cells || VD != 1 || bucket32<VD>(g, cell) == g.nb) m.cell[i] = cell;
         m.a[i] = a;
 #pragma unroll
         for (int d = 0; d < VD; ++d) m.b[(size_t)d * g.np + i] = b[d];
@@ -107,7 +123,7 @@ template <int PREC, int VD, int K> struct Group;
 
 template <int VD, int K> struct Group<0, VD, K> {
     Pay<0, VD> p[K];
-    __device__ void load(const M64& m, const Geo& g, int first, int last, bool with_f, int = VD) {
+    __device__ void load(const M64& m, const Geo& g, int first, int last, bool with_f, int = VD, int = -1) {
         if (first + K - 1 <= last) {
             double t[K];
             vload<double, K>(m.x + first, t);
@@ -134,14 +150,26 @@ template <int VD, int K> struct Group<0, VD, K> {
 template <int VD, int K> struct Group<1, VD, K> {
     Pay<1, VD> p[K];
     // nvel < VD loads only the first nvel velocity offsets (the count pass
-    // needs the cell index, a and the x-velocity offset only)
-    __device__ void load(const M32& m, const Geo& g, int first, int last, bool with_f, int nvel = VD) {
+    // needs the cell index, a and the x-velocity offset only).  ovf >= 0:
+    // implied cells, read from memory only at positions >= ovf (the
+    // overflow run of the previous order); the rest are filled in later.
+    __device__ void load(const M32& m, const Geo& g, int first, int last, bool with_f, int nvel = VD, int ovf = -1) {
         if (first + K - 1 <= last) {
             int ti[K];
             float t[K];
-            vload<int, K>(m.cell + first, ti);
+            if (ovf < 0) {
+                vload<int, K>(m.cell + first, ti);
 #pragma unroll
-            for (int k = 0; k < K; ++k) p[k].cell = ti[k];
+                for (int k = 0; k < K; ++k) p[k].cell = ti[k];
+            } else {
+#pragma unroll
+                for (int k = 0; k < K; ++k) p[k].cell = 0;
+                if (first + K - 1 >= ovf) {
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+                        if (first + k >= ovf) p[k].cell = m.cell[first + k];
+                }
+            }
             vload<float, K>(m.a + first, t);
 #pragma unroll
             for (int k = 0; k < K; ++k) p[k].a = t[k];
@@ -163,10 +191,93 @@ template <int VD, int K> struct Group<1, VD, K> {
             }
         } else {
 #pragma unroll
-            for (int k = 0; k < K; ++k) p[k].load(m, g, min(first + k, last), with_f, nvel);
+            for (int k = 0; k < K; ++k) {
+                const int i = min(first + k, last);
+                p[k].load(m, g, i, with_f, nvel, ovf < 0 || i >= ovf);
+            }
         }
     }
 };
+
+// ---------------------------------------------------------------------------
+// Implied cells: the previous order's buckets of one tile's positions.
+// ---------------------------------------------------------------------------
+constexpr int kTfLog = 11;                   // the scan records the bucket of every 2^kTfLog-th position
+constexpr int kTfStride = 1 << kTfLog;
+static_assert(kSortTile == kTfStride && kCountTile % kTfStride == 0, "tiles start at recorded positions");
+
+// The order the markers are in, for implied cells: its run offsets (nb + 2
+// entries) and the bucket of every kTfStride-th position.  off == nullptr:
+// the cell indices are all stored.
+struct Prev {
+    const int* off;
+    const int* tfirst;
+};
+
+// Buckets of the positions [base, end) of a tile (base a multiple of
+// kTfStride, end at most the start of the overflow run): the largest b with
+// off[b] <= p.  Thread t owns the SL slots [t SL, t SL + SL) of `map` (T =
+// kSortThreads SL ints of LDS, free on entry) and gets their buckets in bk[]
+// (undefined past end); with WRITE they are also left in map for other
+// threads, after a barrier.  s_aux: kSortThreads / kWave + 1 ints of LDS.
+template <int SL, bool WRITE>
+__device__ __forceinline__ void tile_buckets(const Geo& g, const Prev& pv, int base, int end, int* map, int* s_aux,
+                                             int (&bk)[SL])
+{
+    static_assert(SL % 4 == 0, "slots are cleared and read as 16-byte vectors");
+    const int tid = threadIdx.x;
+    const int b0 = pv.tfirst[base >> kTfLog];          // the run that holds position base
+    // the LDS is the previous tile's histogram, which its last stores may
+    // still be reading (a block walks several tiles)
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < SL; k += 4) *reinterpret_cast<int4*>(map + tid * SL + k) = make_int4(-1, -1, -1, -1);
+    if (tid == 0) map[0] = b0;
+    __syncthreads();
+    // mark the start of every later run that begins inside the tile
+    for (int bs = b0 + 1;; bs += kSortThreads) {
+        const int b = bs + tid;
+        int lo = end;
+        if (b < g.nb) {
+            lo = pv.off[b];
+            const int hi = pv.off[b + 1];
+            if (lo < hi && lo > base && lo < end) map[lo - base] = b;
+        }
+        if (tid == kSortThreads - 1) s_aux[kSortThreads / kWave] = (b < g.nb && lo < end) ? 1 : 0;
+        __syncthreads();
+        const int more = s_aux[kSortThreads / kWave];
+        __syncthreads();
+        if (!more) break;
+    }
+    // running maximum over the slots: within the thread, then across threads
+#pragma unroll
+    for (int k = 0; k < SL; k += 4) {
+        const int4 v = *reinterpret_cast<const int4*>(map + tid * SL + k);
+        bk[k] = v.x; bk[k + 1] = v.y; bk[k + 2] = v.z; bk[k + 3] = v.w;
+    }
+#pragma unroll
+    for (int k = 1; k < SL; ++k) bk[k] = max(bk[k], bk[k - 1]);
+    const int lane = tid & (kWave - 1), w = tid / kWave;
+    int inc = bk[SL - 1];
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int t = __shfl_up(inc, o, kWave);
+        if (lane >= o) inc = max(inc, t);
+    }
+    int carry = __shfl_up(inc, 1, kWave);
+    if (lane == 0) carry = -1;
+    if (lane == kWave - 1) s_aux[w] = inc;
+    __syncthreads();
+    for (int q = 0; q < w; ++q) carry = max(carry, s_aux[q]);
+#pragma unroll
+    for (int k = 0; k < SL; ++k) bk[k] = max(bk[k], carry);
+    if constexpr (WRITE) {
+#pragma unroll
+        for (int k = 0; k < SL; k += 4)
+            *reinterpret_cast<int4*>(map + tid * SL + k) = make_int4(bk[k], bk[k + 1], bk[k + 2], bk[k + 3]);
+        __syncthreads();
+    }
+}
 
 // The LDS window of a sort block: bucket rows around the rows of the block's
 // first and last marker (which bound the block's rows, the input being
@@ -233,7 +344,9 @@ struct SortSmem {
         using ET = typename MarkersOf<PREC>::E;
         sE = reinterpret_cast<ET*>(smem);
         sRow = reinterpret_cast<RowShift*>(smem + sizeof(ET) * g.nx);
-        hist = reinterpret_cast<int*>(smem + sizeof(ET) * g.nx + (PREC ? sizeof(RowShift) * (g.nv[0] + 1) : 0));
+        // 16-byte aligned: the implied-cell map is accessed as int4
+        const size_t h = (sizeof(ET) * g.nx + (PREC ? sizeof(RowShift) * (g.nv[0] + 1) : 0) + 15) & ~(size_t)15;
+        hist = reinterpret_cast<int*>(smem + h);
     }
 };
 
@@ -267,13 +380,24 @@ struct Agg {
 // One tile of the count pass: the thread's group of K consecutive markers
 // [first, first+K) of the tile [base, last] is in grp (previous order), the
 // field and drift table staged in LDS.
-template <int PREC, int VD, bool PUSH>
+template <int PREC, int VD, bool PUSH, bool IMPL>
 __device__ __forceinline__ void count_tile(const Geo& g, const SortSmem<PREC>& sm, Group<PREC, VD, count_mpt<PREC>()>& grp,
                                            double dtk, float bk, int* __restrict__ counts, int* __restrict__ tsum,
-                                           int base, int last, int* s_b, int* s_lo, int* s_nb, int* s_tile, int& fl)
+                                           int base, int last, int* s_b, int* s_lo, int* s_nb, int* s_tile, int& fl,
+                                           const Prev& pv, int ovf, int* s_aux)
 {
     constexpr int K = count_mpt<PREC>();
     const int first = base + threadIdx.x * K;
+    if constexpr (IMPL) {
+        // implied cells: this thread's K consecutive positions are its own slots
+        int ob[K];
+        if (base < ovf) {
+            tile_buckets<K, false>(g, pv, base, min(last + 1, ovf), sm.hist, s_aux, ob);
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (first + k < ovf) grp.p[k].cell = ob[k];
+        }
+    }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         if (first + k == base) s_b[0] = grp.p[k].bucket(g);
@@ -338,24 +462,26 @@ __device__ __forceinline__ int count_tile_last(const Geo& g, int t)
 
 // count pass of one block over one tile (the batched kernel and the forms
 // without a tiled kernel)
-template <int PREC, int VD, bool PUSH>
+template <int PREC, int VD, bool PUSH, bool IMPL>
 __device__ __forceinline__ void count_block(const Geo& g, const typename MarkersOf<PREC>::T& m,
                                             const double* __restrict__ E, const RowShift* __restrict__ rows_g,
                                             double dtk, float bk, int* __restrict__ counts, int* __restrict__ tsum,
-                                            int* __restrict__ flags, int blk)
+                                            int* __restrict__ flags, int blk, const Prev& pv)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     SortSmem<PREC> sm(smem, g);
-    __shared__ int s_b[2], s_lo, s_nb, s_flags, s_tile[8];
+    __shared__ int s_b[2], s_lo, s_nb, s_flags, s_tile[8], s_aux[kSortThreads / kWave + 1];
     if (threadIdx.x == 0) s_flags = 0;
     if (PUSH) stage_tables<PREC>(g, sm.sE, sm.sRow, E, rows_g, bk);
     constexpr int K = count_mpt<PREC>();
     Group<PREC, VD, K> grp;
     const int base = blk * (kSortThreads * K);
     const int last = count_tile_last<PREC>(g, blk);
-    grp.load(m, g, base + threadIdx.x * K, last, false, PREC ? 1 : VD);
+    const int ovf = IMPL ? pv.off[g.nb] : -1;
+    grp.load(m, g, base + threadIdx.x * K, last, false, PREC ? 1 : VD, ovf);
     int fl = 0;
-    count_tile<PREC, VD, PUSH>(g, sm, grp, dtk, bk, counts, tsum, base, last, s_b, &s_lo, &s_nb, s_tile, fl);
+    count_tile<PREC, VD, PUSH, IMPL>(g, sm, grp, dtk, bk, counts, tsum, base, last, s_b, &s_lo, &s_nb, s_tile, fl, pv,
+                                     ovf, s_aux);
     if (fl) atomicOr(&s_flags, fl);
     __syncthreads();
     if (threadIdx.x == 0 && s_flags) atomicOr(flags, s_flags);
@@ -369,34 +495,36 @@ __global__ __launch_bounds__(kSortThreads) void k_count(Geo g, typename MarkersO
                                                          int* __restrict__ counts, int* __restrict__ tsum,
                                                          int* __restrict__ flags)
 {
-    count_block<PREC, VD, PUSH>(g, m, E, rows_g, dtk, bk, counts, tsum, flags, blockIdx.x);
+    count_block<PREC, VD, PUSH, false>(g, m, E, rows_g, dtk, bk, counts, tsum, flags, blockIdx.x, Prev{nullptr, nullptr});
 }
 
 // Tiled count pass: each block takes tiles blockIdx.x, blockIdx.x + gridDim.x,
 // ... (one block per resident slot), so the field and drift table are staged
 // once per block instead of once per tile.
-template <int PREC, int VD, bool PUSH>
+template <int PREC, int VD, bool PUSH, bool IMPL>
 __global__ __launch_bounds__(kSortThreads) void k_count_tiled(Geo g, typename MarkersOf<PREC>::T m,
                                                          const double* __restrict__ E,
                                                          const RowShift* __restrict__ rows_g,
                                                          double dtk, float bk,
                                                          int* __restrict__ counts, int* __restrict__ tsum,
-                                                         int* __restrict__ flags)
+                                                         int* __restrict__ flags, Prev pv)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     SortSmem<PREC> sm(smem, g);
-    __shared__ int s_b[2], s_lo, s_nb, s_flags, s_tile[8];
+    __shared__ int s_b[2], s_lo, s_nb, s_flags, s_tile[8], s_aux[kSortThreads / kWave + 1];
     constexpr int K = count_mpt<PREC>();
     constexpr int T = kSortThreads * K;
     const int ntiles = (g.n + T - 1) / T;
+    const int ovf = IMPL ? pv.off[g.nb] : -1;
     if (threadIdx.x == 0) s_flags = 0;
     if (PUSH) stage_tables<PREC>(g, sm.sE, sm.sRow, E, rows_g, bk);
     int fl = 0;
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         Group<PREC, VD, K> grp;
         const int last = count_tile_last<PREC>(g, t);
-        grp.load(m, g, t * T + threadIdx.x * K, last, false, PREC ? 1 : VD);
-        count_tile<PREC, VD, PUSH>(g, sm, grp, dtk, bk, counts, tsum, t * T, last, s_b, &s_lo, &s_nb, s_tile, fl);
+        grp.load(m, g, t * T + threadIdx.x * K, last, false, PREC ? 1 : VD, ovf);
+        count_tile<PREC, VD, PUSH, IMPL>(g, sm, grp, dtk, bk, counts, tsum, t * T, last, s_b, &s_lo, &s_nb, s_tile,
+                                         fl, pv, ovf, s_aux);
     }
     if (fl) atomicOr(&s_flags, fl);
     __syncthreads();
@@ -413,13 +541,26 @@ __global__ __launch_bounds__(kSortThreads) void k_count_tiled(Geo g, typename Ma
 // ---------------------------------------------------------------------------
 // One tile of the scatter: the markers [base, last] of the previous order are
 // in p[] (lane-strided), the field and drift table staged in LDS.
-template <int PREC, int VD, bool PUSH>
+template <int PREC, int VD, bool PUSH, bool IMPL>
 __device__ __forceinline__ void scatter_tile(const Geo& g, const SortSmem<PREC>& sm, Pay<PREC, VD>* p,
                                              const typename MarkersOf<PREC>::T& dst, double dtk, float bk,
                                              const int* __restrict__ offsets, int* __restrict__ counts,
-                                             int base, int last, int* s_b, int* s_lo, int* s_nb, int& fl)
+                                             int base, int last, int* s_b, int* s_lo, int* s_nb, int& fl,
+                                             const Prev& pv, int ovf, int* s_aux)
 {
     constexpr int K = kSortMPT;
+    if constexpr (IMPL) {
+        // implied cells: the tile's buckets are left in LDS, read lane-strided
+        if (base < ovf) {
+            int ob[K];
+            tile_buckets<K, true>(g, pv, base, min(last + 1, ovf), sm.hist, s_aux, ob);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int i = base + k * kSortThreads + threadIdx.x;
+                if (i <= last && i < ovf) p[k].cell = sm.hist[i - base];
+            }
+        }
+    }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int i = base + k * kSortThreads + threadIdx.x;
@@ -473,38 +614,44 @@ __device__ __forceinline__ void scatter_tile(const Geo& g, const SortSmem<PREC>&
             dest = slot < 0 ? -1 : offsets[bkt[k]] + slot;
         }
         if (dest < 0) { fl |= FLAG_SLOT; continue; }
-        p[k].store(dst, g, dest);
+        p[k].store(dst, g, dest, false);
     }
 }
 
+// ovf >= 0: implied cells, stored only at positions >= ovf
 template <int PREC, int VD>
 __device__ __forceinline__ void load_tile(const typename MarkersOf<PREC>::T& src, const Geo& g, Pay<PREC, VD>* p,
-                                          int base, int last)
+                                          int base, int last, int ovf = -1)
 {
 #pragma unroll
-    for (int k = 0; k < kSortMPT; ++k) p[k].load(src, g, min(base + k * kSortThreads + (int)threadIdx.x, last), true);
+    for (int k = 0; k < kSortMPT; ++k) {
+        const int i = min(base + k * kSortThreads + (int)threadIdx.x, last);
+        p[k].load(src, g, i, true, VD, ovf < 0 || i >= ovf);
+    }
 }
 
 // scatter pass of one block over one tile (the batched kernel and the forms
 // without a tiled kernel)
-template <int PREC, int VD, bool PUSH>
+template <int PREC, int VD, bool PUSH, bool IMPL>
 __device__ __forceinline__ void scatter_block(const Geo& g, const typename MarkersOf<PREC>::T& src,
                                               const typename MarkersOf<PREC>::T& dst,
                                               const double* __restrict__ E, const RowShift* __restrict__ rows_g,
                                               double dtk, float bk, const int* __restrict__ offsets,
-                                              int* __restrict__ counts, int* __restrict__ flags, int blk)
+                                              int* __restrict__ counts, int* __restrict__ flags, int blk, const Prev& pv)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     SortSmem<PREC> sm(smem, g);
-    __shared__ int s_b[2], s_lo, s_nb, s_flags;
+    __shared__ int s_b[2], s_lo, s_nb, s_flags, s_aux[kSortThreads / kWave + 1];
     const int base = blk * kSortTile;
     const int last = min(base + kSortTile, g.n) - 1;
+    const int ovf = IMPL ? pv.off[g.nb] : -1;
     if (threadIdx.x == 0) s_flags = 0;
     if (PUSH) stage_tables<PREC>(g, sm.sE, sm.sRow, E, rows_g, bk);
     Pay<PREC, VD> p[kSortMPT];
-    load_tile<PREC, VD>(src, g, p, base, last);
+    load_tile<PREC, VD>(src, g, p, base, last, ovf);
     int fl = 0;
-    scatter_tile<PREC, VD, PUSH>(g, sm, p, dst, dtk, bk, offsets, counts, base, last, s_b, &s_lo, &s_nb, fl);
+    scatter_tile<PREC, VD, PUSH, IMPL>(g, sm, p, dst, dtk, bk, offsets, counts, base, last, s_b, &s_lo, &s_nb, fl,
+                                       pv, ovf, s_aux);
     if (fl) atomicOr(&s_flags, fl);
     __syncthreads();
     if (threadIdx.x == 0 && s_flags) atomicOr(flags, s_flags);
@@ -519,37 +666,40 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter1(Geo g, typename Marke
                                                            const int* __restrict__ offsets,
                                                            int* __restrict__ counts, int* __restrict__ flags)
 {
-    scatter_block<PREC, VD, PUSH>(g, src, dst, E, rows_g, dtk, bk, offsets, counts, flags, blockIdx.x);
+    scatter_block<PREC, VD, PUSH, false>(g, src, dst, E, rows_g, dtk, bk, offsets, counts, flags, blockIdx.x,
+                                         Prev{nullptr, nullptr});
 }
 
 // Tiled scatter: each block takes tiles blockIdx.x, blockIdx.x + gridDim.x,
 // ... and loads its next tile's markers while the current one is pushed,
 // ranked, claimed and stored, so the loads of one tile overlap the latency
 // chain of the previous one; the field and drift table are staged once.
-template <int PREC, int VD, bool PUSH>
+template <int PREC, int VD, bool PUSH, bool IMPL>
 __global__ __launch_bounds__(kSortThreads) void k_scatter(Geo g, typename MarkersOf<PREC>::T src,
                                                           typename MarkersOf<PREC>::T dst,
                                                           const double* __restrict__ E,
                                                           const RowShift* __restrict__ rows_g,
                                                           double dtk, float bk,
                                                           const int* __restrict__ offsets,
-                                                          int* __restrict__ counts, int* __restrict__ flags)
+                                                          int* __restrict__ counts, int* __restrict__ flags, Prev pv)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     SortSmem<PREC> sm(smem, g);
-    __shared__ int s_b[2], s_lo, s_nb, s_flags;
+    __shared__ int s_b[2], s_lo, s_nb, s_flags, s_aux[kSortThreads / kWave + 1];
     const int ntiles = (g.n + kSortTile - 1) / kSortTile;
+    const int ovf = IMPL ? pv.off[g.nb] : -1;
     if (threadIdx.x == 0) s_flags = 0;
     if (PUSH) stage_tables<PREC>(g, sm.sE, sm.sRow, E, rows_g, bk);
     int fl = 0;
     Pay<PREC, VD> p[kSortMPT], q[kSortMPT];
     int t = blockIdx.x;
-    load_tile<PREC, VD>(src, g, p, t * kSortTile, min(t * kSortTile + kSortTile, g.n) - 1);
+    load_tile<PREC, VD>(src, g, p, t * kSortTile, min(t * kSortTile + kSortTile, g.n) - 1, ovf);
     for (; t < ntiles; t += gridDim.x) {
         const int tn = t + gridDim.x;
-        if (tn < ntiles) load_tile<PREC, VD>(src, g, q, tn * kSortTile, min(tn * kSortTile + kSortTile, g.n) - 1);
-        scatter_tile<PREC, VD, PUSH>(g, sm, p, dst, dtk, bk, offsets, counts, t * kSortTile,
-                                     min(t * kSortTile + kSortTile, g.n) - 1, s_b, &s_lo, &s_nb, fl);
+        if (tn < ntiles) load_tile<PREC, VD>(src, g, q, tn * kSortTile, min(tn * kSortTile + kSortTile, g.n) - 1, ovf);
+        scatter_tile<PREC, VD, PUSH, IMPL>(g, sm, p, dst, dtk, bk, offsets, counts, t * kSortTile,
+                                           min(t * kSortTile + kSortTile, g.n) - 1, s_b, &s_lo, &s_nb, fl, pv, ovf,
+                                           s_aux);
 #pragma unroll
         for (int k = 0; k < kSortMPT; ++k) p[k] = q[k];
     }
@@ -581,7 +731,7 @@ __global__ __launch_bounds__(kSortThreads) void k_push(Geo g, typename MarkersOf
             Pay<PREC, VD> p;
             p.load(m, g, i, true);
             p.push(g, sE, sRow, dtk, bk, fl);
-            p.store(m, g, i);
+            p.store(m, g, i, true);
         }
     }
     if (fl) atomicOr(flags, fl);
@@ -644,10 +794,12 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(int* __restrict__ tile_sums
 // Offsets of one tile of kScanTile buckets: the tile's start (the sum of the
 // preceding tiles' totals, or an already-scanned prefix when `scanned`) plus
 // an in-block exclusive scan of its counts, 16 per thread as 16-byte vectors.
-// Also clears the other parity's tile totals for the next count pass.
+// Also clears the other parity's tile totals for the next count pass, and
+// (tfirst non-null) records for every position p = t kTfStride of the new
+// order the bucket whose run holds it: tfirst[t].
 __device__ __forceinline__ void scan_tile(const int* __restrict__ counts, int nbt, const int* __restrict__ tsum,
                                           int scanned, int* __restrict__ tsum_next, int* __restrict__ offsets,
-                                          int tile)
+                                          int tile, int* __restrict__ tfirst)
 {
     __shared__ int s_w[kScanThreads / kWave + 1];
     __shared__ int s_pre;
@@ -690,6 +842,12 @@ __device__ __forceinline__ void scan_tile(const int* __restrict__ counts, int nb
         o[k] = run;
         run += c[k];
     }
+    if (tfirst) {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k)
+            for (int t = (o[k] + kTfStride - 1) >> kTfLog; c[k] > 0 && t <= (o[k] + c[k] - 1) >> kTfLog; ++t)
+                tfirst[t] = base + k;
+    }
     if (base + kScanItems <= nbt) {
 #pragma unroll
         for (int k = 0; k < kScanItems; k += 4)
@@ -703,9 +861,10 @@ __device__ __forceinline__ void scan_tile(const int* __restrict__ counts, int nb
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int* __restrict__ counts, int nbt,
                                                             const int* __restrict__ tsum, int scanned,
-                                                            int* __restrict__ tsum_next, int* __restrict__ offsets)
+                                                            int* __restrict__ tsum_next, int* __restrict__ offsets,
+                                                            int* __restrict__ tfirst)
 {
-    scan_tile(counts, nbt, tsum, scanned, tsum_next, offsets, blockIdx.x);
+    scan_tile(counts, nbt, tsum, scanned, tsum_next, offsets, blockIdx.x, tfirst);
 }
 
 // ---------------------------------------------------------------------------
@@ -717,43 +876,53 @@ static size_t sort_smem(const Geo& g, bool push)
     (void)push;
     size_t e = sizeof(typename MarkersOf<PREC>::E) * g.nx;
     size_t r = PREC ? sizeof(RowShift) * (g.nv[0] + 1) : 0;
-    return e + r + sizeof(int) * g.hist_bins;
+    // the histogram's LDS also holds a tile's implied buckets (FP32 1D-1V)
+    const int bins = (PREC == 1 && g.vdim == 1) ? std::max(g.hist_bins, kCountTile) : g.hist_bins;
+    return ((e + r + 15) & ~(size_t)15) + sizeof(int) * bins;
 }
 
 template <int PREC, int VD>
 static hipError_t launch_sort_t(const Geo& g, void* src, void* dst, const double* E, const RowShift* rows,
                                 double dtk, float bk, int* counts, int* offsets, int* tile_sums, int* tile_next,
-                                int* flags, bool push, hipStream_t st, int phase)
+                                int* flags, bool push, hipStream_t st, int phase, const int* off_old,
+                                const int* tf_old, int* tf_new)
 {
     using MT = typename MarkersOf<PREC>::T;
     MT s = *reinterpret_cast<MT*>(src);
     MT d = dst ? *reinterpret_cast<MT*>(dst) : s;
     // The FP32 1D-1V form uses the tiled count and scatter (one block per
     // resident slot, each walking several tiles; the scatter loads the next
-    // while working on the current one); the other forms hold more registers
+    // while working on the current one) and implied cells when the markers
+    // are in a sorted order (off_old); the other forms hold more registers
     // per marker and use one tile per block.
     constexpr bool tiled = PREC == 1 && VD == 1;
+    const bool impl = tiled && off_old != nullptr;
+    const Prev pv{off_old, tf_old};
     const int ctiles = (g.n + count_tile_size(PREC) - 1) / count_tile_size(PREC);
     const int cblocks = tiled && g.cblocks > 0 ? std::min(ctiles, g.cblocks) : ctiles;
     const int stiles = (g.n + kSortTile - 1) / kSortTile;
     const int sblocks = tiled && g.sblocks > 0 ? std::min(stiles, g.sblocks) : stiles;
     const size_t smem = sort_smem<PREC>(g, push);
     if (g.n == 0 && phase != 1) return hipSuccess;   // the scan still runs: offsets become zero
-    static int granted[4] = {0, 0, 0, 0};
+    static int granted[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     {
-        const void* fns[4];
+        const void* fns[8];
         if constexpr (tiled) {
-            fns[0] = (const void*)k_count_tiled<PREC, VD, true>;
-            fns[1] = (const void*)k_count_tiled<PREC, VD, false>;
-            fns[2] = (const void*)k_scatter<PREC, VD, true>;
-            fns[3] = (const void*)k_scatter<PREC, VD, false>;
+            fns[0] = (const void*)k_count_tiled<PREC, VD, true, false>;
+            fns[1] = (const void*)k_count_tiled<PREC, VD, false, false>;
+            fns[2] = (const void*)k_scatter<PREC, VD, true, false>;
+            fns[3] = (const void*)k_scatter<PREC, VD, false, false>;
+            fns[4] = (const void*)k_count_tiled<PREC, VD, true, true>;
+            fns[5] = (const void*)k_count_tiled<PREC, VD, false, true>;
+            fns[6] = (const void*)k_scatter<PREC, VD, true, true>;
+            fns[7] = (const void*)k_scatter<PREC, VD, false, true>;
         } else {
-            fns[0] = (const void*)k_count<PREC, VD, true>;
-            fns[1] = (const void*)k_count<PREC, VD, false>;
-            fns[2] = (const void*)k_scatter1<PREC, VD, true>;
-            fns[3] = (const void*)k_scatter1<PREC, VD, false>;
+            fns[0] = fns[4] = (const void*)k_count<PREC, VD, true>;
+            fns[1] = fns[5] = (const void*)k_count<PREC, VD, false>;
+            fns[2] = fns[6] = (const void*)k_scatter1<PREC, VD, true>;
+            fns[3] = fns[7] = (const void*)k_scatter1<PREC, VD, false>;
         }
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < 8; ++i) {
             hipError_t e = ensure_lds(fns[i], smem, granted[i]);
             if (e != hipSuccess) return e;
         }
@@ -761,8 +930,14 @@ static hipError_t launch_sort_t(const Geo& g, void* src, void* dst, const double
     const dim3 bl(kSortThreads);
     if (phase == 0) {
         if constexpr (tiled) {
-            if (push) launch(k_count_tiled<PREC, VD, true>, dim3(cblocks), bl, smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags);
-            else launch(k_count_tiled<PREC, VD, false>, dim3(cblocks), bl, smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags);
+            const dim3 gr(cblocks);
+            if (impl) {
+                if (push) launch(k_count_tiled<PREC, VD, true, true>, gr, bl, smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags, pv);
+                else launch(k_count_tiled<PREC, VD, false, true>, gr, bl, smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags, pv);
+            } else {
+                if (push) launch(k_count_tiled<PREC, VD, true, false>, gr, bl, smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags, pv);
+                else launch(k_count_tiled<PREC, VD, false, false>, gr, bl, smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags, pv);
+            }
         } else {
             if (push) launch(k_count<PREC, VD, true>, dim3(cblocks), bl, smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags);
             else launch(k_count<PREC, VD, false>, dim3(cblocks), bl, smem, st, g, s, E, rows, dtk, bk, counts, tile_sums, flags);
@@ -777,11 +952,17 @@ static hipError_t launch_sort_t(const Geo& g, void* src, void* dst, const double
             scanned = 1;
         }
         hipLaunchKernelGGL(k_scan_apply, dim3(ntiles), dim3(kScanThreads), 0, st, counts, nbt, tile_sums, scanned,
-                           tile_next, offsets);
+                           tile_next, offsets, tf_new);
     } else {
         if constexpr (tiled) {
-            if (push) launch(k_scatter<PREC, VD, true>, dim3(sblocks), bl, smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags);
-            else launch(k_scatter<PREC, VD, false>, dim3(sblocks), bl, smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags);
+            const dim3 gr(sblocks);
+            if (impl) {
+                if (push) launch(k_scatter<PREC, VD, true, true>, gr, bl, smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags, pv);
+                else launch(k_scatter<PREC, VD, false, true>, gr, bl, smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags, pv);
+            } else {
+                if (push) launch(k_scatter<PREC, VD, true, false>, gr, bl, smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags, pv);
+                else launch(k_scatter<PREC, VD, false, false>, gr, bl, smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags, pv);
+            }
         } else {
             if (push) launch(k_scatter1<PREC, VD, true>, dim3(sblocks), bl, smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags);
             else launch(k_scatter1<PREC, VD, false>, dim3(sblocks), bl, smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags);
@@ -790,21 +971,26 @@ static hipError_t launch_sort_t(const Geo& g, void* src, void* dst, const double
     return hipGetLastError();
 }
 
-// phase 0 = count, 1 = scan, 2 = scatter
+// phase 0 = count, 1 = scan, 2 = scatter.  offsets: the run offsets of the new
+// order (written by the scan, used by the scatter); off_old / tf_old: the
+// order the markers are in, for implied cells (FP32 1D-1V; nullptr when every
+// cell index is stored); tf_new (may be null): the scan's record of the new
+// order's tile starts.
 hipError_t launch_sort(const Geo& g, void* src, void* dst, const double* E, const RowShift* rows,
                        double dtk, float bk, int* counts, int* offsets, int* tile_sums, int* tile_next, int* flags,
-                       bool push, hipStream_t st, int phase)
+                       bool push, hipStream_t st, int phase, const int* off_old, const int* tf_old, int* tf_new)
 {
-    if (g.prec == 0 && g.vdim == 1) return launch_sort_t<0, 1>(g, src, dst, E, rows, dtk, bk, counts, offsets, tile_sums, tile_next, flags, push, st, phase);
-    if (g.prec == 0 && g.vdim == 3) return launch_sort_t<0, 3>(g, src, dst, E, rows, dtk, bk, counts, offsets, tile_sums, tile_next, flags, push, st, phase);
-    if (g.prec == 1 && g.vdim == 1) return launch_sort_t<1, 1>(g, src, dst, E, rows, dtk, bk, counts, offsets, tile_sums, tile_next, flags, push, st, phase);
-    return launch_sort_t<1, 3>(g, src, dst, E, rows, dtk, bk, counts, offsets, tile_sums, tile_next, flags, push, st, phase);
+    if (g.prec == 0 && g.vdim == 1) return launch_sort_t<0, 1>(g, src, dst, E, rows, dtk, bk, counts, offsets, tile_sums, tile_next, flags, push, st, phase, nullptr, nullptr, tf_new);
+    if (g.prec == 0 && g.vdim == 3) return launch_sort_t<0, 3>(g, src, dst, E, rows, dtk, bk, counts, offsets, tile_sums, tile_next, flags, push, st, phase, nullptr, nullptr, tf_new);
+    if (g.prec == 1 && g.vdim == 1) return launch_sort_t<1, 1>(g, src, dst, E, rows, dtk, bk, counts, offsets, tile_sums, tile_next, flags, push, st, phase, off_old, tf_old, tf_new);
+    return launch_sort_t<1, 3>(g, src, dst, E, rows, dtk, bk, counts, offsets, tile_sums, tile_next, flags, push, st, phase, nullptr, nullptr, tf_new);
 }
 
 // ---------------------------------------------------------------------------
 // batched passes: one launch covers every instance of a batch (1D-1V); block b
 // belongs to the instance whose prefix range holds b and runs that
-// instance's block body with the instance's own geometry and buffers.
+// instance's block body with the instance's own geometry and buffers.  The
+// instances are always in a sorted order here, so FP32 cells are implied.
 // ---------------------------------------------------------------------------
 template <int PREC> __device__ __forceinline__ const typename MarkersOf<PREC>::T& bmark(const BInst& I, int b);
 template <> __device__ __forceinline__ const M64& bmark<0>(const BInst& I, int b) { return I.m64[b]; }
@@ -817,8 +1003,8 @@ __global__ __launch_bounds__(kSortThreads) void k_count_b(const BInst* __restric
     const int* pr = pre + BPRE_COUNT * (ninst + 1);
     const int i = find_inst(pr, ninst, blockIdx.x);
     const BInst& I = tab[i];
-    count_block<PREC, 1, true>(I.g, bmark<PREC>(I, cur), I.E, I.rows, I.dtk, I.bk, I.counts, I.tsum[cur], I.flags,
-                               blockIdx.x - pr[i]);
+    count_block<PREC, 1, true, PREC == 1>(I.g, bmark<PREC>(I, cur), I.E, I.rows, I.dtk, I.bk, I.counts, I.tsum[cur],
+                                          I.flags, blockIdx.x - pr[i], Prev{I.offsets[cur], I.tfirst[cur]});
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_b(const BInst* __restrict__ tab, const int* __restrict__ pre,
@@ -827,7 +1013,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_b(const BInst* __restrict
     const int* pr = pre + BPRE_SCAN * (ninst + 1);
     const int i = find_inst(pr, ninst, blockIdx.x);
     const BInst& I = tab[i];
-    scan_tile(I.counts, I.g.nb + 1, I.tsum[cur], 0, I.tsum[1 - cur], I.offsets, blockIdx.x - pr[i]);
+    scan_tile(I.counts, I.g.nb + 1, I.tsum[cur], 0, I.tsum[1 - cur], I.offsets[1 - cur], blockIdx.x - pr[i],
+              I.tfirst[1 - cur]);
 }
 
 template <int PREC>
@@ -837,8 +1024,9 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter_b(const BInst* __restr
     const int* pr = pre + BPRE_SCATTER * (ninst + 1);
     const int i = find_inst(pr, ninst, blockIdx.x);
     const BInst& I = tab[i];
-    scatter_block<PREC, 1, true>(I.g, bmark<PREC>(I, cur), bmark<PREC>(I, 1 - cur), I.E, I.rows, I.dtk, I.bk,
-                                 I.offsets, I.counts, I.flags, blockIdx.x - pr[i]);
+    scatter_block<PREC, 1, true, PREC == 1>(I.g, bmark<PREC>(I, cur), bmark<PREC>(I, 1 - cur), I.E, I.rows, I.dtk,
+                                            I.bk, I.offsets[1 - cur], I.counts, I.flags, blockIdx.x - pr[i],
+                                            Prev{I.offsets[cur], I.tfirst[cur]});
 }
 
 // Blocks of a batched pass for one instance (host side).
@@ -859,9 +1047,9 @@ int count_blocks_per_cu(const Geo& g)
     const size_t smem = sort_smem<1>(g, true);
     static int granted = 0;
     int per_cu = 0;
-    if (ensure_lds((const void*)k_count_tiled<1, 1, true>, smem, granted) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_count_tiled<1, 1, true>, kSortThreads,
-                                                     smem) != hipSuccess ||
+    if (ensure_lds((const void*)k_count_tiled<1, 1, true, true>, smem, granted) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_count_tiled<1, 1, true, true>,
+                                                     kSortThreads, smem) != hipSuccess ||
         per_cu <= 0) {
         (void)hipGetLastError();
         per_cu = 0;
@@ -875,9 +1063,9 @@ int scatter_blocks_per_cu(const Geo& g)
     const size_t smem = sort_smem<1>(g, true);
     static int granted = 0;
     int per_cu = 0;
-    if (ensure_lds((const void*)k_scatter<1, 1, true>, smem, granted) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_scatter<1, 1, true>, kSortThreads, smem) !=
-            hipSuccess ||
+    if (ensure_lds((const void*)k_scatter<1, 1, true, true>, smem, granted) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_scatter<1, 1, true, true>, kSortThreads,
+                                                     smem) != hipSuccess ||
         per_cu <= 0) {
         (void)hipGetLastError();
         per_cu = 4;
@@ -910,6 +1098,24 @@ hipError_t launch_sort_batch(int prec, const BInst* tab, const int* pre, int nin
         if (prec == 0) hipLaunchKernelGGL(k_scatter_b<0>, gr, dim3(kSortThreads), smem, st, tab, pre, ninst, cur);
         else hipLaunchKernelGGL(k_scatter_b<1>, gr, dim3(kSortThreads), smem, st, tab, pre, ninst, cur);
     }
+    return hipGetLastError();
+}
+
+// Stored cell index of every marker of a sorted FP32 1D-1V order: the run a
+// position lies in is its cell (the overflow run keeps its stored values).
+__global__ __launch_bounds__(256) void k_cells(Geo g, const int* __restrict__ off, int* __restrict__ cell)
+{
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < g.nb; b += gridDim.x * blockDim.x) {
+        const int lo = off[b], hi = off[b + 1];
+        for (int p = lo; p < hi; ++p) cell[p] = b;
+    }
+}
+
+hipError_t launch_cells(const Geo& g, const int* offsets, int* cell, hipStream_t st)
+{
+    if (g.n == 0) return hipSuccess;
+    const int blocks = std::min((g.nb + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_cells, dim3(blocks), dim3(256), 0, st, g, offsets, cell);
     return hipGetLastError();
 }
 
