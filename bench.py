@@ -96,6 +96,14 @@ def run_form(avl, inputs, w, x, v, f, form, steps, warmup):
         # algorithmic bytes per launch over the launch's mean duration, against the HBM peak
         frac = nbytes / (ms_avg * 1e-3) / 1e9 / HBM_PEAK_GBS if ms_avg else None
         kt[name] = {"ms_avg": ms_avg, "launches": cnt, "bytes_per_launch": nbytes, "hbm_frac": frac}
+    # the step entry counts the method's own bytes (push and reconstruction,
+    # sorting excluded); the sort's bytes are listed beside it
+    sort_bytes = sum(kt[k]["bytes_per_launch"] for k in ("push_count", "scan", "scatter"))
+    kt["step"]["bytes_kind"] = "method (push + reconstruction, sort excluded)"
+    kt["step"]["sort_bytes_per_step"] = sort_bytes
+    if kt["step"]["ms_avg"]:
+        both = kt["step"]["bytes_per_launch"] + sort_bytes
+        kt["step"]["hbm_frac_with_sort_bytes"] = both / (kt["step"]["ms_avg"] * 1e-3) / 1e9 / HBM_PEAK_GBS
     avl.avl_timing(sim.h, False)
     sim.check()
     sim.close()
@@ -221,6 +229,7 @@ def cpu_baseline_all_cores(args, procs):
 
 
 def cpu_model():
+    """The host CPU's model name as lscpu reports it."""
     try:
         out = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
         for line in out.splitlines():
@@ -228,7 +237,15 @@ def cpu_model():
                 return line.split(":", 1)[1].strip()
     except Exception:
         pass
-    return platform.processor()
+    return platform.processor() or "unknown"
+
+
+def cpu_count():
+    """Logical CPUs the process may use (nproc)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except Exception:
+        return os.cpu_count() or 1
 
 
 def main():
@@ -248,7 +265,8 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="instances of the batched parameter scan (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--cpu-cores", type=int, default=16,
-                    help="processes of the all-core CPU baseline (at most the host's cores; 0: skip)")
+                    help="most processes of the all-core CPU baseline (nproc of the host, capped here: a GPU "
+                         "box grants one GPU's share of 16 CPUs; 0: skip)")
     ap.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_child:
@@ -336,11 +354,12 @@ def main():
     if not args.no_cpu:
         log(f"cpu baseline: oracle, {args.cpu_steps} steps on the full marker set, 1 thread")
         rate, secs = cpu_baseline(inputs, w, x, v.reshape(1, -1), f, args.cpu_steps)
+        nproc = cpu_count()
         out["cpu_baseline"] = {"value": rate, "unit": "marker-steps/s", "cores": 1, "kind": "oracle",
                                "sample": f"{args.cpu_steps} steps of the full {w.n_markers}-marker workload "
                                          f"after the initial solve ({secs:.1f} s), FP64, single thread",
-                               "cpu": cpu_model()}
-        procs = min(args.cpu_cores, os.cpu_count() or 1)
+                               "cpu": cpu_model(), "nproc": nproc}
+        procs = min(args.cpu_cores, nproc)
         if procs > 1:
             steps_all = max(1, args.cpu_steps // 8)
             log(f"cpu baseline, all cores: {procs} oracle processes, {steps_all} steps each")
@@ -348,9 +367,11 @@ def main():
             a.cpu_steps = steps_all
             rate_all, secs_all = cpu_baseline_all_cores(a, procs)
             out["cpu_baseline_all_cores"] = {
-                "value": rate_all, "unit": "marker-steps/s", "cores": procs, "kind": "oracle",
+                "value": rate_all, "unit": "marker-steps/s", "cores": procs, "kind": "oracle", "nproc": nproc,
+                "cpu": cpu_model(),
                 "sample": f"{procs} independent copies of the full {w.n_markers}-marker workload, "
-                          f"{steps_all} steps each after the initial solve ({secs_all:.1f} s), FP64, one thread each"}
+                          f"{steps_all} steps each after the initial solve ({secs_all:.1f} s), FP64, one thread each "
+                          f"(nproc {nproc}; at most {args.cpu_cores} processes, the CPU share a GPU box grants)"}
     print(json.dumps(out), flush=True)
 
 

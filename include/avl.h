@@ -266,8 +266,12 @@ int avl_timing(avl_handle* h, int enable);
 int avl_kernel_time(avl_handle* h, int kernel, double* ms_total, int64_t* launches);
 
 /* Algorithmic bytes one launch of the named kernel class moves for this
- * handle's configuration (what the method must read and write, excluding
- * re-reads): used to express achieved bandwidth. */
+ * handle's configuration (what the kernel must read and write, excluding
+ * re-reads): used to express achieved bandwidth.  For AVL_K_STEP it is the
+ * method's own traffic of one step with the sort left out (the push reads and
+ * writes positions and velocities; the reconstruction reads every marker's
+ * offsets and f and the run offsets and writes the f grid); the sort's bytes
+ * are the sum of the AVL_K_PUSH_COUNT, AVL_K_SCAN and AVL_K_SCATTER entries. */
 double avl_kernel_bytes(const avl_handle* h, int kernel);
 
 /* Measurement aid: copy `bytes` (multiple of 16) from src to dst with a plain

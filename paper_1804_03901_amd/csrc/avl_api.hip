@@ -943,21 +943,28 @@ double avl_kernel_bytes(const avl_handle* h, int kernel)
     const double n = g.n;
     double cells = g.nx;
     for (int d = 0; d < g.vdim; ++d) cells *= g.nv[d];
-    const double mk = g.prec == AVL_FP64 ? 8.0 * (2 + g.vdim) : 4.0 * (3 + g.vdim);   // bytes per marker
-    const double pos = g.prec == AVL_FP64 ? 8.0 * (1 + g.vdim) : 4.0 * (2 + g.vdim);  // without f
+    const bool implied = g.prec == AVL_FP32 && g.vdim == 1;     // the sort stores no cell index
+    // stored bytes per marker: everything, and the position/velocity part alone
+    const double mk = g.prec == AVL_FP64 ? 8.0 * (2 + g.vdim) : 4.0 * (3 + g.vdim) - (implied ? 4.0 : 0.0);
+    const double pos = g.prec == AVL_FP64 ? 8.0 * (1 + g.vdim) : 4.0 * (2 + g.vdim) - (implied ? 4.0 : 0.0);
+    // what the push itself must read and write: the FP32 1D-3V form moves
+    // cell, a and b_x only (b_y, b_z never change)
+    const double moved = (g.prec == AVL_FP32 && g.vdim == 3) ? 12.0 : pos;
     const double esz = g.prec == AVL_FP64 ? 8.0 : 4.0;
+    const double runs = 4.0 * (g.nb + 1.0);                     // one run offset per bucket
+    // the reconstruction reads every marker's offsets and f (the FP32 form's
+    // cell index is implied by the sorted order), the run offsets, and writes
+    // the f grid
+    const double recon = n * (g.prec == AVL_FP64 ? mk : 4.0 * (2 + g.vdim)) + runs + cells * esz;
     switch (kernel) {
-    case AVL_K_PUSH_COUNT: return n * pos;                      // read positions and velocities
-    case AVL_K_SCAN: return 3.0 * 4.0 * (g.nb + 1.0);           // counts read twice, offsets written
-    case AVL_K_SCATTER: return 2.0 * n * mk;                    // read and write every marker
-    case AVL_K_RECONSTRUCT: {
-        // every marker's offsets and f (the FP32 form's cell index is implied by
-        // the sorted order), the run offsets, and the f grid written
-        const double rd = g.prec == AVL_FP64 ? mk : 4.0 * (2 + g.vdim);
-        return n * rd + 4.0 * (g.nb + 1.0) + cells * esz;
-    }
-    case AVL_K_FIELD: return 8.0 * g.nx * (g.nchunk + 2.0);          // chunk partials in, rho and E out
-    case AVL_K_STEP: return n * (pos + 3.0 * mk) + cells * esz;
+    case AVL_K_PUSH_COUNT: return n * moved + (implied ? runs : 0.0);   // positions read (+ old run offsets)
+    case AVL_K_SCAN: return 3.0 * runs;                         // counts read twice, offsets written
+    case AVL_K_SCATTER: return 2.0 * n * mk + (implied ? runs : 0.0);   // every marker read and written
+    case AVL_K_RECONSTRUCT: return recon;
+    case AVL_K_FIELD: return 8.0 * g.nx * (g.nchunk + 2.0);     // chunk partials in, rho and E out
+    // the method's own bytes per step, sorting excluded: the push reads and
+    // writes positions and velocities, the reconstruction as above
+    case AVL_K_STEP: return 2.0 * n * moved + recon;
     default: return 0.0;
     }
 }

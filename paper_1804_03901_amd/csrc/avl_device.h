@@ -331,13 +331,21 @@ struct FixGrid {
 // Power of two 2^e as an FP64 number, for e in the normal range.
 __device__ __forceinline__ double fix_pow2(int e) { return __longlong_as_double((long long)(e + 1023) << 52); }
 
-// Grid for len terms of magnitude below 2^(emax + 1).  The exponent is kept
+// Grid exponent for len terms of magnitude below 2^(emax + 1).  It is kept
 // where q, 1/q and C are all normal numbers (a coarser grid for terms below
 // 2^-900 still bounds them).
-__device__ __forceinline__ FixGrid fix_grid(int emax, int len)
+__device__ __forceinline__ int fix_exponent(int emax, int len)
 {
     const int lg = len > 1 ? 32 - __builtin_clz((unsigned)(len - 1)) : 0;     // ceil(log2(len))
-    const int e = min(max(emax + 1 + lg - 51, -960), 960);
+    return min(max(emax + 1 + lg - 51, -960), 960);
+}
+
+// The accumulator origin C = 3 * 2^51 * q alone (all the rounding-mode path needs).
+__device__ __forceinline__ double fix_origin(int emax, int len) { return 3.0 * fix_pow2(fix_exponent(emax, len) + 51); }
+
+__device__ __forceinline__ FixGrid fix_grid(int emax, int len)
+{
+    const int e = fix_exponent(emax, len);
     FixGrid gr;
     gr.q = fix_pow2(e);
     gr.inv_q = fix_pow2(-e);
@@ -347,11 +355,13 @@ __device__ __forceinline__ FixGrid fix_grid(int emax, int len)
 
 // floor(log2 |x|) bounds from the raw bits: |x| < 2^(e + 1) with e the
 // returned value (denormals and zero give the smallest normal exponent - 1).
-__device__ __forceinline__ int fix_exp_bits(float x) { return (int)((__float_as_uint(x) >> 23) & 0xff) - 127; }
-__device__ __forceinline__ int fix_exp_bits(double x)
-{
-    return (int)(((unsigned)(__double_as_longlong(x) >> 32) >> 20) & 0x7ff) - 1023;
-}
+// For the largest e over many values, take the largest fix_key (the
+// magnitude's bits, which order like the magnitudes) and convert it once.
+__device__ __forceinline__ unsigned fix_key(float x) { return __float_as_uint(x) & 0x7fffffffu; }
+__device__ __forceinline__ unsigned fix_key(double x) { return (unsigned)(__double_as_longlong(x) >> 32) & 0x7fffffffu; }
+__device__ __forceinline__ int fix_exp_of_key(unsigned k, float) { return (int)(k >> 23) - 127; }
+__device__ __forceinline__ int fix_exp_of_key(unsigned k, double) { return (int)(k >> 20) - 1023; }
+template <typename T> __device__ __forceinline__ int fix_exp_bits(T x) { return fix_exp_of_key(fix_key(x), x); }
 
 __device__ __forceinline__ void fixsum_pin(double& v) { asm volatile("" : "+v"(v)); }
 

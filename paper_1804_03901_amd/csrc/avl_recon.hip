@@ -505,12 +505,13 @@ __device__ __forceinline__ void recon_task(const Geo& g, const typename RT<PREC>
             // largest weight, 1, taken as f = 1): for f = c = 2^k on every
             // marker the f grid is then c times the offset grid, every N sum is
             // c times its D sum, and f = c comes out exactly
-            int emax = -1100;
+            unsigned kmax = 0;
             if (staged) {
-                for (int u = 0; u < len; ++u) emax = max(emax, fix_exp_bits(lds.f[p0 + u]));
+                for (int u = 0; u < len; ++u) kmax = max(kmax, fix_key(lds.f[p0 + u]));
             } else {
-                for (int u = 0; u < len; ++u) emax = max(emax, fix_exp_bits(m.f[p0 + u]));
+                for (int u = 0; u < len; ++u) kmax = max(kmax, fix_key(m.f[p0 + u]));
             }
+            const int emax = len > 0 ? fix_exp_of_key(kmax, T()) : -1100;
             const FixGrid gf = fix_grid(emax, len), gd = fix_grid(0, len);
             FixMoments M;
             M.init(gf, gd);

@@ -251,25 +251,26 @@ void k_recon_3v(Geo g, typename R3<PREC>::M m, const int* __restrict__ offsets, 
             // run's largest w, the f w sums on one fitted to its largest |f w|.
             // For f = c = 2^k on every marker every f w is c w exactly, the two
             // grids differ by exactly c, and f = c comes out exactly
-            int ew = -1100, ef = -1100;
+            unsigned kw = 0, kf = 0;
             if (staged) {
                 for (int k = 0; k < len; ++k) {
-                    const St3 e = st[p0 + k];
-                    ew = max(ew, fix_exp_bits(e.w));
-                    ef = max(ef, fix_exp_bits(e.fw));
+                    kw = max(kw, fix_key(st[p0 + k].w));
+                    kf = max(kf, fix_key(st[p0 + k].fw));
                 }
             } else {
                 for (int k = 0; k < len; ++k) {
                     Raw3<PREC> rr;
                     rr.load(m, g, p0 + k);
                     const St3 e = rr.stage(g, ws);
-                    ew = max(ew, fix_exp_bits(e.w));
-                    ef = max(ef, fix_exp_bits(e.fw));
+                    kw = max(kw, fix_key(e.w));
+                    kf = max(kf, fix_key(e.fw));
                 }
             }
-            const FixGrid gf = fix_grid(ef, len), gd = fix_grid(ew, len);
-            double Sw = gd.C, Saw = gd.C, Sbw = gd.C, Sabw = gd.C;
-            double Sf = gf.C, Saf = gf.C, Sbf = gf.C, Sabf = gf.C;
+            const int ew = len > 0 ? fix_exp_of_key(kw, 0.0) : -1100;
+            const int ef = len > 0 ? fix_exp_of_key(kf, 0.0) : -1100;
+            const double Cw = fix_origin(ew, len), Cf = fix_origin(ef, len);
+            double Sw = Cw, Saw = Cw, Sbw = Cw, Sabw = Cw;
+            double Sf = Cf, Saf = Cf, Sbf = Cf, Sabf = Cf;
             auto pin8 = [&]() {
                 fixsum_pin(Sw); fixsum_pin(Saw); fixsum_pin(Sbw); fixsum_pin(Sabw);
                 fixsum_pin(Sf); fixsum_pin(Saf); fixsum_pin(Sbf); fixsum_pin(Sabf);
@@ -295,25 +296,32 @@ void k_recon_3v(Geo g, typename R3<PREC>::M m, const int* __restrict__ offsets, 
                 fixsum_round_nearest();
                 pin8();
             } else {
-                // the FP64 form locates each marker here, in the default rounding
+                // staged per marker in the default rounding (the FP64 form
+                // locates it here), then added in the rounding toward -infinity
                 for (int k = 0; k < len; ++k) {
                     Raw3<PREC> rr;
                     rr.load(m, g, p0 + k);
-                    const St3 e = rr.stage(g, ws);
+                    St3 e = rr.stage(g, ws);
+                    fixsum_pin(e.a); fixsum_pin(e.b); fixsum_pin(e.w); fixsum_pin(e.fw);
+                    fixsum_round_down();
+                    pin8();
                     const double ab = e.a * e.b;
-                    Sw += fixsum_floor(gd, e.w);
-                    Saw += fixsum_floor(gd, e.a * e.w);
-                    Sbw += fixsum_floor(gd, e.b * e.w);
-                    Sabw += fixsum_floor(gd, ab * e.w);
-                    Sf += fixsum_floor(gf, e.fw);
-                    Saf += fixsum_floor(gf, e.a * e.fw);
-                    Sbf += fixsum_floor(gf, e.b * e.fw);
-                    Sabf += fixsum_floor(gf, ab * e.fw);
+                    Sw += e.w;
+                    Saw = fma(e.a, e.w, Saw);
+                    Sbw = fma(e.b, e.w, Sbw);
+                    Sabw = fma(ab, e.w, Sabw);
+                    Sf += e.fw;
+                    Saf = fma(e.a, e.fw, Saf);
+                    Sbf = fma(e.b, e.fw, Sbf);
+                    Sabf = fma(ab, e.fw, Sabf);
+                    pin8();
+                    fixsum_round_nearest();
+                    pin8();
                 }
             }
             wave_sync_lds3();
-            Sw -= gd.C; Saw -= gd.C; Sbw -= gd.C; Sabw -= gd.C;
-            Sf -= gf.C; Saf -= gf.C; Sbf -= gf.C; Sabf -= gf.C;
+            Sw -= Cw; Saw -= Cw; Sbw -= Cw; Sabw -= Cw;
+            Sf -= Cf; Saf -= Cf; Sbf -= Cf; Sabf -= Cf;
             const double n11 = Sabf, n10 = Saf - Sabf, n01 = Sbf - Sabf, n00 = (Sf - Saf) - n01;
             const double d11 = Sabw, d10 = Saw - Sabw, d01 = Sbw - Sabw, d00 = (Sw - Saw) - d01;
             cN[t] += n00 + from_left3(n10);
