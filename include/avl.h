@@ -34,7 +34,7 @@
  *    carries, its "weight" in the paper's words, Sec. 2).
  *  - Units are the caller's: acceleration is (q/m) E, Poisson's equation is
  *    dE/dx = c_p * rho (c_p = 4*pi in the paper's CGS units, Eq. (poisson)).
- *  - Return values: AVL_OK (0) or a negative avl_status.  Host-side validation
+ *  - Return values: AVL_OK (0) or a negative avl_rc.  Host-side validation
  *    runs before anything is enqueued, so an error return leaves the handle and
  *    the device untouched, except AVL_EDEVICE (a HIP call failed).
  */
@@ -62,7 +62,7 @@ typedef enum {
     AVL_ENOTSUP = -6,     /* configuration outside what this build implements */
     AVL_ENONFINITE = -7,  /* device kernels saw a non-finite marker or field value */
     AVL_EINTERNAL = -8    /* device consistency check failed (sort slots, encoding range) */
-} avl_status;
+} avl_rc;
 
 /* Marker storage form.
  *  AVL_FP64: plain form, markers and grid in FP64.
@@ -251,6 +251,9 @@ int64_t avl_step_count(const avl_handle* h);
 /* Synchronise the stream and report sticky device-side conditions:
  * AVL_ENONFINITE, AVL_EINTERNAL or AVL_OK. */
 int avl_check(avl_handle* h);
+
+/* The same query under its other name: identical behaviour and result. */
+int avl_status(avl_handle* h);
 
 /* Rebind the handle to another stream (hipStream_t). */
 int avl_set_stream(avl_handle* h, void* stream);

@@ -54,7 +54,7 @@ _lib = None
 
 EXPORTS = ["avl_workspace_bytes", "avl_init", "avl_push", "avl_sort", "avl_reconstruct", "avl_moments",
            "avl_poisson", "avl_step", "avl_step_graph", "avl_get_markers", "avl_set_markers", "avl_get_field",
-           "avl_step_count", "avl_check", "avl_set_stream", "avl_timing", "avl_kernel_time", "avl_kernel_bytes",
+           "avl_step_count", "avl_check", "avl_status", "avl_set_stream", "avl_timing", "avl_kernel_time", "avl_kernel_bytes",
            "avl_copy_probe", "avl_strerror", "avl_destroy", "avl_batch_workspace_bytes", "avl_batch_init",
            "avl_batch_step", "avl_batch_instance", "avl_batch_count", "avl_batch_check", "avl_batch_destroy",
            "avl_adjoint_workspace_bytes", "avl_adjoint", "avl_diagnostics", "avl_multi_workspace_bytes",
@@ -99,6 +99,7 @@ def load(path: str = LIB_PATH):
     lib.avl_step_count.argtypes = [vp]
     lib.avl_step_count.restype = c.c_int64
     lib.avl_check.argtypes = [vp]
+    lib.avl_status.argtypes = [vp]
     lib.avl_set_stream.argtypes = [vp, vp]
     lib.avl_timing.argtypes = [vp, c.c_int]
     lib.avl_kernel_time.argtypes = [vp, c.c_int, P(c.c_double), P(c.c_int64)]
@@ -265,6 +266,10 @@ def avl_step_count(h) -> int:
 
 def avl_check(h) -> int:
     return int(load().avl_check(h))
+
+
+def avl_status(h) -> int:
+    return int(load().avl_status(h))
 
 
 def avl_set_stream(h, stream):

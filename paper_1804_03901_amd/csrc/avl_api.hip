@@ -141,6 +141,9 @@ int make_geo(const avl_config* c, Geo* g)
         g->nv[d] = c->nv[d];
         rows *= (c->nv[d] + 1);
         cells *= c->nv[d];
+        // each factor is at most 2^20 + 1: checking after every one keeps
+        // the products far inside int64
+        if (rows * c->nx >= (int64_t)INT32_MAX || cells >= (int64_t)INT32_MAX) return AVL_ESIZE;
         g->vmin[d] = c->vmin[d];
         g->dv[d] = (c->vmax[d] - c->vmin[d]) / c->nv[d];
         g->inv_dv[d] = 1.0 / g->dv[d];
@@ -904,6 +907,8 @@ int avl_check(avl_handle* h)
     if (fl & (FLAG_SLOT | FLAG_RANGE)) return AVL_EINTERNAL;
     return AVL_OK;
 }
+
+int avl_status(avl_handle* h) { return avl_check(h); }
 
 int avl_set_stream(avl_handle* h, void* stream)
 {

@@ -77,7 +77,7 @@ def test_workspace_checks_before_device_work():
 
 def test_null_handle_and_strerror():
     lib = avl.load()
-    for name in ("avl_push", "avl_sort", "avl_check", "avl_destroy"):
+    for name in ("avl_push", "avl_sort", "avl_check", "avl_status", "avl_destroy"):
         fn = getattr(lib, name)
         args = [None] * len(fn.argtypes)
         assert fn(*args) == -1
@@ -177,3 +177,52 @@ def test_multi_species_workspace_rules():
     assert lib.avl_multi_step(None, 1, None) == -1
     assert lib.avl_multi_destroy(None) == -1
     assert lib.avl_multi_init(None, 0, None, 0, None) == -1
+
+
+def test_config_fuzz_host_validation():
+    """Seeded draws of every config field, extremes included (sizes up to
+    2^31 - 1, zero, negative, non-finite and huge floats): the host
+    validation either rejects the config or returns a workspace that holds at
+    least the two marker buffers, and never reads or computes out of range
+    (the sanitizer build runs this same test)."""
+    import numpy as np
+    rng = np.random.default_rng(2024)
+    ints = [-(2 ** 31), -1, 0, 1, 2, 3, 7, 8, 16, 64, 4096, 8192, 2 ** 20, 2 ** 20 + 1, 2 ** 30, 2 ** 31 - 1]
+    floats = [0.0, -1.0, 1e-300, 1e-3, 0.5, 1.0, 12.566, 1e300, float("inf"), float("-inf"), float("nan")]
+    big = [-1, 0, 1, 63, 64, 2 ** 20, 2 ** 31 - 2, 2 ** 31 - 1, 2 ** 31, 2 ** 40, 2 ** 62]
+    lib = avl.load()
+    accepted = 0
+    # the largest velocity grids the validation admits per axis, all at once
+    for vd, nv, nx in [(3, 2 ** 20, 4096), (3, 2 ** 20 + 1, 4096), (3, 2 ** 20, 8), (1, 2 ** 20, 4096)]:
+        for prec in (avl.AVL_FP64, avl.AVL_FP32):
+            c = _cfg(vdim=vd, nv=(nv, nv, nv), nx=nx, precision=prec, n_markers=2 ** 31 - 2,
+                     vmin=(-1.0, -1.0, -1.0), vmax=(1.0, 1.0, 1.0))
+            assert avl.avl_workspace_bytes(c) == 0
+    for i in range(3000):
+        c = _cfg()
+        pick = lambda xs: xs[int(rng.integers(len(xs)))]
+        if rng.random() < 0.5: c.vdim = pick([-1, 0, 1, 2, 3, 3, 1])
+        if rng.random() < 0.5: c.nx = pick(ints + [2 ** int(rng.integers(0, 31))])
+        for d in range(3):
+            if rng.random() < 0.4: c.nv[d] = pick(ints + [int(rng.integers(2, 300))])
+            if rng.random() < 0.2: c.vmin[d] = pick(floats) * pick([-1, 1])
+            if rng.random() < 0.2: c.vmax[d] = pick(floats)
+            if rng.random() < 0.1: c.B[d] = pick(floats)
+        if rng.random() < 0.3: c.precision = pick([-1, 0, 1, 2])
+        if rng.random() < 0.2: c.first_kick = pick([-1, 0, 1, 2])
+        if rng.random() < 0.2: c.options = pick([-1, 0, 1, 2, 3])
+        if rng.random() < 0.4: c.n_markers = pick(big + [int(rng.integers(0, 2 ** 24))])
+        for k in ("L", "dt", "q", "m", "c_p"):
+            if rng.random() < 0.15: setattr(c, k, pick(floats) * pick([-1, 1]))
+        if rng.random() < 0.2: c.tune[0] = pick([-1, 0, 1, 255, 256, 257, 2 ** 31 - 1])
+        n = avl.avl_workspace_bytes(c)
+        if n:
+            accepted += 1
+            per = (8 if c.precision == avl.AVL_FP64 else 4) * (2 + c.vdim)
+            assert n >= 2 * per * max(c.n_markers, 0), (i, n)
+            assert 1 <= c.vdim <= 3 and c.nx >= 8 and 0 <= c.n_markers < 2 ** 31 - 1
+        h = ctypes.c_void_p()
+        rc = lib.avl_init(ctypes.byref(c), ctypes.c_void_p(4096 + 8), 1 << 40, None, None, None, None,
+                          ctypes.byref(h))
+        assert rc < 0 and not h.value
+    assert accepted > 50
