@@ -360,6 +360,42 @@ size_t avl_adjoint_workspace_bytes(const avl_config* cfg, int32_t nsteps, int32_
 int avl_adjoint(avl_handle* h, const double* x, const double* v, const double* f, int32_t nsteps, int32_t every,
                 void* rec, size_t rec_bytes, double* J_out, double* grad_f);
 
+/* The reverse stages of one step, one call each, on caller-supplied states
+ * (avl_adjoint chains the same kernels).  Each is the transpose of the
+ * linearised forward stage, so <J du, lam> = <du, J^T lam> holds for any du,
+ * lam.  All arrays are device memory, caller-owned, 8-byte aligned; outputs
+ * are overwritten; enqueued on the handle's stream.  AVL_ESTATE while kernel
+ * timing is enabled.  The field adjoint of the push is summed as integers on a
+ * grid set by its largest term (see the header of the reverse kernels), so
+ * results do not depend on marker order.
+ *
+ * Reconstruction f = N/D (Eq. (reconstruction)) and moments
+ * rho_i = q prod(dv) sum_j f_ij (Sec. 2), reversed: rho_bar (nx) gives
+ * f_bar = dJ/df_l and, when lam_x and lam_v are both non-NULL, the position
+ * and velocity adjoints dJ/dx_l, dJ/dv_l (n each, in the order of x, v, f).
+ * x, v, f: the state's markers (FP64, n = cfg n_markers, any order); f_grid,
+ * D_grid: that state's f and D grids in the storage precision, as
+ * avl_reconstruct writes them for these markers.  Cells with D = 0 carry
+ * nothing.  1D-1V only (AVL_ENOTSUP otherwise). */
+int avl_adjoint_deposit(avl_handle* h, const double* x, const double* v, const double* f, const void* f_grid,
+                        const void* D_grid, const double* rho_bar, double* f_bar, double* lam_x, double* lam_v);
+
+/* Gather + kick + drift (Sec. 2: E interpolated to the marker with the
+ * cloud-in-cell weights, v' = v + (q/m) E dt kick, x' = x + v' dt), reversed:
+ * from the adjoints lam_x_in, lam_v_in of (x', v') and the field E (nx) the
+ * push used, the adjoints lam_x, lam_v of (x, v) and E_bar = dJ/dE (nx).  x:
+ * positions before the push (FP64, n); kick: the fraction of dt of the
+ * velocity update (1, or 1/2 for a half first kick).  lam_x may equal
+ * lam_x_in and lam_v may equal lam_v_in (in place).  1D-1V only. */
+int avl_adjoint_push(avl_handle* h, const double* x, const double* E, double kick, const double* lam_x_in,
+                     const double* lam_v_in, double* lam_x, double* lam_v, double* E_bar);
+
+/* The spectral solve E = P rho (Eq. (poissonk), softened by
+ * Eq. (kappasoftening), mean of rho removed), reversed: rho_bar = P^T mu =
+ * -P mu (P is a real convolution whose transfer function is odd and
+ * imaginary).  mu and rho_bar: nx doubles each, distinct arrays. */
+int avl_adjoint_field(avl_handle* h, const double* mu, double* rho_bar);
+
 /* ---------------------------------------------------------------------------
  * For callers that cannot allocate device memory -- code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc: the

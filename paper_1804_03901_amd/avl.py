@@ -58,7 +58,8 @@ EXPORTS = ["avl_workspace_bytes", "avl_init", "avl_push", "avl_sort", "avl_recon
            "avl_copy_probe", "avl_strerror", "avl_destroy", "avl_batch_workspace_bytes", "avl_batch_init",
            "avl_batch_step", "avl_batch_instance", "avl_batch_count", "avl_batch_check", "avl_batch_destroy",
            "avl_adjoint_workspace_bytes", "avl_adjoint", "avl_diagnostics", "avl_multi_workspace_bytes",
-           "avl_multi_init", "avl_multi_step", "avl_multi_destroy", "avl_reconstruct_noalloc"]
+           "avl_multi_init", "avl_multi_step", "avl_multi_destroy", "avl_reconstruct_noalloc",
+           "avl_adjoint_deposit", "avl_adjoint_push", "avl_adjoint_field"]
 
 # size of the static scratch array avl_reconstruct_noalloc uses per GPU
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -121,6 +122,9 @@ def load(path: str = LIB_PATH):
     lib.avl_adjoint_workspace_bytes.argtypes = [P(AvlConfig), c.c_int32, c.c_int32]
     lib.avl_adjoint_workspace_bytes.restype = c.c_size_t
     lib.avl_adjoint.argtypes = [vp, vp, vp, vp, c.c_int32, c.c_int32, vp, c.c_size_t, vp, vp]
+    lib.avl_adjoint_deposit.argtypes = [vp] * 10
+    lib.avl_adjoint_push.argtypes = [vp, vp, vp, c.c_double, vp, vp, vp, vp, vp]
+    lib.avl_adjoint_field.argtypes = [vp, vp, vp]
     lib.avl_reconstruct_noalloc.argtypes = [P(AvlConfig), vp, vp, vp, vp, vp, vp]
     for name in EXPORTS:
         if name not in ("avl_workspace_bytes", "avl_step_count", "avl_kernel_bytes", "avl_strerror",
@@ -306,6 +310,20 @@ def avl_adjoint_workspace_bytes(cfg: AvlConfig, nsteps: int, every: int) -> int:
 def avl_adjoint(h, x, v, f, nsteps: int, every: int, rec, J_out, grad_f):
     return _ck(load().avl_adjoint(h, _ptr(x), _ptr(v), _ptr(f), int(nsteps), int(every), _ptr(rec),
                                   rec.numel() * rec.element_size(), _ptr(J_out), _ptr(grad_f)), "avl_adjoint")
+
+
+def avl_adjoint_deposit(h, x, v, f, f_grid, D_grid, rho_bar, f_bar, lam_x=None, lam_v=None):
+    return _ck(load().avl_adjoint_deposit(h, _ptr(x), _ptr(v), _ptr(f), _ptr(f_grid), _ptr(D_grid), _ptr(rho_bar),
+                                          _ptr(f_bar), _ptr(lam_x), _ptr(lam_v)), "avl_adjoint_deposit")
+
+
+def avl_adjoint_push(h, x, E, kick: float, lam_x_in, lam_v_in, lam_x, lam_v, E_bar):
+    return _ck(load().avl_adjoint_push(h, _ptr(x), _ptr(E), float(kick), _ptr(lam_x_in), _ptr(lam_v_in), _ptr(lam_x),
+                                       _ptr(lam_v), _ptr(E_bar)), "avl_adjoint_push")
+
+
+def avl_adjoint_field(h, mu, rho_bar):
+    return _ck(load().avl_adjoint_field(h, _ptr(mu), _ptr(rho_bar)), "avl_adjoint_field")
 
 
 def _cfg_array(cfgs):

@@ -23,7 +23,9 @@
 //              lam_x <- lam_x' + c E'(x) lam_v, E_bar(x) = c lam_v;
 //   * gather:  mu_i^n += W_i(x^n) E_bar (deposited onto the grid).
 // Adjoints are kept per marker identity (the sort moves identities with the
-// markers), so recorded states can be visited in any order.
+// markers), so recorded states can be visited in any order; the gathered
+// field adjoint is summed as integers (order-free), so the gradient is the
+// same bit for bit from run to run.
 #include "avl_device.h"
 
 namespace avl {
@@ -33,17 +35,19 @@ __global__ void k_iota(int* __restrict__ id, int n)
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) id[i] = i;
 }
 
-// Reverse of the reconstruction and moments for the markers of one state:
-// Pmu = P mu (so rho_bar = -Pmu), fg and Dg the state's grids.
+// Reverse of the reconstruction and moments for the markers of one state.
+// R times rscale is rho_bar (the driver passes P mu with rscale = -1); fg and
+// Dg the state's grids.  Marker k has identity id[k] (k itself when id is
+// null); its adjoints are added at that identity.
 template <typename T>
 __global__ void k_adj_deposit(Geo g, const double* __restrict__ x, const double* __restrict__ v,
                               const int* __restrict__ id, const double* __restrict__ f_by_id,
                               const T* __restrict__ fg, const T* __restrict__ Dg,
-                              const double* __restrict__ Pmu, double* __restrict__ lam_x,
+                              const double* __restrict__ R, double rscale, double* __restrict__ lam_x,
                               double* __restrict__ lam_v, double* __restrict__ f_bar, int with_positions)
 {
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < g.n; k += gridDim.x * blockDim.x) {
-        const int l = id[k];
+        const int l = id ? id[k] : k;
         const double fl = f_by_id[l];
         const double s = x[k] * g.inv_dx - 0.5;
         const double fs = floor(s);
@@ -65,7 +69,7 @@ __global__ void k_adj_deposit(Geo g, const double* __restrict__ x, const double*
                 const int col = ci ? ib : ia;
                 const size_t gi = (size_t)j * g.nx + col;
                 const double D = (double)Dg[gi];
-                const double Nb = D > 0.0 ? -g.q_vol * Pmu[col] / D : 0.0;
+                const double Nb = D > 0.0 ? rscale * g.q_vol * R[col] / D : 0.0;
                 const double Db = -Nb * (double)fg[gi];
                 const double G = Nb * fl + Db;
                 const double wx = ci ? a : 1.0 - a;
@@ -82,50 +86,136 @@ __global__ void k_adj_deposit(Geo g, const double* __restrict__ x, const double*
     }
 }
 
-// Reverse of gather + kick + drift for the markers of state n (positions
-// before the push), E the field at step n.  The field adjoint is summed per
-// block in LDS and added to mu_dep with one FP64 atomic per touched column.
-__global__ __launch_bounds__(256) void k_adj_push(Geo g, const double* __restrict__ x, const int* __restrict__ id,
-                                                  const double* __restrict__ E, double c,
-                                                  double* __restrict__ lam_x, double* __restrict__ lam_v,
-                                                  double* __restrict__ mu_dep)
+// Order-free sums of the field adjoint E_bar.  Every term t of a launch is
+// bounded by M < 2^(e + 1), e from the largest |E_bar| of the markers (found
+// by the pass before).  The term is taken on the integer grid q = 2^(e+1-P):
+// T = round(t / q), split as T = H 2^S + Lo with 0 <= Lo < 2^S, and H and Lo
+// are summed in two 64-bit integers per column.  Integer sums do not depend
+// on the order of their terms, so neither does E_bar; S = 62 - ceil(log2(n+1))
+// and P = 2 S keep both sums of up to n terms inside int64, and each term is
+// carried to M 2^-P.
+struct DepScale {
+    int S, P;
+};
+
+static DepScale dep_scale(int n)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    double* dep = reinterpret_cast<double*>(smem);
-    for (int i = threadIdx.x; i < g.nx; i += blockDim.x) dep[i] = 0.0;
-    __syncthreads();
-    const int per = blockDim.x * 8;
-    const int base = blockIdx.x * per;
-    for (int k = base + threadIdx.x; k < min(base + per, g.n); k += blockDim.x) {
-        const int l = id[k];
-        const double Lx = lam_x[l], Lv = lam_v[l];
+    int lg = 0;
+    while (lg < 62 && ((long long)1 << lg) < (long long)n + 1) ++lg;
+    DepScale d;
+    d.S = 62 - lg;
+    d.P = 2 * d.S;
+    return d;
+}
+
+__device__ __forceinline__ int dep_shift(unsigned key, int P)
+{
+    const int e = min(max(fix_exp_of_key(key, 0.0), -900), 1024);
+    return P - e - 1;                        // q = 2^-shift
+}
+
+__device__ __forceinline__ void dep_add(unsigned long long* acc, int nx, int i, double t, int S, int shift)
+{
+    const double T = ldexp(t, shift);        // a power-of-two scaling: exact
+    const double hf = floor(ldexp(T, -S));
+    const long long H = (long long)hf;
+    const long long Lo = (long long)rint(T - ldexp(hf, S));
+    if (H) atomicAdd(&acc[i], (unsigned long long)H);
+    if (Lo) atomicAdd(&acc[nx + i], (unsigned long long)Lo);
+}
+
+// Reverse of gather + kick + drift for the markers of state n (positions
+// before the push), E the field at step n, first pass: the velocity and
+// position adjoints, lam_v <- lam_v' + lam_x' dt, lam_x <- lam_x' + c E'(x)
+// lam_v (in place when the input and output arrays are the same), and the
+// largest |c lam_v| of the launch into key.
+__global__ __launch_bounds__(256) void k_adj_push_lam(Geo g, const double* __restrict__ x, const int* __restrict__ id,
+                                                      const double* __restrict__ E, double c,
+                                                      const double* lam_x_in, const double* lam_v_in,
+                                                      double* lam_x, double* lam_v, unsigned* __restrict__ key)
+{
+    unsigned kmax = 0u;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < g.n; k += gridDim.x * blockDim.x) {
+        const int l = id ? id[k] : k;
+        const double Lx = lam_x_in[l], Lv = lam_v_in[l];
         const double lvt = Lv + Lx * g.dt;
         const double s = x[k] * g.inv_dx - 0.5;
         const double fs = floor(s);
-        const double a = s - fs;
         const int ia = wrap_pow2((int)fs, g.nx);
         const int ib = wrap_pow2(ia + 1, g.nx);
         const double Ep = (E[ib] - E[ia]) * g.inv_dx;
         lam_x[l] = Lx + c * Ep * lvt;
         lam_v[l] = lvt;
-        const double Eb = c * lvt;
-        atomicAdd(&dep[ia], (1.0 - a) * Eb);
-        atomicAdd(&dep[ib], a * Eb);
+        kmax = max(kmax, fix_key(c * lvt));
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < g.nx; i += blockDim.x)
-        if (dep[i] != 0.0) atomicAdd(&mu_dep[i], dep[i]);
+    for (int off = kWave / 2; off > 0; off >>= 1) kmax = max(kmax, (unsigned)__shfl_xor((int)kmax, off));
+    if ((threadIdx.x & (kWave - 1)) == 0 && kmax) atomicMax(key, kmax);
 }
 
-// mu = w * E + mu_dep (w = 2 dx dt for a step that enters J, else 0); mu_dep
-// is cleared for the next step.
-__global__ void k_adj_mu(int nx, const double* __restrict__ E, double w, double* __restrict__ mu_dep,
-                         double* __restrict__ mu)
+// Second pass: E_bar(x) = c lam_v gathered back onto the grid with the
+// cloud-in-cell weights, (1-a) to column ia and a to ia + 1, as order-free
+// integer sums, per block in LDS and then one global add per touched column.
+__global__ __launch_bounds__(256) void k_adj_push_dep(Geo g, const double* __restrict__ x, const int* __restrict__ id,
+                                                      const double* __restrict__ lam_v, double c,
+                                                      const unsigned* __restrict__ key, int S, int P,
+                                                      unsigned long long* __restrict__ acc)
 {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nx; i += gridDim.x * blockDim.x) {
-        mu[i] = w * E[i] + mu_dep[i];
-        mu_dep[i] = 0.0;
+    extern __shared__ __align__(16) unsigned char smem[];
+    unsigned long long* sacc = reinterpret_cast<unsigned long long*>(smem);
+    const int nx = g.nx;
+    for (int i = threadIdx.x; i < 2 * nx; i += blockDim.x) sacc[i] = 0ull;
+    __syncthreads();
+    const int shift = dep_shift(*key, P);
+    const int per = blockDim.x * 8;
+    const int base = blockIdx.x * per;
+    for (int k = base + threadIdx.x; k < min(base + per, g.n); k += blockDim.x) {
+        const int l = id ? id[k] : k;
+        const double Eb = c * lam_v[l];
+        const double s = x[k] * g.inv_dx - 0.5;
+        const double fs = floor(s);
+        const double a = s - fs;
+        const int ia = wrap_pow2((int)fs, nx);
+        const int ib = wrap_pow2(ia + 1, nx);
+        dep_add(sacc, nx, ia, (1.0 - a) * Eb, S, shift);
+        dep_add(sacc, nx, ib, a * Eb, S, shift);
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2 * nx; i += blockDim.x)
+        if (sacc[i]) atomicAdd(&acc[i], sacc[i]);
+}
+
+// mu = w E + E_bar (w = 2 dx dt for a step that enters J; E may be null),
+// with E_bar converted from its integer sums; the sums and the key are
+// cleared for the next step.  One block.
+__global__ __launch_bounds__(1024) void k_adj_mu(int nx, const double* __restrict__ E, double w, unsigned* key, int S,
+                                                 int P, unsigned long long* __restrict__ acc, double* __restrict__ mu)
+{
+    const int shift = dep_shift(*key, P);
+    __syncthreads();
+    if (threadIdx.x == 0) *key = 0u;
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+        const long long H = (long long)acc[i], Lo = (long long)acc[nx + i];
+        const double dep = ldexp((double)H, S - shift) + ldexp((double)Lo, -shift);
+        mu[i] = (E ? w * E[i] : 0.0) + dep;
+        acc[i] = 0ull;
+        acc[nx + i] = 0ull;
+    }
+}
+
+__global__ void k_adj_clear(unsigned long long* __restrict__ acc, int nx, unsigned* __restrict__ key)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 2 * nx; i += gridDim.x * blockDim.x) acc[i] = 0ull;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *key = 0u;
+}
+
+__global__ void k_fill_f64(double* __restrict__ p, int n, double value)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = value;
+}
+
+__global__ void k_scale_f64(double* __restrict__ p, int n, double s)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] *= s;
 }
 
 static int grid_for(int n, int per) { return max(1, min((n + per - 1) / per, 8192)); }
@@ -138,36 +228,64 @@ hipError_t launch_iota(int* id, int n, hipStream_t st)
 }
 
 hipError_t launch_adj_deposit(const Geo& g, int grid_prec, const double* x, const double* v, const int* id,
-                              const double* f_by_id, const void* fg, const void* Dg, const double* Pmu, double* lam_x,
-                              double* lam_v, double* f_bar, int with_positions, hipStream_t st)
+                              const double* f_by_id, const void* fg, const void* Dg, const double* R, double rscale,
+                              double* lam_x, double* lam_v, double* f_bar, int with_positions, hipStream_t st)
 {
     if (g.n == 0) return hipSuccess;
     const dim3 gr(grid_for(g.n, 256)), bl(256);
     if (grid_prec == 0)
         hipLaunchKernelGGL(k_adj_deposit<double>, gr, bl, 0, st, g, x, v, id, f_by_id, (const double*)fg,
-                           (const double*)Dg, Pmu, lam_x, lam_v, f_bar, with_positions);
+                           (const double*)Dg, R, rscale, lam_x, lam_v, f_bar, with_positions);
     else
         hipLaunchKernelGGL(k_adj_deposit<float>, gr, bl, 0, st, g, x, v, id, f_by_id, (const float*)fg,
-                           (const float*)Dg, Pmu, lam_x, lam_v, f_bar, with_positions);
+                           (const float*)Dg, R, rscale, lam_x, lam_v, f_bar, with_positions);
     return hipGetLastError();
 }
 
-hipError_t launch_adj_push(const Geo& g, const double* x, const int* id, const double* E, double c, double* lam_x,
-                           double* lam_v, double* mu_dep, hipStream_t st)
+// acc: 2 nx unsigned 64-bit sums, key: one unsigned, both zero on entry (the
+// clear below, then k_adj_mu leaves them zero).
+hipError_t launch_adj_push(const Geo& g, const double* x, const int* id, const double* E, double c,
+                           const double* lam_x_in, const double* lam_v_in, double* lam_x, double* lam_v,
+                           unsigned long long* acc, unsigned* key, hipStream_t st)
 {
     if (g.n == 0) return hipSuccess;
-    const size_t smem = sizeof(double) * g.nx;
+    const DepScale d = dep_scale(g.n);
+    hipLaunchKernelGGL(k_adj_push_lam, dim3(grid_for(g.n, 256)), dim3(256), 0, st, g, x, id, E, c, lam_x_in, lam_v_in,
+                       lam_x, lam_v, key);
+    const size_t smem = sizeof(unsigned long long) * 2 * (size_t)g.nx;
     static int granted = 0;
-    hipError_t e = ensure_lds((const void*)k_adj_push, smem, granted);
+    hipError_t e = ensure_lds((const void*)k_adj_push_dep, smem, granted);
     if (e != hipSuccess) return e;
     const int blocks = (g.n + 256 * 8 - 1) / (256 * 8);
-    hipLaunchKernelGGL(k_adj_push, dim3(blocks), dim3(256), smem, st, g, x, id, E, c, lam_x, lam_v, mu_dep);
+    hipLaunchKernelGGL(k_adj_push_dep, dim3(blocks), dim3(256), smem, st, g, x, id, lam_v, c, key, d.S, d.P, acc);
     return hipGetLastError();
 }
 
-hipError_t launch_adj_mu(int nx, const double* E, double w, double* mu_dep, double* mu, hipStream_t st)
+hipError_t launch_adj_mu(const Geo& g, const double* E, double w, unsigned long long* acc, unsigned* key, double* mu,
+                         hipStream_t st)
 {
-    hipLaunchKernelGGL(k_adj_mu, dim3(grid_for(nx, 256)), dim3(256), 0, st, nx, E, w, mu_dep, mu);
+    const DepScale d = dep_scale(g.n);
+    hipLaunchKernelGGL(k_adj_mu, dim3(1), dim3(1024), 0, st, g.nx, E, w, key, d.S, d.P, acc, mu);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_clear(int nx, unsigned long long* acc, unsigned* key, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_adj_clear, dim3(grid_for(2 * nx, 256)), dim3(256), 0, st, acc, nx, key);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double* p, int n, double value, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_f64(double* p, int n, double s, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scale_f64, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, s);
     return hipGetLastError();
 }
 

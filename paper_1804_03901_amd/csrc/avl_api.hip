@@ -42,11 +42,16 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t st)
 size_t recon3_scratch_bytes(const Geo& g);
 hipError_t launch_iota(int* id, int n, hipStream_t st);
 hipError_t launch_adj_deposit(const Geo& g, int grid_prec, const double* x, const double* v, const int* id,
-                              const double* f_by_id, const void* fg, const void* Dg, const double* Pmu, double* lam_x,
-                              double* lam_v, double* f_bar, int with_positions, hipStream_t st);
-hipError_t launch_adj_push(const Geo& g, const double* x, const int* id, const double* E, double c, double* lam_x,
-                           double* lam_v, double* mu_dep, hipStream_t st);
-hipError_t launch_adj_mu(int nx, const double* E, double w, double* mu_dep, double* mu, hipStream_t st);
+                              const double* f_by_id, const void* fg, const void* Dg, const double* R, double rscale,
+                              double* lam_x, double* lam_v, double* f_bar, int with_positions, hipStream_t st);
+hipError_t launch_adj_push(const Geo& g, const double* x, const int* id, const double* E, double c,
+                           const double* lam_x_in, const double* lam_v_in, double* lam_x, double* lam_v,
+                           unsigned long long* acc, unsigned* key, hipStream_t st);
+hipError_t launch_adj_mu(const Geo& g, const double* E, double w, unsigned long long* acc, unsigned* key, double* mu,
+                         hipStream_t st);
+hipError_t launch_adj_clear(int nx, unsigned long long* acc, unsigned* key, hipStream_t st);
+hipError_t launch_fill_f64(double* p, int n, double value, hipStream_t st);
+hipError_t launch_scale_f64(double* p, int n, double s, hipStream_t st);
 int sort_blocks(const Geo& g, int phase);
 size_t sort_lds(const Geo& g);
 int scatter_blocks_per_cu(const Geo& g);
@@ -74,7 +79,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
     size_t markers[2], counts, offsets[2], tfirst[2], tile_sums, fgrid, rho_part, rho_slices, rho, E, tw, green, rows, diag, ctr, flags, bad,
-        scratch3, diag_part, total;
+        scratch3, diag_part, adj, total;
 };
 
 int ilog2(int v)
@@ -245,6 +250,8 @@ void make_layout(const avl_config* c, const Geo& g, Layout* L)
     L->bad = take(sizeof(int));
     L->scratch3 = take(g.vdim == 3 ? recon3_scratch_bytes(g) : 0);
     L->diag_part = take(sizeof(double) * 4 * (size_t)g.nx * diag_chunks(g));
+    // reverse runs: integer sums of the field adjoint (2 nx), their bound key
+    L->adj = take(sizeof(unsigned long long) * 2 * (size_t)g.nx + 256);
     L->total = off;
 }
 
@@ -1327,7 +1334,7 @@ namespace {
 struct AdjLayout {
     size_t cp, cp_stride, cp_ids, cp_E, mbytes;
     size_t seg, seg_stride, st_x, st_v, st_id, st_fg, st_D, st_E;
-    size_t ids[2], lam_x, lam_v, f_bar, f_by_id, f_tmp, Pmu, mu, mu_dep, diag, total;
+    size_t ids[2], lam_x, lam_v, f_bar, f_by_id, f_tmp, Pmu, mu, diag, total;
     int nseg;
 };
 
@@ -1368,7 +1375,6 @@ bool adj_layout(const avl_config* c, const Geo& g, int32_t nsteps, int32_t every
     A->f_tmp = take(8 * n);
     A->Pmu = take(8 * nx);
     A->mu = take(8 * nx);
-    A->mu_dep = take(8 * nx);
     A->diag = take(16 * (size_t)nsteps);
     A->total = o;
     return true;
@@ -1465,8 +1471,9 @@ int avl_adjoint(avl_handle* h, const double* x, const double* v, const double* f
     double* f_tmp = (double*)(R + A.f_tmp);
     double* Pmu = (double*)(R + A.Pmu);
     double* mu = (double*)(R + A.mu);
-    double* mu_dep = (double*)(R + A.mu_dep);
     double* diag = (double*)(R + A.diag);
+    unsigned long long* acc = (unsigned long long*)(h->ws + h->lay.adj);
+    unsigned* key = (unsigned*)(h->ws + h->lay.adj + sizeof(unsigned long long) * 2 * (size_t)h->g.nx);
     auto state = [&](int q) { return R + A.seg + A.seg_stride * (size_t)q; };
     auto ckpt = [&](int k) { return R + A.cp + A.cp_stride * (size_t)k; };
     const double dxdt2 = 2.0 * g.dx * g.dt;
@@ -1516,10 +1523,10 @@ int avl_adjoint(avl_handle* h, const double* x, const double* v, const double* f
     hipError_t e = hipMemsetAsync(lam_x, 0, 8 * (size_t)g.np, h->st);
     if (e == hipSuccess) e = hipMemsetAsync(lam_v, 0, 8 * (size_t)g.np, h->st);
     if (e == hipSuccess) e = hipMemsetAsync(f_bar, 0, 8 * (size_t)g.np, h->st);
-    if (e == hipSuccess) e = hipMemsetAsync(mu_dep, 0, 8 * (size_t)g.nx, h->st);
+    if (e == hipSuccess) e = launch_adj_clear(g.nx, acc, key, h->st);
     if (e != hipSuccess) return done(report(e, "adjoint clear", __LINE__));
     // mu^N = 2 dx dt E^N
-    if (launch_adj_mu(g.nx, h->E, dxdt2, mu_dep, mu, h->st) != hipSuccess) return done(AVL_EDEVICE);
+    if (launch_adj_mu(g, h->E, dxdt2, acc, key, mu, h->st) != hipSuccess) return done(AVL_EDEVICE);
     const double c_full = g.qm * g.dt;
     for (int k = A.nseg - 1; k >= 0; --k) {
         const int s0 = k * every, s1 = std::min(nsteps, s0 + every);
@@ -1546,14 +1553,14 @@ int avl_adjoint(avl_handle* h, const double* x, const double* v, const double* f
                              h->flags, h->st) != hipSuccess)
                 return done(AVL_EDEVICE);
             if (launch_adj_deposit(g, gp, (double*)(S1 + A.st_x), (double*)(S1 + A.st_v), (int*)(S1 + A.st_id),
-                                   f_by_id, S1 + A.st_fg, S1 + A.st_D, Pmu, lam_x, lam_v, f_bar, 1, h->st) !=
+                                   f_by_id, S1 + A.st_fg, S1 + A.st_D, Pmu, -1.0, lam_x, lam_v, f_bar, 1, h->st) !=
                 hipSuccess)
                 return done(AVL_EDEVICE);
             const double kick = (step == 0 && h->cfg.first_kick) ? 0.5 : 1.0;
             if (launch_adj_push(g, (double*)(S0 + A.st_x), (int*)(S0 + A.st_id), (double*)(S0 + A.st_E),
-                                c_full * kick, lam_x, lam_v, mu_dep, h->st) != hipSuccess)
+                                c_full * kick, lam_x, lam_v, lam_x, lam_v, acc, key, h->st) != hipSuccess)
                 return done(AVL_EDEVICE);
-            if (launch_adj_mu(g.nx, (double*)(S0 + A.st_E), step >= 1 ? dxdt2 : 0.0, mu_dep, mu, h->st) != hipSuccess)
+            if (launch_adj_mu(g, (double*)(S0 + A.st_E), step >= 1 ? dxdt2 : 0.0, acc, key, mu, h->st) != hipSuccess)
                 return done(AVL_EDEVICE);
         }
         if (k == 0) {
@@ -1563,7 +1570,7 @@ int avl_adjoint(avl_handle* h, const double* x, const double* v, const double* f
                              h->flags, h->st) != hipSuccess)
                 return done(AVL_EDEVICE);
             if (launch_adj_deposit(g, gp, (double*)(S0 + A.st_x), (double*)(S0 + A.st_v), (int*)(S0 + A.st_id),
-                                   f_by_id, S0 + A.st_fg, S0 + A.st_D, Pmu, lam_x, lam_v, f_bar, 0, h->st) !=
+                                   f_by_id, S0 + A.st_fg, S0 + A.st_D, Pmu, -1.0, lam_x, lam_v, f_bar, 0, h->st) !=
                 hipSuccess)
                 return done(AVL_EDEVICE);
         }
@@ -1575,6 +1582,64 @@ int avl_adjoint(avl_handle* h, const double* x, const double* v, const double* f
     // field and f are current for that state
     h->have_rho = h->partials = false;
     return done(AVL_OK);
+}
+
+int avl_adjoint_deposit(avl_handle* h, const double* x, const double* v, const double* f, const void* f_grid,
+                        const void* D_grid, const double* rho_bar, double* f_bar, double* lam_x, double* lam_v)
+{
+    if (!h) return AVL_EINVAL;
+    if (h->g.vdim != 1) return AVL_ENOTSUP;
+    const Geo& g = h->g;
+    if (!f_grid || !D_grid || !rho_bar) return AVL_EINVAL;
+    if (g.n > 0 && (!x || !v || !f || !f_bar)) return AVL_EINVAL;
+    if ((lam_x == nullptr) != (lam_v == nullptr)) return AVL_EINVAL;
+    const uintptr_t gal = g.prec == AVL_FP64 ? 7 : 3;
+    if (((uintptr_t)x | (uintptr_t)v | (uintptr_t)f | (uintptr_t)rho_bar | (uintptr_t)f_bar | (uintptr_t)lam_x |
+         (uintptr_t)lam_v) & 7)
+        return AVL_EALIGN;
+    if (((uintptr_t)f_grid | (uintptr_t)D_grid) & gal) return AVL_EALIGN;
+    if (h->timing) return AVL_ESTATE;
+    AVL_TRY(launch_fill_f64(f_bar, g.n, 0.0, h->st));
+    if (lam_x) {
+        AVL_TRY(launch_fill_f64(lam_x, g.n, 0.0, h->st));
+        AVL_TRY(launch_fill_f64(lam_v, g.n, 0.0, h->st));
+    }
+    AVL_TRY(launch_adj_deposit(g, g.prec, x, v, nullptr, f, f_grid, D_grid, rho_bar, 1.0, lam_x, lam_v, f_bar,
+                               lam_x ? 1 : 0, h->st));
+    return AVL_OK;
+}
+
+int avl_adjoint_push(avl_handle* h, const double* x, const double* E, double kick, const double* lam_x_in,
+                     const double* lam_v_in, double* lam_x, double* lam_v, double* E_bar)
+{
+    if (!h) return AVL_EINVAL;
+    if (h->g.vdim != 1) return AVL_ENOTSUP;
+    const Geo& g = h->g;
+    if (!E || !E_bar || !std::isfinite(kick)) return AVL_EINVAL;
+    if (g.n > 0 && (!x || !lam_x_in || !lam_v_in || !lam_x || !lam_v)) return AVL_EINVAL;
+    if (((uintptr_t)x | (uintptr_t)E | (uintptr_t)lam_x_in | (uintptr_t)lam_v_in | (uintptr_t)lam_x |
+         (uintptr_t)lam_v | (uintptr_t)E_bar) & 7)
+        return AVL_EALIGN;
+    if (h->timing) return AVL_ESTATE;
+    unsigned long long* acc = (unsigned long long*)(h->ws + h->lay.adj);
+    unsigned* key = (unsigned*)(h->ws + h->lay.adj + sizeof(unsigned long long) * 2 * (size_t)g.nx);
+    AVL_TRY(launch_adj_clear(g.nx, acc, key, h->st));
+    AVL_TRY(launch_adj_push(g, x, nullptr, E, g.qm * g.dt * kick, lam_x_in, lam_v_in, lam_x, lam_v, acc, key, h->st));
+    AVL_TRY(launch_adj_mu(g, nullptr, 0.0, acc, key, E_bar, h->st));
+    return AVL_OK;
+}
+
+int avl_adjoint_field(avl_handle* h, const double* mu, double* rho_bar)
+{
+    if (!h || !mu || !rho_bar) return AVL_EINVAL;
+    if (((uintptr_t)mu | (uintptr_t)rho_bar) & 7) return AVL_EALIGN;
+    if (mu == rho_bar) return AVL_EINVAL;
+    if (h->timing) return AVL_ESTATE;
+    const Geo& g = h->g;
+    AVL_TRY(launch_field(g, nullptr, mu, h->rho_slices, h->rho, rho_bar, h->tw, h->green, h->diag, h->ctr, 0, nullptr,
+                         h->flags, h->st));
+    AVL_TRY(launch_scale_f64(rho_bar, g.nx, -1.0, h->st));
+    return AVL_OK;
 }
 
 }  // extern "C"
