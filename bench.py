@@ -110,11 +110,17 @@ def run_form(avl, inputs, w, x, v, f, form, steps, warmup):
     return ms / steps, ms_graph / steps, kt
 
 
-RECON_SOURCES = ("paper_1804_03901_amd/csrc/avl_recon.hip", "paper_1804_03901_amd/csrc/avl_device.h")
-TRAFFIC_SUMMARY = "profiles/hbm_traffic_bump_on_tail_16M.txt"
+# per workload: the PMC traffic summary and the sources of the reconstruction
+# kernel its counters belong to
+TRAFFIC = {
+    "bump_on_tail": ("profiles/hbm_traffic_bump_on_tail_16M.txt",
+                     ("paper_1804_03901_amd/csrc/avl_recon.hip", "paper_1804_03901_amd/csrc/avl_device.h")),
+    "two_stream_3v": ("profiles/hbm_traffic_two_stream_3v_537M.txt",
+                      ("paper_1804_03901_amd/csrc/avl_recon3.hip", "paper_1804_03901_amd/csrc/avl_device.h")),
+}
 
 
-def source_digest(paths=RECON_SOURCES):
+def source_digest(paths):
     """sha256 over the sources that define the reconstruction kernel."""
     import hashlib
     h = hashlib.sha256()
@@ -124,12 +130,15 @@ def source_digest(paths=RECON_SOURCES):
     return h.hexdigest()
 
 
-def measured_traffic(kernel_tag):
+def measured_traffic(workload, kernel_tag):
     """HBM bytes per launch of the reconstruction from the committed PMC
     summary (FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel
     calibration), or None when the kernel sources changed since the counters
     were taken or no summary exists."""
-    path = os.path.join(ROOT, TRAFFIC_SUMMARY)
+    if workload not in TRAFFIC:
+        return None
+    rel, sources = TRAFFIC[workload]
+    path = os.path.join(ROOT, rel)
     if not os.path.exists(path):
         return None
     digest = None
@@ -140,7 +149,7 @@ def measured_traffic(kernel_tag):
         elif line.startswith("traffic "):
             _, tag, fetch, write = line.split()[:4]
             rows[tag] = (float(fetch), float(write))
-    if digest != source_digest() or kernel_tag not in rows:
+    if digest != source_digest(sources) or kernel_tag not in rows:
         return None
     return rows[kernel_tag][0] + rows[kernel_tag][1]
 
@@ -321,7 +330,8 @@ def main():
         "config": {"workload": w.name, "markers": w.n_markers, "nx": w.nx, "nv": list(w.nv[: w.vdim]), "ppc": w.ppc,
                    "form": main_form, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None if three_v else measured_traffic(f"recon_{main_form}"),
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.workload, f"{'recon3' if three_v else 'recon'}_{main_form}"),
                      "traffic_unit": "bytes per launch (PMC, calibrated)", "kernel": recon_kernel,
                      "bytes_per_launch": rk["bytes_per_launch"], "ms_per_launch": rk["ms_avg"]},
         "timing": "value: HIP-graph replay of the step, events around the whole timed region; kernels: a "
@@ -332,6 +342,9 @@ def main():
                       "ms_per_step_direct": r[0], "marker_steps_per_s_direct": w.n_markers / (r[0] * 1e-3),
                       "kernels": r[2]} for k, r in results.items()},
     }
+    for k in results:
+        t = measured_traffic(args.workload, f"{'recon3' if three_v else 'recon'}_{k}")
+        out["forms"][k]["kernels"]["reconstruct"]["traffic"] = t
     # the paper's own throughput figure (Sec. Performance and Parallelization), quoted with its
     # hardware: context next to the measured rate, not a target (its workload is not stated)
     out["paper_figure"] = {"value": PAPER_RATE_PER_CORE, "unit": "marker-steps/s per core",

@@ -177,21 +177,30 @@ def test_3v_magnetised_step_matches_oracle(graph):
     assert np.max(np.abs(vo[1:] - v[1:])) > 1e-3
 
 
-def test_full_size_two_stream_3v_sampled_planes():
+@pytest.mark.parametrize("precision", [avl.AVL_FP32, avl.AVL_FP64])
+def test_full_size_two_stream_3v_sampled_planes(precision):
     """The 1D-3V benchmark workload at full size (nx = 512, 64^3 velocity
-    cells, 4 markers per cell: 536,870,912 markers, FP32 form), stepped as a
-    replayed graph as the benchmark does.  One step from the exported state is
-    checked on sampled target (vy, vz) planes -- two corners of the velocity
-    grid and an interior plane -- against the oracle's push and reconstruction
-    of the markers whose clouds reach those planes (selected from the exported
-    state by their own vy, vz; without a magnetic field the push keeps both),
-    at the FP32 form's bounds (1e-5 on f, 1e-6 on D, normwise per plane)."""
+    cells, 4 markers per cell: 536,870,912 markers), in the FP32 form and in
+    FP64, stepped as a replayed graph as the benchmark does.
+
+    One step from the exported state is checked on sampled target (vy, vz)
+    planes -- two corners of the velocity grid and an interior plane --
+    against the oracle's push and reconstruction of the markers whose clouds
+    reach those planes (selected from the exported state by their own vy, vz;
+    without a magnetic field the push keeps both).  The charge density is
+    checked on sampled x columns against the oracle's reconstruction and
+    moments of every marker whose cloud reaches those columns (selected from
+    the state the step left), and the field is the oracle's solve of the
+    GPU's own rho at 1e-12 of max|E|, with W beside it.  Bounds: FP32 form 1e-5
+    on f, 1e-6 on D and rho (normwise per plane, per column set); FP64 1e-12."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
+    fp64 = precision == avl.AVL_FP64
+    tol_f, tol_D, tol_rho = (TOL64, TOL64, TOL64) if fp64 else (1e-5, 1e-6, 1e-6)
     w = inputs.two_stream_3v()
     x, v, f = inputs.markers_threaded(w)
-    print(f"[case] {w.name} prec=fp32 n={x.size}", flush=True)
-    sim = avl.Simulation(w, x, v.reshape(-1), f, precision=avl.AVL_FP32)
+    print(f"[case] {w.name} prec={precision} n={x.size}", flush=True)
+    sim = avl.Simulation(w, x, v.reshape(-1), f, precision=precision)
     del x, v, f
     sim.step(2, graph=True, diag=False)
     xt, vt, ft = sim.markers()
@@ -208,14 +217,46 @@ def test_full_size_two_stream_3v_sampled_planes():
     sim.step(1, graph=True, diag=False)
     fg, Dg = sim.reconstruct(want_D=True)
     fg, Dg = fg.reshape(w.nv[2], w.nv[1], w.nv[0], w.nx), Dg.reshape(w.nv[2], w.nv[1], w.nv[0], w.nx)
-    sim.check()
     g = oracle.Grid.from_workload(w)
     xo, vo = oracle.push(g, xs, vs, E)
     _, Do, fo = oracle.reconstruct(g, xo, vo, fs)
+    del xo, vo, xs, vs, fs
     for jy, jz in planes:
         ef = nrel(t2n(fg[jz, jy]), fo[jz, jy])
         eD = nrel(t2n(Dg[jz, jy]), Do[jz, jy])
         print(f"[result] plane (vy {jy}, vz {jz}): f {ef:.2e} D {eD:.2e}", flush=True)
-        assert ef <= 1e-5
-        assert eD <= 1e-6
+        assert ef <= tol_f
+        assert eD <= tol_D
+    del fg, Dg, fo, Do
+    # rho on sampled columns: every marker whose x cloud reaches them
+    E_g, rho_g = (t2n(a) for a in sim.field())
+    cols = [0, 137, w.nx - 1]
+    xt, vt, ft = sim.markers()
+    ix = torch.floor(xt / (w.L / w.nx) - 0.5)
+    ix = torch.where(ix < 0, ix + w.nx, ix)
+    keep = torch.zeros_like(ft, dtype=torch.bool)
+    for c in cols:
+        # one dual cell of slack each way: a marker the selection takes in
+        # excess only adds to columns that are not compared
+        for d in (-2, -1, 0, 1):
+            keep |= ix == (c + d) % w.nx
+    xs, vs, fs = t2n(xt[keep]), t2n(vt[:, keep]), t2n(ft[keep])
+    del xt, vt, ft, ix, keep
+    print(f"[case] {xs.size} markers reach the sampled columns", flush=True)
+    _, _, fo = oracle.reconstruct(g, xs, vs, fs)
+    rho_o = oracle.moments(g, fo)[0][cols]
+    del fo
+    erho = float(np.max(np.abs(rho_g[cols] - rho_o)) / np.max(np.abs(rho_o)))
+    print(f"[result] rho on columns {cols}: {erho:.2e}", flush=True)
+    assert erho <= tol_rho
+    # the field: the oracle's solve of the GPU's rho, and its energy
+    E_o, _ = oracle.poisson(w.nx, w.L, w.c_p, rho_g)
+    eE = float(np.max(np.abs(E_g - E_o)) / np.max(np.abs(E_o)))
+    _, W_g = sim.poisson(None)
+    W_g = float(t2n(W_g)[0])
+    W_o = oracle.field_energy(w.nx, w.L, w.c_p, E_o)
+    print(f"[result] E (solve of the GPU's rho) {eE:.2e} of max|E|; W {abs(W_g - W_o) / W_o:.2e}", flush=True)
+    assert eE <= TOL64
+    assert abs(W_g - W_o) <= TOL64 * W_o
+    sim.check()
     sim.close()
