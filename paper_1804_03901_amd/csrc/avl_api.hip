@@ -55,6 +55,7 @@ hipError_t launch_scale_f64(double* p, int n, double s, hipStream_t st);
 int sort_blocks(const Geo& g, int phase);
 size_t sort_lds(const Geo& g);
 int scatter_blocks_per_cu(const Geo& g);
+int scatter_step_blocks_per_cu(const Geo& g);
 int count_blocks_per_cu(const Geo& g);
 int diag_chunks(const Geo& g);
 hipError_t launch_diag(const Geo& g, const void* fgrid, const double* rho, const double* E, double mass,
@@ -182,6 +183,10 @@ int make_geo(const avl_config* c, Geo* g)
         want = std::max<int64_t>(want, 4 * (int64_t)c->nx);
         want = std::min<int64_t>(want, std::max<int64_t>(8192, 4 * (int64_t)c->nx));
         g->hist_bins = (int)want;
+        // the step's scatter (2048-marker tiles, a row or two of buckets in
+        // the dense rows) keeps three rows: a tile inside one row and its
+        // neighbours, which leaves room for five blocks per CU
+        g->sbins = (int)std::min<int64_t>(g->hist_bins, std::max<int64_t>(3 * (int64_t)c->nx, kSortTile));
     }
     // reconstruction decomposition
     if (c->vdim == 1) {
@@ -264,6 +269,7 @@ void fit_lds(Geo* g, int lds)
     int bins = (lds - fixed) / 4;
     bins = (bins >> g->lognx) << g->lognx;
     if (g->hist_bins > bins) g->hist_bins = bins;
+    if (g->sbins > g->hist_bins) g->sbins = g->hist_bins;
 }
 
 }  // namespace
@@ -685,6 +691,7 @@ int avl_init(const avl_config* cfg, void* workspace, size_t ws_bytes, void* stre
         set_lds_limit(lds);
         fit_lds(&h->g, lds);
         h->g.sblocks = scatter_blocks_per_cu(h->g) * device_cus();
+        h->g.sblocks_step = scatter_step_blocks_per_cu(h->g) * device_cus();
         h->g.cblocks = count_blocks_per_cu(h->g) * device_cus();
         if (debug_on())
             std::fprintf(stderr, "[avl] lds limit %d B, recon cap %d, hist bins %d, rc %d, chunks %d, strips %d\n", lds,
@@ -1882,6 +1889,7 @@ extern "C" int avl_reconstruct_noalloc(const avl_config* cfg, void* stream, cons
         set_lds_limit(lds);
         fit_lds(&g, lds);
         g.sblocks = scatter_blocks_per_cu(g) * device_cus();
+        g.sblocks_step = scatter_step_blocks_per_cu(g) * device_cus();
         g.cblocks = count_blocks_per_cu(g) * device_cus();
     }
     M64 m64[2];

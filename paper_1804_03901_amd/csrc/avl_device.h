@@ -52,10 +52,12 @@ struct Geo {
     int rc;              // target velocity rows per reconstruct chunk (1D-1V)
     int nchunk, nstrip;  // reconstruct chunks along v and column strips along x
     int hist_bins;       // LDS histogram bins per sort block
+    int sbins;           // LDS histogram bins of the step's scatter (FP32 1D-1V), at most hist_bins
     int cap;             // markers staged in LDS per reconstruct wave
     int jpad, jrange;    // FP32 1D-3V: x-velocity dual index stored with offset jpad, range jrange
     int kahan;           // FP32 form: compensated FP32 accumulation instead of FP64 accumulators
     int sblocks;         // blocks of the tiled scatter (FP32 1D-1V): the resident capacity; 0 = a tile per block
+    int sblocks_step;    // blocks of the step's scatter (FP32 1D-1V): its resident capacity
     int cblocks;         // blocks of the count pass: its resident capacity; 0 = a tile per block
     int magnetic;        // 1D-3V FP64 with a background magnetic field: Boris push
     double B[3];         // background magnetic field

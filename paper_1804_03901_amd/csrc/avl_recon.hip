@@ -144,6 +144,32 @@ __device__ __forceinline__ double from_left(double v)
     return __hiloint2double(hi, lo);
 }
 
+// Largest and smallest of a value over the wavefront: DPP steps within quads,
+// half rows and rows of 16 lanes, then row broadcasts, leave the result in
+// lane 63.  Lanes a step does not write take the identity (0 for the maximum,
+// all ones for the minimum).
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v)
+{
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xb1, 0xf, 0xf, false));   // quad_perm 1,0,3,2
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4e, 0xf, 0xf, false));   // quad_perm 2,3,0,1
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, false));  // row_half_mirror
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xf, 0xf, false));  // row_mirror
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+__device__ __forceinline__ unsigned wave_min_u32(unsigned v)
+{
+    v = min(v, (unsigned)__builtin_amdgcn_update_dpp(-1, (int)v, 0xb1, 0xf, 0xf, false));
+    v = min(v, (unsigned)__builtin_amdgcn_update_dpp(-1, (int)v, 0x4e, 0xf, 0xf, false));
+    v = min(v, (unsigned)__builtin_amdgcn_update_dpp(-1, (int)v, 0x141, 0xf, 0xf, false));
+    v = min(v, (unsigned)__builtin_amdgcn_update_dpp(-1, (int)v, 0x140, 0xf, 0xf, false));
+    v = min(v, (unsigned)__builtin_amdgcn_update_dpp(-1, (int)v, 0x142, 0xa, 0xf, false));
+    v = min(v, (unsigned)__builtin_amdgcn_update_dpp(-1, (int)v, 0x143, 0xc, 0xf, false));
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 __device__ __forceinline__ void wave_sync_lds()
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -457,15 +483,34 @@ __device__ __forceinline__ void recon_task(const Geo& g, const typename RT<PREC>
         const Seg seg = sg[0];
         const int beg = rb[0], end = re[0];
         const bool staged = seg.fits(MAIN);
+        // order-free bounds of the staged segment: the largest |f| and the
+        // smallest nonzero |f| (magnitude bits) over its markers; the minimum
+        // is kept as min(k - 1), which a zero key (wrapping to the largest
+        // value) cannot lower
+        unsigned smax = 0u, smin1 = ~0u;
         if (staged) {
 #pragma unroll
             for (int u = 0; u < KU / V; ++u) {
                 if (SPARSE && u * kWave * V >= seg.nmain) break;     // not loaded (wave-uniform)
                 lds.putv(g, u * kWave * V + lane * V, R[u]);
+                if constexpr (!KAHAN) {
+                    const int left = seg.nmain - (u * kWave * V + lane * V);   // markers of the vector in range
+#pragma unroll
+                    for (int q = 0; q < V; ++q) {
+                        const unsigned kf = q < left ? fix_key((T)R[u].r[q].f) : 0u;
+                        smax = max(smax, kf);
+                        smin1 = min(smin1, kf - 1u);
+                    }
+                }
             }
             // slots past the main range hold zeros from the bounded loads;
             // the wrapped run is written over them afterwards
-            if (lane < seg.wlen) lds.put(g, seg.nmain + lane, W);
+            if (lane < seg.wlen) {
+                lds.put(g, seg.nmain + lane, W);
+                const unsigned kf = fix_key((T)W.f);
+                smax = max(smax, kf);
+                smin1 = min(smin1, kf - 1u);
+            }
         }
         wave_sync_lds();
         const int p0 = staged ? ((wrapped && lane == 0) ? seg.nmain : beg - seg.lo) : beg;
@@ -505,11 +550,26 @@ __device__ __forceinline__ void recon_task(const Geo& g, const typename RT<PREC>
             // largest weight, 1, taken as f = 1): for f = c = 2^k on every
             // marker the f grid is then c times the offset grid, every N sum is
             // c times its D sum, and f = c comes out exactly
+            //
+            // A staged segment whose nonzero |f| all share one binary exponent
+            // or two (a factor below 4, as along x in a smooth distribution)
+            // takes the segment's largest |f| as every run's bound: each run's
+            // own largest |f| is at least the segment's smallest, so its grid is
+            // at most twice as coarse as its own bound would give, and the pass
+            // over the run is saved.  Otherwise each run takes its own bound.
             unsigned kmax = 0;
+            bool narrow = false;
             if (staged) {
-                for (int u = 0; u < len; ++u) kmax = max(kmax, fix_key(lds.f[p0 + u]));
-            } else {
-                for (int u = 0; u < len; ++u) kmax = max(kmax, fix_key(m.f[p0 + u]));
+                const unsigned gmax = wave_max_u32(smax), gmin = wave_min_u32(smin1) + 1u;
+                narrow = gmax == 0u || fix_exp_of_key(gmax, T()) - fix_exp_of_key(gmin, T()) <= 1;
+                if (narrow) kmax = gmax;
+            }
+            if (!narrow) {
+                if (staged) {
+                    for (int u = 0; u < len; ++u) kmax = max(kmax, fix_key(lds.f[p0 + u]));
+                } else {
+                    for (int u = 0; u < len; ++u) kmax = max(kmax, fix_key(m.f[p0 + u]));
+                }
             }
             const int emax = len > 0 ? fix_exp_of_key(kmax, T()) : -1100;
             const FixGrid gf = fix_grid(emax, len), gd = fix_grid(0, len);

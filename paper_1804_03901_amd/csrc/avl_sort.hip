@@ -281,15 +281,15 @@ __device__ __forceinline__ void tile_buckets(const Geo& g, const Prev& pv, int b
 
 // The LDS window of a sort block: bucket rows around the rows of the block's
 // first and last marker (which bound the block's rows, the input being
-// sorted), widened by one row each way, at most hist_bins buckets.
-__device__ __forceinline__ void set_window(const Geo& g, int b0, int b1, int* s_lo, int* s_nb)
+// sorted), widened by one row each way, at most maxbins buckets.
+__device__ __forceinline__ void set_window(const Geo& g, int b0, int b1, int* s_lo, int* s_nb, int maxbins)
 {
     int r0 = (b0 >= g.nb ? g.nrow - 1 : b0 >> g.lognx);
     int r1 = (b1 >= g.nb ? g.nrow - 1 : b1 >> g.lognx);
     int lo = min(r0, r1) - 1, hi = max(r0, r1) + 1;
     lo = max(lo, 0);
     hi = min(hi, g.nrow - 1);
-    int maxrows = g.hist_bins >> g.lognx;
+    int maxrows = maxbins >> g.lognx;
     if (hi - lo + 1 > maxrows) hi = lo + maxrows - 1;
     *s_lo = lo << g.lognx;
     *s_nb = (hi - lo + 1) << g.lognx;
@@ -404,7 +404,7 @@ __device__ __forceinline__ void count_tile(const Geo& g, const SortSmem<PREC>& s
         if (first + k == last) s_b[1] = grp.p[k].bucket(g);
     }
     __syncthreads();
-    if (threadIdx.x == 0) set_window(g, s_b[0], s_b[1], s_lo, s_nb);
+    if (threadIdx.x == 0) set_window(g, s_b[0], s_b[1], s_lo, s_nb, g.hist_bins);
     __syncthreads();
     const int lo = *s_lo, nbw = *s_nb;
     for (int i = threadIdx.x; i < nbw; i += blockDim.x) sm.hist[i] = 0;
@@ -546,7 +546,7 @@ __device__ __forceinline__ void scatter_tile(const Geo& g, const SortSmem<PREC>&
                                              const typename MarkersOf<PREC>::T& dst, double dtk, float bk,
                                              const int* __restrict__ offsets, int* __restrict__ counts,
                                              int base, int last, int* s_b, int* s_lo, int* s_nb, int& fl,
-                                             const Prev& pv, int ovf, int* s_aux)
+                                             const Prev& pv, int ovf, int* s_aux, int maxbins)
 {
     constexpr int K = kSortMPT;
     if constexpr (IMPL) {
@@ -568,7 +568,7 @@ __device__ __forceinline__ void scatter_tile(const Geo& g, const SortSmem<PREC>&
         if (i == last) s_b[1] = p[k].bucket(g);
     }
     __syncthreads();
-    if (threadIdx.x == 0) set_window(g, s_b[0], s_b[1], s_lo, s_nb);
+    if (threadIdx.x == 0) set_window(g, s_b[0], s_b[1], s_lo, s_nb, maxbins);
     __syncthreads();
     const int lo = *s_lo, nbw = *s_nb;
     for (int i = threadIdx.x; i < nbw; i += blockDim.x) sm.hist[i] = 0;
@@ -651,7 +651,7 @@ __device__ __forceinline__ void scatter_block(const Geo& g, const typename Marke
     load_tile<PREC, VD>(src, g, p, base, last, ovf);
     int fl = 0;
     scatter_tile<PREC, VD, PUSH, IMPL>(g, sm, p, dst, dtk, bk, offsets, counts, base, last, s_b, &s_lo, &s_nb, fl,
-                                       pv, ovf, s_aux);
+                                       pv, ovf, s_aux, g.hist_bins);
     if (fl) atomicOr(&s_flags, fl);
     __syncthreads();
     if (threadIdx.x == 0 && s_flags) atomicOr(flags, s_flags);
@@ -674,15 +674,20 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter1(Geo g, typename Marke
 // ... and loads its next tile's markers while the current one is pushed,
 // ranked, claimed and stored, so the loads of one tile overlap the latency
 // chain of the previous one; the field and drift table are staged once.
-template <int PREC, int VD, bool PUSH, bool IMPL>
-__global__ __launch_bounds__(kSortThreads) void k_scatter(Geo g, typename MarkersOf<PREC>::T src,
-                                                          typename MarkersOf<PREC>::T dst,
-                                                          const double* __restrict__ E,
-                                                          const RowShift* __restrict__ rows_g,
-                                                          double dtk, float bk,
-                                                          const int* __restrict__ offsets,
-                                                          int* __restrict__ counts, int* __restrict__ flags, Prev pv)
+// ID false: the markers carry no identities (every run but an adjoint's), so
+// the payload holds no id register (the null pointers are known at compile
+// time).
+template <int PREC, int VD, bool PUSH, bool IMPL, bool ID>
+__device__ __forceinline__ void scatter_tiled(const Geo& g, typename MarkersOf<PREC>::T src,
+                                              typename MarkersOf<PREC>::T dst, const double* __restrict__ E,
+                                              const RowShift* __restrict__ rows_g, double dtk, float bk,
+                                              const int* __restrict__ offsets, int* __restrict__ counts,
+                                              int* __restrict__ flags, const Prev& pv)
 {
+    if constexpr (!ID) {
+        src.id = nullptr;
+        dst.id = nullptr;
+    }
     extern __shared__ __align__(16) unsigned char smem[];
     SortSmem<PREC> sm(smem, g);
     __shared__ int s_b[2], s_lo, s_nb, s_flags, s_aux[kSortThreads / kWave + 1];
@@ -699,13 +704,37 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(Geo g, typename Marker
         if (tn < ntiles) load_tile<PREC, VD>(src, g, q, tn * kSortTile, min(tn * kSortTile + kSortTile, g.n) - 1, ovf);
         scatter_tile<PREC, VD, PUSH, IMPL>(g, sm, p, dst, dtk, bk, offsets, counts, t * kSortTile,
                                            min(t * kSortTile + kSortTile, g.n) - 1, s_b, &s_lo, &s_nb, fl, pv, ovf,
-                                           s_aux);
+                                           s_aux, g.sbins);
 #pragma unroll
         for (int k = 0; k < kSortMPT; ++k) p[k] = q[k];
     }
     if (fl) atomicOr(&s_flags, fl);
     __syncthreads();
     if (threadIdx.x == 0 && s_flags) atomicOr(flags, s_flags);
+}
+
+template <int PREC, int VD, bool PUSH, bool IMPL>
+__global__ __launch_bounds__(kSortThreads) void k_scatter(Geo g, typename MarkersOf<PREC>::T src,
+                                                          typename MarkersOf<PREC>::T dst,
+                                                          const double* __restrict__ E,
+                                                          const RowShift* __restrict__ rows_g,
+                                                          double dtk, float bk,
+                                                          const int* __restrict__ offsets,
+                                                          int* __restrict__ counts, int* __restrict__ flags, Prev pv)
+{
+    scatter_tiled<PREC, VD, PUSH, IMPL, true>(g, src, dst, E, rows_g, dtk, bk, offsets, counts, flags, pv);
+}
+
+// The step's scatter (push, implied cells, no identities), fitted to five
+// waves per SIMD: with the smaller scatter window its LDS admits five blocks
+// per CU, and the registers are held to match.
+template <int PREC, int VD>
+__global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(5)))
+void k_scatter_step(Geo g, typename MarkersOf<PREC>::T src, typename MarkersOf<PREC>::T dst,
+                    const double* __restrict__ E, const RowShift* __restrict__ rows_g, double dtk, float bk,
+                    const int* __restrict__ offsets, int* __restrict__ counts, int* __restrict__ flags, Prev pv)
+{
+    scatter_tiled<PREC, VD, true, true, false>(g, src, dst, E, rows_g, dtk, bk, offsets, counts, flags, pv);
 }
 
 // ---------------------------------------------------------------------------
@@ -881,6 +910,15 @@ static size_t sort_smem(const Geo& g, bool push)
     return ((e + r + 15) & ~(size_t)15) + sizeof(int) * bins;
 }
 
+// LDS of the step's scatter (FP32 1D-1V): a window of at most sbins buckets,
+// and a scatter tile's implied buckets.
+static size_t scatter_step_smem(const Geo& g)
+{
+    size_t e = sizeof(float2) * g.nx;
+    size_t r = sizeof(RowShift) * (g.nv[0] + 1);
+    return ((e + r + 15) & ~(size_t)15) + sizeof(int) * std::max(g.sbins, kSortTile);
+}
+
 template <int PREC, int VD>
 static hipError_t launch_sort_t(const Geo& g, void* src, void* dst, const double* E, const RowShift* rows,
                                 double dtk, float bk, int* counts, int* offsets, int* tile_sums, int* tile_next,
@@ -957,7 +995,14 @@ static hipError_t launch_sort_t(const Geo& g, void* src, void* dst, const double
         if constexpr (tiled) {
             const dim3 gr(sblocks);
             if (impl) {
-                if (push) launch(k_scatter<PREC, VD, true, true>, gr, bl, smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags, pv);
+                if (push && !s.id) {
+                    static int granted_step = 0;
+                    const size_t sm_step = scatter_step_smem(g);
+                    hipError_t e = ensure_lds((const void*)k_scatter_step<PREC, VD>, sm_step, granted_step);
+                    if (e != hipSuccess) return e;
+                    launch(k_scatter_step<PREC, VD>, dim3(g.sblocks_step > 0 ? std::min(stiles, g.sblocks_step) : stiles),
+                           bl, sm_step, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags, pv);
+                } else if (push) launch(k_scatter<PREC, VD, true, true>, gr, bl, smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags, pv);
                 else launch(k_scatter<PREC, VD, false, true>, gr, bl, smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags, pv);
             } else {
                 if (push) launch(k_scatter<PREC, VD, true, false>, gr, bl, smem, st, g, s, d, E, rows, dtk, bk, offsets, counts, flags, pv);
@@ -1053,6 +1098,22 @@ int count_blocks_per_cu(const Geo& g)
         per_cu <= 0) {
         (void)hipGetLastError();
         per_cu = 0;
+    }
+    return per_cu;
+}
+
+int scatter_step_blocks_per_cu(const Geo& g)
+{
+    if (!(g.prec == 1 && g.vdim == 1)) return 0;
+    const size_t smem = scatter_step_smem(g);
+    static int granted = 0;
+    int per_cu = 0;
+    if (ensure_lds((const void*)k_scatter_step<1, 1>, smem, granted) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_scatter_step<1, 1>, kSortThreads,
+                                                     smem) != hipSuccess ||
+        per_cu <= 0) {
+        (void)hipGetLastError();
+        per_cu = 4;
     }
     return per_cu;
 }
