@@ -263,19 +263,22 @@ def test_set_markers_resume():
     assert torch.equal(Ea, Eb) and torch.equal(rho_a, rho_b)
 
 
-@pytest.mark.parametrize("precision,options", [(avl.AVL_FP64, 0), (avl.AVL_FP32, 0),
-                                               (avl.AVL_FP32, avl.AVL_OPT_KAHAN32)])
-def test_full_size_bump_on_tail_step(precision, options):
+@pytest.mark.parametrize("precision,options,weights", [(avl.AVL_FP64, 0, "analytic"), (avl.AVL_FP32, 0, "analytic"),
+                                                       (avl.AVL_FP32, avl.AVL_OPT_KAHAN32, "analytic"),
+                                                       (avl.AVL_FP32, 0, "logu"),
+                                                       (avl.AVL_FP32, avl.AVL_OPT_KAHAN32, "logu")])
+def test_full_size_bump_on_tail_step(precision, options, weights):
     """The benchmark workload at full size (1024 x 1024 cells, 16 markers per
     cell, 16.8M markers), stepped as a replayed graph as the benchmark does:
     one step from the exported state against the oracle (FP64 path 1e-12,
     FP32 form, with FP64 or compensated FP32 sums, 1e-5 on f and 1e-6 on rho;
-    the field at its own scale as everywhere)."""
-    w = inputs.bump_on_tail()
+    the field at its own scale as everywhere).  Also with the configuration's
+    log-uniform marker weights (1e-8 .. 1), the reconstruction's stress case."""
+    w = inputs.bump_on_tail().replace(weights=weights)
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     x0, v0, f0 = inputs.markers(w)
-    print(f"[case] {w.name} prec={precision} options={options} n={x0.size}", flush=True)
+    print(f"[case] {w.name} prec={precision} options={options} weights={weights} n={x0.size}", flush=True)
     sim = avl.Simulation(w, x0, v0.reshape(-1), f0, precision=precision, options=options)
     del x0, v0, f0
     tol_f, tol_r = (TOL64, TOL64) if precision == avl.AVL_FP64 else (1e-5, 1e-6)
@@ -290,7 +293,7 @@ def test_full_size_bump_on_tail_step(precision, options):
     sim.check()
     r = check_field(w, t2n(rho_g), t2n(E_g), rho_o, E_o, W_g=W_g, label=f"full size {precision}")
     cell = cell_rel(t2n(fg), fo, Do)
-    print(f"[result] {precision} options={options}: f {nrel(t2n(fg), fo):.2e} cell {cell:.2e} D {nrel(t2n(Dg), Do):.2e} "
+    print(f"[result] {precision} options={options} weights={weights}: f {nrel(t2n(fg), fo):.2e} cell {cell:.2e} D {nrel(t2n(Dg), Do):.2e} "
           f"rho {nrel(t2n(rho_g), rho_o):.2e} E {r['E']:.2e} (bound {r['E_bound']:.2e}, solve {r['E_solve']:.2e}) "
           f"W {r['W']:.2e}", flush=True)
     assert nrel(t2n(fg), fo) <= tol_f
