@@ -186,6 +186,39 @@ def run_batched(avl, inputs, steps, warmup, count):
     return out
 
 
+def run_adjoint(avl, inputs, every=50):
+    """The adjoint configuration: bump-on-tail at nx = 1024, nv = 512, 8
+    markers per cell (4,194,304 markers), 500 steps, FP32 forward with a
+    checkpoint every 50 steps; the time of one whole gradient (forward with
+    checkpoints, segment recomputation, reverse sweep) against the time of the
+    plain 500-step forward run."""
+    import torch
+    from paper_1804_03901_amd import adjoint
+    w = inputs.adjoint_case()
+    x, v, f = inputs.markers_threaded(w)
+    dev = torch.device("cuda:0")
+    xt = torch.tensor(x, device=dev)
+    vt = torch.tensor(v.reshape(-1), device=dev)
+    ft = torch.tensor(f, device=dev)
+    sim = avl.Simulation(w, xt, vt, ft, precision=avl.AVL_FP32)
+    adjoint.energy_and_gradient(sim, xt, vt, ft, w.steps, every=every)      # warm-up (workspace, code)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    J, grad = adjoint.energy_and_gradient(sim, xt, vt, ft, w.steps, every=every)
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t
+    t = time.perf_counter()
+    adjoint.energy_and_gradient(sim, xt, vt, ft, w.steps, want_grad=False)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t
+    sim.check()
+    sim.close()
+    return {"workload": w.name, "markers": w.n_markers, "steps": w.steps, "checkpoint_every": every, "form": "fp32",
+            "seconds_gradient": t_grad, "seconds_forward": t_fwd, "gradient_over_forward": t_grad / t_fwd,
+            "J": float(J), "grad_l2": float(torch.linalg.vector_norm(grad)),
+            "timing": "host clock around one call, device synchronised on both sides"}
+
+
 def cpu_baseline(inputs, w, x, v, f, steps):
     import oracle
     g = oracle.Grid.from_workload(w)
@@ -277,6 +310,8 @@ def main():
     ap.add_argument("--workload", default="bump_on_tail", choices=["bump_on_tail", "two_stream_3v"],
                     help="two_stream_3v: the 1D-3V two-stream case, 512 x 64^3 cells, 4 markers per cell")
     ap.add_argument("--no-probe", action="store_true")
+    ap.add_argument("--adjoint", default=True, action=argparse.BooleanOptionalAction,
+                    help="time one gradient of the adjoint configuration (default on)")
     ap.add_argument("--batch", type=int, default=64, help="instances of the batched parameter scan (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--cpu-cores", type=int, default=16,
@@ -363,6 +398,11 @@ def main():
                            "source": "Sec. Performance and Parallelization", "workload": "not stated"}
     if "fp32" in results and "fp64" in results:
         out["fp32_speedup_over_fp64"] = results["fp64"][1] / results["fp32"][1]
+    if args.adjoint and not three_v:
+        log("adjoint: 4.2M markers, 500 steps, FP32 forward, checkpoint every 50")
+        out["adjoint"] = run_adjoint(avl, inputs)
+        log(f"adjoint: {out['adjoint']['seconds_gradient']:.3f} s a gradient, "
+            f"{out['adjoint']['gradient_over_forward']:.2f}x the forward run")
     if args.batch and not three_v:
         log(f"batched scan: {args.batch} instances, warmup {args.warmup}, timed {args.batch_steps}")
         out["batched"] = run_batched(avl, inputs, args.batch_steps, args.warmup, args.batch)

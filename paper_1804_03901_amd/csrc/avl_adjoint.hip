@@ -26,6 +26,8 @@
 // markers), so recorded states can be visited in any order; the gathered
 // field adjoint is summed as integers (order-free), so the gradient is the
 // same bit for bit from run to run.
+#include <algorithm>
+
 #include "avl_device.h"
 
 namespace avl {
@@ -148,8 +150,17 @@ __global__ __launch_bounds__(256) void k_adj_push_lam(Geo g, const double* __res
         lam_v[l] = lvt;
         kmax = max(kmax, fix_key(c * lvt));
     }
+    // one atomic per block: the launch has a few blocks per CU, so the
+    // single address sees a few thousand updates rather than one per wave
+    __shared__ unsigned s_max[256 / kWave];
     for (int off = kWave / 2; off > 0; off >>= 1) kmax = max(kmax, (unsigned)__shfl_xor((int)kmax, off));
-    if ((threadIdx.x & (kWave - 1)) == 0 && kmax) atomicMax(key, kmax);
+    if ((threadIdx.x & (kWave - 1)) == 0) s_max[threadIdx.x / kWave] = kmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned m = 0u;
+        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) m = max(m, s_max[w]);
+        if (m) atomicMax(key, m);
+    }
 }
 
 // Second pass: E_bar(x) = c lam_v gathered back onto the grid with the
@@ -250,8 +261,8 @@ hipError_t launch_adj_push(const Geo& g, const double* x, const int* id, const d
 {
     if (g.n == 0) return hipSuccess;
     const DepScale d = dep_scale(g.n);
-    hipLaunchKernelGGL(k_adj_push_lam, dim3(grid_for(g.n, 256)), dim3(256), 0, st, g, x, id, E, c, lam_x_in, lam_v_in,
-                       lam_x, lam_v, key);
+    hipLaunchKernelGGL(k_adj_push_lam, dim3(std::min(grid_for(g.n, 256), 1024)), dim3(256), 0, st, g, x, id, E, c,
+                       lam_x_in, lam_v_in, lam_x, lam_v, key);
     const size_t smem = sizeof(unsigned long long) * 2 * (size_t)g.nx;
     static int granted = 0;
     hipError_t e = ensure_lds((const void*)k_adj_push_dep, smem, granted);
