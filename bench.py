@@ -156,16 +156,18 @@ def measured_traffic(workload, kernel_tag):
 
 def run_batched(avl, inputs, steps, warmup, count):
     """The parameter-scan batch (uneven 1D-1V bump-on-tail instances, FP32
-    form), stepped as batched launches replayed as a HIP graph."""
+    form), stepped as batched launches replayed as a HIP graph, and beside it
+    the same instances stepped one after another, each as its own handle with
+    its own graph (the library's defaults), so that the batch's gain is
+    measured rather than assumed."""
     import torch
     from paper_1804_03901_amd import tune
     ws = inputs.batched_scan(count=count)
     mk = [inputs.markers_threaded(w) for w in ws]
-    # rows per reconstruction task for the batch, chosen by timing candidates
-    tunes, table = tune.tune_batch(ws, mk, precision=avl.AVL_FP32, candidates=(0, 6, 12, 24), steps=5, warmup=2,
-                                   cache_path=None)
+    # reconstruction rows per task and row form for the batch, chosen by timing candidates
+    tunes, tables = tune.tune_batch(ws, mk, precision=avl.AVL_FP32, candidates=(0, 6, 12, 24), forms=(1, 2),
+                                    steps=5, warmup=2, cache_path=None)
     b = avl.Batch(ws, mk, precision=avl.AVL_FP32, tunes=tunes)
-    del mk
     torch.cuda.synchronize()
     b.step(warmup, diag=False)
     t0 = torch.cuda.Event(enable_timing=True)
@@ -177,13 +179,34 @@ def run_batched(avl, inputs, steps, warmup, count):
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / steps
     b.check()
-    out = {"instances": len(ws), "markers": b.n_markers, "ms_per_step": ms,
-           "marker_steps_per_s": b.n_markers / (ms * 1e-3), "steps": steps, "form": "fp32",
-           "nx": sorted({w.nx for w in ws}), "nv": sorted({w.nv[0] for w in ws}),
-           "tuned_recon_rows": tunes[0][avl.TUNE_RECON_ROWS],
-           "tuning_ms_per_step": {str(k): v for k, v in table.items()}}
+    n_markers = b.n_markers
     b.close()
-    return out
+    # one instance at a time: the sum of the instances' own graph-replayed steps
+    one_ms = 0.0
+    for w, (x, v, f) in zip(ws, mk):
+        sim = avl.Simulation(w, x, v.reshape(-1), f, precision=avl.AVL_FP32)
+        sim.step(warmup, graph=True, diag=False)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(sim.stream)
+        sim.step(steps, graph=True, diag=False)
+        e1.record(sim.stream)
+        torch.cuda.synchronize()
+        one_ms += e0.elapsed_time(e1) / steps
+        sim.check()
+        sim.close()
+    del mk
+    names = {avl.TUNE_RECON_ROWS: "recon_rows", avl.TUNE_RECON_FORM: "recon_form"}
+    return {"instances": len(ws), "markers": n_markers, "ms_per_step": ms,
+            "marker_steps_per_s": n_markers / (ms * 1e-3), "steps": steps, "form": "fp32",
+            "nx": sorted({w.nx for w in ws}), "nv": sorted({w.nv[0] for w in ws}),
+            "tuned": {names[k]: v for k, v in tunes[0].items()},
+            "tuning_ms_per_step": {names[k]: {str(c): t for c, t in tab.items()} for k, tab in tables.items()},
+            "one_by_one": {"ms_per_step": one_ms, "marker_steps_per_s": n_markers / (one_ms * 1e-3),
+                           "batched_speedup": one_ms / ms,
+                           "timing": "each instance alone, its own graph replay, library defaults; "
+                                     "sum over the instances of their ms per step"}}
 
 
 def run_adjoint(avl, inputs, every=50):
@@ -407,7 +430,8 @@ def main():
         log(f"batched scan: {args.batch} instances, warmup {args.warmup}, timed {args.batch_steps}")
         out["batched"] = run_batched(avl, inputs, args.batch_steps, args.warmup, args.batch)
         log(f"batched scan: {out['batched']['ms_per_step']:.4f} ms/step, "
-            f"{out['batched']['marker_steps_per_s']:.3e} marker-steps/s")
+            f"{out['batched']['marker_steps_per_s']:.3e} marker-steps/s; one by one "
+            f"{out['batched']['one_by_one']['ms_per_step']:.4f} ms/step")
         if "fp64" in results:
             fp64_rate = w.n_markers / (results["fp64"][1] * 1e-3)
             out["batched"]["fp32_batched_over_fp64_plain"] = out["batched"]["marker_steps_per_s"] / fp64_rate

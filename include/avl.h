@@ -108,7 +108,14 @@ typedef struct avl_config {
     int32_t tune[4];     /* kernel tuning knobs, 0 = library default (results do not depend on
                             them beyond summation order):
                             [0] target velocity rows per 1D-1V reconstruction task, 1..256;
-                            [1]..[3] reserved, must be 0 */
+                            [1] row form of the FP32 1D-1V reconstruction: 1 dense rows (every
+                                register load issued), 2 sparse rows (loads past a row segment
+                                skipped); the default takes sparse rows when a segment averages
+                                below 0.6 of the register capacity; ignored by other forms;
+                            [2] resident blocks per compute unit of the FP32 1D-1V tiled count
+                                and scatter passes, 1..64 (at most what fits; the default is
+                                what fits);
+                            [3] reserved, must be 0 */
     double B[3];         /* uniform background magnetic field (1D-3V, AVL_FP64 only; all zero
                             otherwise): the acceleration is (q/m)(E + v x B), E along x, and
                             the push is the Boris scheme (Sec. 2, magnetised 1D-3V: a half

@@ -48,6 +48,8 @@ class AvlConfig(ctypes.Structure):
 
 # avl_config.tune slots (0 leaves the library's choice)
 TUNE_RECON_ROWS = 0       # target velocity rows per 1D-1V reconstruction task, 1..256
+TUNE_RECON_FORM = 1       # FP32 1D-1V reconstruction rows: 1 dense, 2 sparse
+TUNE_SORT_BLOCKS = 2      # resident blocks per compute unit of the FP32 1D-1V tiled sort passes, 1..64
 
 
 _lib = None

@@ -54,6 +54,7 @@ hipError_t launch_fill_f64(double* p, int n, double value, hipStream_t st);
 hipError_t launch_scale_f64(double* p, int n, double s, hipStream_t st);
 int sort_blocks(const Geo& g, int phase);
 size_t sort_lds(const Geo& g);
+size_t scatter_lds(const Geo& g);
 int scatter_blocks_per_cu(const Geo& g);
 int scatter_step_blocks_per_cu(const Geo& g);
 int count_blocks_per_cu(const Geo& g);
@@ -106,6 +107,18 @@ int device_cus()
 }
 
 // Validate a configuration and derive the kernel constants.
+// Grids of the tiled FP32 1D-1V sort passes: the blocks that fit on every
+// compute unit at once, at most sort_cap per compute unit when that is set.
+// A pass that is not tiled reports 0 (a block per tile) and stays 0.
+void sort_launch_shapes(Geo& g)
+{
+    const int cus = device_cus();
+    auto capped = [&](int per_cu) { return g.sort_cap > 0 ? std::min(per_cu, g.sort_cap) : per_cu; };
+    g.sblocks = capped(scatter_blocks_per_cu(g)) * cus;
+    g.sblocks_step = capped(scatter_step_blocks_per_cu(g)) * cus;
+    g.cblocks = capped(count_blocks_per_cu(g)) * cus;
+}
+
 int make_geo(const avl_config* c, Geo* g)
 {
     if (!c) return AVL_EINVAL;
@@ -115,7 +128,9 @@ int make_geo(const avl_config* c, Geo* g)
     if (c->precision != AVL_FP64 && c->precision != AVL_FP32) return AVL_EINVAL;
     if (c->first_kick != 0 && c->first_kick != 1) return AVL_EINVAL;
     if (c->options & ~AVL_OPT_KAHAN32) return AVL_EINVAL;
-    if (c->tune[0] < 0 || c->tune[0] > 256 || c->tune[1] || c->tune[2] || c->tune[3]) return AVL_EINVAL;
+    if (c->tune[0] < 0 || c->tune[0] > 256 || c->tune[1] < 0 || c->tune[1] > 2 || c->tune[2] < 0 ||
+        c->tune[2] > 64 || c->tune[3])
+        return AVL_EINVAL;
     if ((c->options & AVL_OPT_KAHAN32) && c->precision != AVL_FP32) return AVL_EINVAL;
     // the 1D-3V reconstruction always accumulates in FP64
     if ((c->options & AVL_OPT_KAHAN32) && c->vdim == 3) return AVL_ENOTSUP;
@@ -136,6 +151,7 @@ int make_geo(const avl_config* c, Geo* g)
     g->vdim = c->vdim;
     g->prec = c->precision;
     g->kahan = (c->options & AVL_OPT_KAHAN32) ? 1 : 0;
+    g->sort_cap = c->tune[2];
     g->nx = c->nx;
     g->lognx = ilog2(c->nx);
     int64_t rows = 1, cells = c->nx;
@@ -199,6 +215,7 @@ int make_geo(const avl_config* c, Geo* g)
         int rc = (int)std::max<int64_t>(2, std::min<int64_t>(32, ((int64_t)c->nv[0] * g->nstrip + slots - 1) / slots));
         if (c->tune[0]) rc = c->tune[0];
         g->rc = rc;
+        g->rform = c->tune[1];
         g->nchunk = (c->nv[0] + rc - 1) / rc;
         g->cap = recon_capacity(c->precision);
     } else {
@@ -690,9 +707,7 @@ int avl_init(const avl_config* cfg, void* workspace, size_t ws_bytes, void* stre
             if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) lds = 65536;
         set_lds_limit(lds);
         fit_lds(&h->g, lds);
-        h->g.sblocks = scatter_blocks_per_cu(h->g) * device_cus();
-        h->g.sblocks_step = scatter_step_blocks_per_cu(h->g) * device_cus();
-        h->g.cblocks = count_blocks_per_cu(h->g) * device_cus();
+        sort_launch_shapes(h->g);
         if (debug_on())
             std::fprintf(stderr, "[avl] lds limit %d B, recon cap %d, hist bins %d, rc %d, chunks %d, strips %d\n", lds,
                          h->g.cap, h->g.hist_bins, h->g.rc, h->g.nchunk, h->g.nstrip);
@@ -1037,7 +1052,7 @@ struct avl_batch {
     int* pre;                   // device, BPRE_KINDS x (n+1)
     int tot[BPRE_KINDS];
     int prec, kahan, max_nx;
-    size_t lds;
+    size_t lds, lds_scatter;
     hipGraphExec_t gexec[2];
     hipStream_t cap_st;
     bool graph_ok;
@@ -1091,7 +1106,7 @@ int batch_launch(avl_batch* b, int cur, hipStream_t st)
 {
     AVL_TRY(launch_sort_batch(b->prec, b->tab, b->pre, b->n, b->tot[BPRE_COUNT], b->lds, cur, st, 0));
     AVL_TRY(launch_sort_batch(b->prec, b->tab, b->pre, b->n, b->tot[BPRE_SCAN], b->lds, cur, st, 1));
-    AVL_TRY(launch_sort_batch(b->prec, b->tab, b->pre, b->n, b->tot[BPRE_SCATTER], b->lds, cur, st, 2));
+    AVL_TRY(launch_sort_batch(b->prec, b->tab, b->pre, b->n, b->tot[BPRE_SCATTER], b->lds_scatter, cur, st, 2));
     // the sparse-row kernels when every instance with markers has sparse rows
     bool sparse = true;
     for (avl_handle* hi : b->h)
@@ -1173,6 +1188,7 @@ int avl_batch_init(const avl_config* cfgs, int32_t count, void* workspace, size_
     b->kahan = (cfgs[0].options & AVL_OPT_KAHAN32) ? 1 : 0;
     b->max_nx = 0;
     b->lds = 0;
+    b->lds_scatter = 0;
     for (int i = 0; i < count; ++i) {
         avl_handle* h = b->h[i];
         const Geo& g = h->g;
@@ -1212,6 +1228,7 @@ int avl_batch_init(const avl_config* cfgs, int32_t count, void* workspace, size_
                                                                                        k >= BPRE_RECON ? items[k] : 0);
         b->max_nx = std::max(b->max_nx, g.nx);
         b->lds = std::max(b->lds, sort_lds(g));
+        b->lds_scatter = std::max(b->lds_scatter, scatter_lds(g));
     }
     for (int k = 0; k < BPRE_KINDS; ++k) b->tot[k] = pre[(size_t)k * (count + 1) + count];
     b->tab = (BInst*)(ws + tab_off);
@@ -1888,9 +1905,7 @@ extern "C" int avl_reconstruct_noalloc(const avl_config* cfg, void* stream, cons
             if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) lds = 65536;
         set_lds_limit(lds);
         fit_lds(&g, lds);
-        g.sblocks = scatter_blocks_per_cu(g) * device_cus();
-        g.sblocks_step = scatter_step_blocks_per_cu(g) * device_cus();
-        g.cblocks = count_blocks_per_cu(g) * device_cus();
+        sort_launch_shapes(g);
     }
     M64 m64[2];
     M32 m32[2];

@@ -59,6 +59,8 @@ struct Geo {
     int sblocks;         // blocks of the tiled scatter (FP32 1D-1V): the resident capacity; 0 = a tile per block
     int sblocks_step;    // blocks of the step's scatter (FP32 1D-1V): its resident capacity
     int cblocks;         // blocks of the count pass: its resident capacity; 0 = a tile per block
+    int sort_cap;        // at most this many resident blocks per CU in the tiled sort passes (0: no limit)
+    int rform;           // FP32 1D-1V reconstruction rows: 0 chosen from the shape, 1 dense, 2 sparse
     int magnetic;        // 1D-3V FP64 with a background magnetic field: Boris push
     double B[3];         // background magnetic field
     double L, inv_L, dx, inv_dx;

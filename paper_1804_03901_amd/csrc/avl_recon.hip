@@ -684,6 +684,7 @@ __global__ __launch_bounds__(kWave) void k_recon_b(const BInst* __restrict__ tab
 bool recon_sparse(const Geo& g)
 {
     if (g.prec != 1 || g.nb <= 0) return false;
+    if (g.rform) return g.rform == 2;
     const double per_row = (double)g.n / (double)g.nb * kReconCols;
     return per_row <= 0.6 * kWave * RT<1>::KU;
 }

@@ -637,7 +637,8 @@ __device__ __forceinline__ void scatter_block(const Geo& g, const typename Marke
                                               const typename MarkersOf<PREC>::T& dst,
                                               const double* __restrict__ E, const RowShift* __restrict__ rows_g,
                                               double dtk, float bk, const int* __restrict__ offsets,
-                                              int* __restrict__ counts, int* __restrict__ flags, int blk, const Prev& pv)
+                                              int* __restrict__ counts, int* __restrict__ flags, int blk, const Prev& pv,
+                                              int maxbins)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     SortSmem<PREC> sm(smem, g);
@@ -651,7 +652,7 @@ __device__ __forceinline__ void scatter_block(const Geo& g, const typename Marke
     load_tile<PREC, VD>(src, g, p, base, last, ovf);
     int fl = 0;
     scatter_tile<PREC, VD, PUSH, IMPL>(g, sm, p, dst, dtk, bk, offsets, counts, base, last, s_b, &s_lo, &s_nb, fl,
-                                       pv, ovf, s_aux, g.hist_bins);
+                                       pv, ovf, s_aux, maxbins);
     if (fl) atomicOr(&s_flags, fl);
     __syncthreads();
     if (threadIdx.x == 0 && s_flags) atomicOr(flags, s_flags);
@@ -667,7 +668,7 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter1(Geo g, typename Marke
                                                            int* __restrict__ counts, int* __restrict__ flags)
 {
     scatter_block<PREC, VD, PUSH, false>(g, src, dst, E, rows_g, dtk, bk, offsets, counts, flags, blockIdx.x,
-                                         Prev{nullptr, nullptr});
+                                         Prev{nullptr, nullptr}, g.hist_bins);
 }
 
 // Tiled scatter: each block takes tiles blockIdx.x, blockIdx.x + gridDim.x,
@@ -1069,9 +1070,14 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter_b(const BInst* __restr
     const int* pr = pre + BPRE_SCATTER * (ninst + 1);
     const int i = find_inst(pr, ninst, blockIdx.x);
     const BInst& I = tab[i];
-    scatter_block<PREC, 1, true, PREC == 1>(I.g, bmark<PREC>(I, cur), bmark<PREC>(I, 1 - cur), I.E, I.rows, I.dtk,
-                                            I.bk, I.offsets[1 - cur], I.counts, I.flags, blockIdx.x - pr[i],
-                                            Prev{I.offsets[cur], I.tfirst[cur]});
+    // batch instances carry no marker identities: with the null pointers
+    // known at compile time the payload holds no id register
+    typename MarkersOf<PREC>::T src = bmark<PREC>(I, cur), dst = bmark<PREC>(I, 1 - cur);
+    src.id = nullptr;
+    dst.id = nullptr;
+    scatter_block<PREC, 1, true, PREC == 1>(I.g, src, dst, I.E, I.rows, I.dtk, I.bk, I.offsets[1 - cur], I.counts,
+                                            I.flags, blockIdx.x - pr[i], Prev{I.offsets[cur], I.tfirst[cur]},
+                                            PREC == 1 ? I.g.sbins : I.g.hist_bins);
 }
 
 // Blocks of a batched pass for one instance (host side).
@@ -1137,6 +1143,10 @@ int scatter_blocks_per_cu(const Geo& g)
 // LDS of the count and scatter blocks for one instance (host side).
 size_t sort_lds(const Geo& g) { return g.prec ? sort_smem<1>(g, true) : sort_smem<0>(g, true); }
 
+// LDS of the batched scatter for one instance: the FP32 form's window is the
+// step scatter's (sbins buckets), the FP64 form's the count's.
+size_t scatter_lds(const Geo& g) { return g.prec ? scatter_step_smem(g) : sort_smem<0>(g, true); }
+
 // phase 0 = count (with push), 1 = scan, 2 = scatter, over `blocks` blocks
 hipError_t launch_sort_batch(int prec, const BInst* tab, const int* pre, int ninst, int blocks, size_t smem, int cur,
                              hipStream_t st, int phase)
@@ -1145,8 +1155,9 @@ hipError_t launch_sort_batch(int prec, const BInst* tab, const int* pre, int nin
     static int granted[4] = {0, 0, 0, 0};
     const void* fns[4] = {(const void*)k_count_b<0>, (const void*)k_count_b<1>, (const void*)k_scatter_b<0>,
                           (const void*)k_scatter_b<1>};
-    for (int i = 0; i < 4; ++i) {
-        hipError_t e = ensure_lds(fns[i], smem, granted[i]);
+    {
+        const int i = (phase == 2 ? 2 : 0) + (prec == 0 ? 0 : 1);
+        hipError_t e = phase == 1 ? hipSuccess : ensure_lds(fns[i], smem, granted[i]);
         if (e != hipSuccess) return e;
     }
     const dim3 gr(blocks);

@@ -52,7 +52,8 @@ def test_workspace_bytes_valid_config():
     dict(nx=48), dict(nx=4), dict(nx=8192), dict(vdim=2), dict(precision=7), dict(first_kick=2),
     dict(options=2), dict(options=1), dict(L=0.0), dict(L=float("nan")), dict(dt=-0.1), dict(c_p=0.0), dict(m=0.0),
     dict(nv=(1, 1, 1)), dict(vmin=(6.0, 0, 0)), dict(n_markers=-1), dict(n_markers=2 ** 31),
-    dict(tune=(-1, 0, 0, 0)), dict(tune=(300, 0, 0, 0)), dict(tune=(0, 1, 0, 0)), dict(tune=(0, 0, 0, 1)),
+    dict(tune=(-1, 0, 0, 0)), dict(tune=(300, 0, 0, 0)), dict(tune=(0, 3, 0, 0)), dict(tune=(0, -1, 0, 0)),
+    dict(tune=(0, 0, 65, 0)), dict(tune=(0, 0, -1, 0)), dict(tune=(0, 0, 0, 1)),
 ])
 def test_invalid_configs_rejected_on_host(bad):
     assert avl.avl_workspace_bytes(_cfg(**bad)) == 0
@@ -106,7 +107,8 @@ def test_three_v_rejects_kahan_option():
 
 
 def test_tuning_knobs_accepted():
-    for t in [(0, 0, 0, 0), (4, 0, 0, 0), (256, 0, 0, 0)]:
+    for t in [(0, 0, 0, 0), (4, 0, 0, 0), (256, 0, 0, 0), (0, 1, 0, 0), (0, 2, 0, 0), (0, 0, 1, 0), (0, 0, 64, 0),
+              (8, 2, 3, 0)]:
         assert avl.avl_workspace_bytes(_cfg(tune=t)) > 0
 
 
@@ -215,6 +217,8 @@ def test_config_fuzz_host_validation():
         for k in ("L", "dt", "q", "m", "c_p"):
             if rng.random() < 0.15: setattr(c, k, pick(floats) * pick([-1, 1]))
         if rng.random() < 0.2: c.tune[0] = pick([-1, 0, 1, 255, 256, 257, 2 ** 31 - 1])
+        if rng.random() < 0.1: c.tune[1] = pick([-1, 0, 1, 2, 3])
+        if rng.random() < 0.1: c.tune[2] = pick([-1, 0, 1, 64, 65, 2 ** 31 - 1])
         n = avl.avl_workspace_bytes(c)
         if n:
             accepted += 1

@@ -23,6 +23,24 @@ def test_shape_key_and_cache_round_trip(tmp_path):
     assert tune._load_cache(os.path.join(tmp_path, "missing.json")) == {}
 
 
+def test_search_is_coordinate_descent():
+    # slot 0 best at 8 with the others at their defaults; slot 1 then best at 2
+    cost = lambda t: abs(t[0] - 8) + (0 if t[1] == 2 else 1) + 0.5 * (t[0] == 8 and t[1] == 2)
+    calls = []
+    best, tables = tune.search([(0, (0, 4, 8)), (1, (0, 1, 2))], lambda t: calls.append(dict(t)) or cost(t),
+                               repeats=1)
+    assert best == {0: 8, 1: 2}
+    assert set(tables) == {0, 1} and set(tables[0]) == {0, 4, 8} and set(tables[1]) == {0, 1, 2}
+    # the second slot is searched with the first at its choice
+    assert all(c[0] == 8 for c in calls[3:]) and all(c[1] == 0 for c in calls[:3])
+
+
+def test_cache_entry_round_trip():
+    best, tables = {0: 6, 1: 2, 2: 0}, {0: {0: 1.5, 6: 1.2}, 1: {0: 1.2, 2: 1.1}}
+    e = tune._to_cache(best, tables)
+    assert tune._from_cache(e) == (best, tables)
+
+
 @pytest.mark.gpu
 def test_tune_single_on_gpu(tmp_path):
     torch = pytest.importorskip("torch")
@@ -30,7 +48,22 @@ def test_tune_single_on_gpu(tmp_path):
         pytest.skip("no GPU")
     w = inputs.bump_on_tail(nx=256, nv=128, ppc=4, seed=2)
     path = os.path.join(tmp_path, "t.json")
-    t, table = tune.tune_single(w, candidates=(0, 4, 8), steps=3, warmup=1, cache_path=path)
-    assert t[avl.TUNE_RECON_ROWS] in (0, 4, 8) and set(table) == {0, 4, 8}
-    t2, _ = tune.tune_single(w, candidates=(0, 4, 8), cache_path=path)
-    assert t2 == t
+    t, tables = tune.tune_single(w, candidates=(0, 4, 8), forms=(0, 1, 2), sort_blocks=(0, 2), steps=3, warmup=1,
+                                 cache_path=path)
+    assert t[avl.TUNE_RECON_ROWS] in (0, 4, 8) and set(tables[avl.TUNE_RECON_ROWS]) == {0, 4, 8}
+    assert t[avl.TUNE_RECON_FORM] in (0, 1, 2) and set(tables[avl.TUNE_RECON_FORM]) == {0, 1, 2}
+    assert t[avl.TUNE_SORT_BLOCKS] in (0, 2) and set(tables[avl.TUNE_SORT_BLOCKS]) == {0, 2}
+    t2, tables2 = tune.tune_single(w, candidates=(0, 4, 8), cache_path=path)
+    assert t2 == t and tables2 == tables
+
+
+@pytest.mark.gpu
+def test_tune_batch_on_gpu(tmp_path):
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ws = inputs.batched_scan(count=3, seed=4, ppc=2, nx_choices=(32, 64), nv_choices=(16, 32))
+    path = os.path.join(tmp_path, "t.json")
+    ts, tables = tune.tune_batch(ws, candidates=(0, 4), forms=(1, 2), steps=2, warmup=1, cache_path=path)
+    assert len(ts) == 3 and all(t == ts[0] for t in ts)
+    assert set(tables) == {avl.TUNE_RECON_ROWS, avl.TUNE_RECON_FORM} and ts[0][avl.TUNE_RECON_FORM] in (1, 2)
