@@ -77,6 +77,10 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"libavl is not built ({path} missing): run paper_1804_03901_amd/build.py")
+    # torch first: the library then binds to the HIP runtime torch has loaded.
+    # Opened first, it would load the system runtime beside torch's, and
+    # pointers and streams from one runtime are invalid in the other.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp, c = ctypes.c_void_p, ctypes
     P = ctypes.POINTER

@@ -230,3 +230,18 @@ def test_config_fuzz_host_validation():
                           ctypes.byref(h))
         assert rc < 0 and not h.value
     assert accepted > 50
+
+
+def test_load_shares_torchs_hip_runtime():
+    """Loading the library before anything imports torch still leaves one HIP
+    runtime in the process (the one torch ships), checked in a fresh
+    interpreter from its memory map."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1804_03901_amd import avl\n"
+            "avl.load()\n"
+            "import torch\n"
+            "print(len({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))\n") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300, check=True)
+    assert out.stdout.strip().splitlines()[-1] == "1"
