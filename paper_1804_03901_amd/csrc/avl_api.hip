@@ -55,6 +55,7 @@ hipError_t launch_scale_f64(double* p, int n, double s, hipStream_t st);
 int sort_blocks(const Geo& g, int phase);
 size_t sort_lds(const Geo& g);
 size_t scatter_lds(const Geo& g);
+int recon_waves_per_cu(int prec, int lds_per_cu);
 int scatter_blocks_per_cu(const Geo& g);
 int scatter_step_blocks_per_cu(const Geo& g);
 int count_blocks_per_cu(const Geo& g);
@@ -106,7 +107,20 @@ int device_cus()
     return cus;
 }
 
-// Validate a configuration and derive the kernel constants.
+// LDS bytes of one compute unit (160 KB on MI355X, assumed when no device is
+// visible).
+int device_lds_per_cu()
+{
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+        lds <= 0) {
+        (void)hipGetLastError();
+        return 160 * 1024;
+    }
+    return lds;
+}
+
 // Grids of the tiled FP32 1D-1V sort passes: the blocks that fit on every
 // compute unit at once, at most sort_cap per compute unit when that is set.
 // A pass that is not tiled reports 0 (a block per tile) and stays 0.
@@ -119,6 +133,7 @@ void sort_launch_shapes(Geo& g)
     g.cblocks = capped(count_blocks_per_cu(g)) * cus;
 }
 
+// Validate a configuration and derive the kernel constants.
 int make_geo(const avl_config* c, Geo* g)
 {
     if (!c) return AVL_EINVAL;
@@ -207,12 +222,14 @@ int make_geo(const avl_config* c, Geo* g)
     // reconstruction decomposition
     if (c->vdim == 1) {
         // wave tasks of one 63-column strip by rc velocity rows: the fewest
-        // rows per task such that all tasks are resident at once (two waves
-        // per SIMD, the reconstruction's register budget), so there is no
-        // partial second round; tune[0] overrides rc
+        // rows per task such that all tasks are resident at once (as many
+        // waves as the reconstruction's registers and LDS let a compute unit
+        // hold), so there is no partial second round; tune[0] overrides rc
         g->nstrip = (c->nx + kReconCols - 1) / kReconCols;
-        const int64_t slots = 8 * (int64_t)device_cus();
-        int rc = (int)std::max<int64_t>(2, std::min<int64_t>(32, ((int64_t)c->nv[0] * g->nstrip + slots - 1) / slots));
+        const int64_t slots =
+            (int64_t)recon_waves_per_cu(c->precision == AVL_FP32 ? 1 : 0, device_lds_per_cu()) * device_cus();
+        int rc = 2;
+        while (rc < 32 && (int64_t)g->nstrip * ((c->nv[0] + rc - 1) / rc) > slots) ++rc;
         if (c->tune[0]) rc = c->tune[0];
         g->rc = rc;
         g->rform = c->tune[1];
@@ -709,8 +726,11 @@ int avl_init(const avl_config* cfg, void* workspace, size_t ws_bytes, void* stre
         fit_lds(&h->g, lds);
         sort_launch_shapes(h->g);
         if (debug_on())
-            std::fprintf(stderr, "[avl] lds limit %d B, recon cap %d, hist bins %d, rc %d, chunks %d, strips %d\n", lds,
-                         h->g.cap, h->g.hist_bins, h->g.rc, h->g.nchunk, h->g.nstrip);
+            std::fprintf(stderr,
+                         "[avl] lds limit %d B, recon cap %d, hist bins %d, rc %d, chunks %d, strips %d, "
+                         "recon waves per CU %d\n",
+                         lds, h->g.cap, h->g.hist_bins, h->g.rc, h->g.nchunk, h->g.nstrip,
+                         h->g.vdim == 1 ? recon_waves_per_cu(h->g.prec, device_lds_per_cu()) : 0);
     }
     if (hipMemsetAsync(h->flags, 0, sizeof(int), h->st) != hipSuccess || (rc = upload_tables(h)) != AVL_OK) {
         delete h;

@@ -180,7 +180,9 @@ template <int PREC> struct RT;
 template <> struct RT<0> {
     using T = double;
     using M = M64;
-    static constexpr int KU = 20;    // register prefetch depth per lane (markers)
+    // register prefetch depth per lane (markers); 18 keeps the staging buffer
+    // at 29 KB, so five waves fit in a compute unit's LDS
+    static constexpr int KU = 18;
 };
 template <> struct RT<1> {
     using T = float;
@@ -748,5 +750,21 @@ hipError_t launch_recon(const Geo& g, void* m, const int* offsets, void* fgrid, 
 }
 
 int recon_capacity(int prec) { return prec ? recon_cap<1>() : recon_cap<0>(); }
+
+// Reconstruction waves resident per compute unit, from the occupancy query:
+// two per SIMD by the register budget, fewer where a compute unit's LDS holds
+// fewer staging buffers (the FP64 form's 29 KB a wave: five).  Without a device,
+// the LDS arithmetic on lds_per_cu bytes.
+int recon_waves_per_cu(int prec, int lds_per_cu)
+{
+    const size_t per_wave = prec ? recon_lds<1>() : recon_lds<0>();
+    const void* fn = prec ? (const void*)k_recon_1v<1, false, false> : (const void*)k_recon_1v<0, false, false>;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kWave, per_wave) != hipSuccess || per_cu <= 0) {
+        (void)hipGetLastError();
+        per_cu = (int)std::max<size_t>(1, std::min<size_t>(8, (size_t)lds_per_cu / per_wave));
+    }
+    return per_cu;
+}
 
 }  // namespace avl
