@@ -154,7 +154,7 @@ def measured_traffic(workload, kernel_tag):
     return rows[kernel_tag][0] + rows[kernel_tag][1]
 
 
-def run_batched(avl, inputs, steps, warmup, count):
+def run_batched(avl, inputs, steps, warmup, count, one_by_one=True):
     """The parameter-scan batch (uneven 1D-1V bump-on-tail instances, FP32
     form), stepped as batched launches replayed as a HIP graph, and beside it
     the same instances stepped one after another, each as its own handle with
@@ -183,7 +183,7 @@ def run_batched(avl, inputs, steps, warmup, count):
     b.close()
     # one instance at a time: the sum of the instances' own graph-replayed steps
     one_ms = 0.0
-    for w, (x, v, f) in zip(ws, mk):
+    for w, (x, v, f) in zip(ws, mk) if one_by_one else ():
         sim = avl.Simulation(w, x, v.reshape(-1), f, precision=avl.AVL_FP32)
         sim.step(warmup, graph=True, diag=False)
         e0 = torch.cuda.Event(enable_timing=True)
@@ -198,15 +198,18 @@ def run_batched(avl, inputs, steps, warmup, count):
         sim.close()
     del mk
     names = {avl.TUNE_RECON_ROWS: "recon_rows", avl.TUNE_RECON_FORM: "recon_form"}
+    obo = None
+    if one_by_one:
+        obo = {"ms_per_step": one_ms, "marker_steps_per_s": n_markers / (one_ms * 1e-3),
+               "batched_speedup": one_ms / ms,
+               "timing": "each instance alone, its own graph replay, library defaults; "
+                         "sum over the instances of their ms per step"}
     return {"instances": len(ws), "markers": n_markers, "ms_per_step": ms,
             "marker_steps_per_s": n_markers / (ms * 1e-3), "steps": steps, "form": "fp32",
             "nx": sorted({w.nx for w in ws}), "nv": sorted({w.nv[0] for w in ws}),
             "tuned": {names[k]: v for k, v in tunes[0].items()},
             "tuning_ms_per_step": {names[k]: {str(c): t for c, t in tab.items()} for k, tab in tables.items()},
-            "one_by_one": {"ms_per_step": one_ms, "marker_steps_per_s": n_markers / (one_ms * 1e-3),
-                           "batched_speedup": one_ms / ms,
-                           "timing": "each instance alone, its own graph replay, library defaults; "
-                                     "sum over the instances of their ms per step"}}
+            "one_by_one": obo}
 
 
 def run_adjoint(avl, inputs, every=50):
@@ -336,6 +339,8 @@ def main():
     ap.add_argument("--adjoint", default=True, action=argparse.BooleanOptionalAction,
                     help="time one gradient of the adjoint configuration (default on)")
     ap.add_argument("--batch", type=int, default=64, help="instances of the batched parameter scan (0: skip)")
+    ap.add_argument("--one-by-one", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the batch's instances one after another (default on)")
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--cpu-cores", type=int, default=16,
                     help="most processes of the all-core CPU baseline (nproc of the host, capped here: a GPU "
@@ -428,10 +433,11 @@ def main():
             f"{out['adjoint']['gradient_over_forward']:.2f}x the forward run")
     if args.batch and not three_v:
         log(f"batched scan: {args.batch} instances, warmup {args.warmup}, timed {args.batch_steps}")
-        out["batched"] = run_batched(avl, inputs, args.batch_steps, args.warmup, args.batch)
+        out["batched"] = run_batched(avl, inputs, args.batch_steps, args.warmup, args.batch, args.one_by_one)
+        obo = out["batched"]["one_by_one"]
         log(f"batched scan: {out['batched']['ms_per_step']:.4f} ms/step, "
-            f"{out['batched']['marker_steps_per_s']:.3e} marker-steps/s; one by one "
-            f"{out['batched']['one_by_one']['ms_per_step']:.4f} ms/step")
+            f"{out['batched']['marker_steps_per_s']:.3e} marker-steps/s"
+            + (f"; one by one {obo['ms_per_step']:.4f} ms/step" if obo else ""))
         if "fp64" in results:
             fp64_rate = w.n_markers / (results["fp64"][1] * 1e-3)
             out["batched"]["fp32_batched_over_fp64_plain"] = out["batched"]["marker_steps_per_s"] / fp64_rate
