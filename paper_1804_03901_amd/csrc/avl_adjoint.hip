@@ -23,9 +23,11 @@
 //              lam_x <- lam_x' + c E'(x) lam_v, E_bar(x) = c lam_v;
 //   * gather:  mu_i^n += W_i(x^n) E_bar (deposited onto the grid).
 // Adjoints are kept per marker identity (the sort moves identities with the
-// markers), so recorded states can be visited in any order; the gathered
-// field adjoint is summed as integers (order-free), so the gradient is the
-// same bit for bit from run to run.
+// markers), so recorded states can be visited in any order; the driver
+// records states in identity order, so a reverse step reads coordinates,
+// weights and adjoints at one index.  The gathered field adjoint is summed as
+// integers (order-free), so the gradient is the same bit for bit from run to
+// run.
 #include <algorithm>
 
 #include "avl_device.h"
@@ -37,10 +39,81 @@ __global__ void k_iota(int* __restrict__ id, int n)
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) id[i] = i;
 }
 
+// Reverse of the reconstruction and moments for one marker at (x, v) with
+// weight fl: its f_bar and the position adjoints dx, dv (per cell width).
+// R times rscale is rho_bar (the driver passes P mu with rscale = -1); fg
+// and Dg the state's grids.
+template <typename T>
+__device__ __forceinline__ void deposit_one(const Geo& g, double x, double v, double fl, const T* __restrict__ fg,
+                                            const T* __restrict__ Dg, const double* __restrict__ R, double rscale,
+                                            double& fb, double& dx, double& dv)
+{
+    const double s = x * g.inv_dx - 0.5;
+    const double fs = floor(s);
+    const double a = s - fs;
+    const int ia = wrap_pow2((int)fs, g.nx);
+    const int ib = wrap_pow2(ia + 1, g.nx);
+    const double t = (v - g.vmin[0]) * g.inv_dv[0] - 0.5;
+    const double ft = floor(t);
+    const double b = t - ft;
+    const int j0 = (int)ft;
+    fb = 0.0;
+    dx = 0.0;
+    dv = 0.0;
+#pragma unroll
+    for (int cj = 0; cj < 2; ++cj) {
+        const int j = j0 + cj;
+        if (j < 0 || j >= g.nv[0]) continue;
+        const double wy = cj ? b : 1.0 - b;
+#pragma unroll
+        for (int ci = 0; ci < 2; ++ci) {
+            const int col = ci ? ib : ia;
+            const size_t gi = (size_t)j * g.nx + col;
+            const double D = (double)Dg[gi];
+            const double Nb = D > 0.0 ? rscale * g.q_vol * R[col] / D : 0.0;
+            const double Db = -Nb * (double)fg[gi];
+            const double G = Nb * fl + Db;
+            const double wx = ci ? a : 1.0 - a;
+            fb += wx * wy * Nb;
+            dx += (ci ? wy : -wy) * G;
+            dv += (cj ? wx : -wx) * G;
+        }
+    }
+}
+
+// Reverse of gather + kick + drift for one marker at x (its position before
+// the push), E the field of that step: lam_v <- lam_v' + lam_x' dt,
+// lam_x <- lam_x' + c E'(x) lam_v, in place on (Lx, Lv).
+__device__ __forceinline__ void push_lam_one(const Geo& g, double x, const double* __restrict__ E, double c,
+                                             double& Lx, double& Lv)
+{
+    const double lvt = Lv + Lx * g.dt;
+    const double s = x * g.inv_dx - 0.5;
+    const double fs = floor(s);
+    const int ia = wrap_pow2((int)fs, g.nx);
+    const int ib = wrap_pow2(ia + 1, g.nx);
+    const double Ep = (E[ib] - E[ia]) * g.inv_dx;
+    Lx = Lx + c * Ep * lvt;
+    Lv = lvt;
+}
+
+// The largest key of a block into *key with one atomic (256 threads).
+__device__ __forceinline__ void block_key_max(unsigned kmax, unsigned* __restrict__ key)
+{
+    __shared__ unsigned s_max[256 / kWave];
+    for (int off = kWave / 2; off > 0; off >>= 1) kmax = max(kmax, (unsigned)__shfl_xor((int)kmax, off));
+    if ((threadIdx.x & (kWave - 1)) == 0) s_max[threadIdx.x / kWave] = kmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned m = 0u;
+        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) m = max(m, s_max[w]);
+        if (m) atomicMax(key, m);
+    }
+}
+
 // Reverse of the reconstruction and moments for the markers of one state.
-// R times rscale is rho_bar (the driver passes P mu with rscale = -1); fg and
-// Dg the state's grids.  Marker k has identity id[k] (k itself when id is
-// null); its adjoints are added at that identity.
+// Marker k has identity id[k] (k itself when id is null); its adjoints are
+// added at that identity.
 template <typename T>
 __global__ void k_adj_deposit(Geo g, const double* __restrict__ x, const double* __restrict__ v,
                               const int* __restrict__ id, const double* __restrict__ f_by_id,
@@ -50,42 +123,44 @@ __global__ void k_adj_deposit(Geo g, const double* __restrict__ x, const double*
 {
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < g.n; k += gridDim.x * blockDim.x) {
         const int l = id ? id[k] : k;
-        const double fl = f_by_id[l];
-        const double s = x[k] * g.inv_dx - 0.5;
-        const double fs = floor(s);
-        const double a = s - fs;
-        const int ia = wrap_pow2((int)fs, g.nx);
-        const int ib = wrap_pow2(ia + 1, g.nx);
-        const double t = (v[k] - g.vmin[0]) * g.inv_dv[0] - 0.5;
-        const double ft = floor(t);
-        const double b = t - ft;
-        const int j0 = (int)ft;
-        double fb = 0.0, dx = 0.0, dv = 0.0;
-#pragma unroll
-        for (int cj = 0; cj < 2; ++cj) {
-            const int j = j0 + cj;
-            if (j < 0 || j >= g.nv[0]) continue;
-            const double wy = cj ? b : 1.0 - b;
-#pragma unroll
-            for (int ci = 0; ci < 2; ++ci) {
-                const int col = ci ? ib : ia;
-                const size_t gi = (size_t)j * g.nx + col;
-                const double D = (double)Dg[gi];
-                const double Nb = D > 0.0 ? rscale * g.q_vol * R[col] / D : 0.0;
-                const double Db = -Nb * (double)fg[gi];
-                const double G = Nb * fl + Db;
-                const double wx = ci ? a : 1.0 - a;
-                fb += wx * wy * Nb;
-                dx += (ci ? wy : -wy) * G;
-                dv += (cj ? wx : -wx) * G;
-            }
-        }
+        double fb, dx, dv;
+        deposit_one<T>(g, x[k], v[k], f_by_id[l], fg, Dg, R, rscale, fb, dx, dv);
         f_bar[l] += fb;
         if (with_positions) {
             lam_x[l] += dx * g.inv_dx;
             lam_v[l] += dv * g.inv_dv[0];
         }
     }
+}
+
+// One reverse step for states recorded in identity order: the deposit
+// reverse on the pushed state (x1, v1, its grids fg, Dg) followed, marker by
+// marker, by the push reverse on the state before the push (x0, field E0) --
+// the same arithmetic as k_adj_deposit then k_adj_push_lam, without storing
+// and reloading the adjoints in between -- and the largest |c lam_v| into key.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_step_rev(Geo g, const double* __restrict__ x1,
+                                                      const double* __restrict__ v1,
+                                                      const double* __restrict__ f_by_id, const T* __restrict__ fg,
+                                                      const T* __restrict__ Dg, const double* __restrict__ R,
+                                                      double rscale, const double* __restrict__ x0,
+                                                      const double* __restrict__ E0, double c,
+                                                      double* __restrict__ lam_x, double* __restrict__ lam_v,
+                                                      double* __restrict__ f_bar, unsigned* __restrict__ key)
+{
+    unsigned kmax = 0u;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < g.n; k += gridDim.x * blockDim.x) {
+        double fb, dx, dv;
+        deposit_one<T>(g, x1[k], v1[k], f_by_id[k], fg, Dg, R, rscale, fb, dx, dv);
+        f_bar[k] += fb;
+        double Lx = lam_x[k] + dx * g.inv_dx;
+        double Lv = lam_v[k] + dv * g.inv_dv[0];
+        push_lam_one(g, x0[k], E0, c, Lx, Lv);
+        lam_x[k] = Lx;
+        lam_v[k] = Lv;
+        kmax = max(kmax, fix_key(c * Lv));
+    }
+    block_key_max(kmax, key);
 }
 
 // Order-free sums of the field adjoint E_bar.  Every term t of a launch is
@@ -128,9 +203,8 @@ __device__ __forceinline__ void dep_add(unsigned long long* acc, int nx, int i, 
 
 // Reverse of gather + kick + drift for the markers of state n (positions
 // before the push), E the field at step n, first pass: the velocity and
-// position adjoints, lam_v <- lam_v' + lam_x' dt, lam_x <- lam_x' + c E'(x)
-// lam_v (in place when the input and output arrays are the same), and the
-// largest |c lam_v| of the launch into key.
+// position adjoints (in place when the input and output arrays are the same),
+// and the largest |c lam_v| of the launch into key.
 __global__ __launch_bounds__(256) void k_adj_push_lam(Geo g, const double* __restrict__ x, const int* __restrict__ id,
                                                       const double* __restrict__ E, double c,
                                                       const double* lam_x_in, const double* lam_v_in,
@@ -139,33 +213,23 @@ __global__ __launch_bounds__(256) void k_adj_push_lam(Geo g, const double* __res
     unsigned kmax = 0u;
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < g.n; k += gridDim.x * blockDim.x) {
         const int l = id ? id[k] : k;
-        const double Lx = lam_x_in[l], Lv = lam_v_in[l];
-        const double lvt = Lv + Lx * g.dt;
-        const double s = x[k] * g.inv_dx - 0.5;
-        const double fs = floor(s);
-        const int ia = wrap_pow2((int)fs, g.nx);
-        const int ib = wrap_pow2(ia + 1, g.nx);
-        const double Ep = (E[ib] - E[ia]) * g.inv_dx;
-        lam_x[l] = Lx + c * Ep * lvt;
-        lam_v[l] = lvt;
-        kmax = max(kmax, fix_key(c * lvt));
+        double Lx = lam_x_in[l], Lv = lam_v_in[l];
+        push_lam_one(g, x[k], E, c, Lx, Lv);
+        lam_x[l] = Lx;
+        lam_v[l] = Lv;
+        kmax = max(kmax, fix_key(c * Lv));
     }
     // one atomic per block: the launch has a few blocks per CU, so the
     // single address sees a few thousand updates rather than one per wave
-    __shared__ unsigned s_max[256 / kWave];
-    for (int off = kWave / 2; off > 0; off >>= 1) kmax = max(kmax, (unsigned)__shfl_xor((int)kmax, off));
-    if ((threadIdx.x & (kWave - 1)) == 0) s_max[threadIdx.x / kWave] = kmax;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned m = 0u;
-        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) m = max(m, s_max[w]);
-        if (m) atomicMax(key, m);
-    }
+    block_key_max(kmax, key);
 }
 
 // Second pass: E_bar(x) = c lam_v gathered back onto the grid with the
 // cloud-in-cell weights, (1-a) to column ia and a to ia + 1, as order-free
 // integer sums, per block in LDS and then one global add per touched column.
+// A block takes chunks of 8 markers a thread, blockIdx.x, blockIdx.x +
+// gridDim.x, ...: markers in identity order reach every column from any
+// chunk, so a bounded grid keeps the global adds to a few per column and block.
 __global__ __launch_bounds__(256) void k_adj_push_dep(Geo g, const double* __restrict__ x, const int* __restrict__ id,
                                                       const double* __restrict__ lam_v, double c,
                                                       const unsigned* __restrict__ key, int S, int P,
@@ -178,17 +242,18 @@ __global__ __launch_bounds__(256) void k_adj_push_dep(Geo g, const double* __res
     __syncthreads();
     const int shift = dep_shift(*key, P);
     const int per = blockDim.x * 8;
-    const int base = blockIdx.x * per;
-    for (int k = base + threadIdx.x; k < min(base + per, g.n); k += blockDim.x) {
-        const int l = id ? id[k] : k;
-        const double Eb = c * lam_v[l];
-        const double s = x[k] * g.inv_dx - 0.5;
-        const double fs = floor(s);
-        const double a = s - fs;
-        const int ia = wrap_pow2((int)fs, nx);
-        const int ib = wrap_pow2(ia + 1, nx);
-        dep_add(sacc, nx, ia, (1.0 - a) * Eb, S, shift);
-        dep_add(sacc, nx, ib, a * Eb, S, shift);
+    for (int base = blockIdx.x * per; base < g.n; base += gridDim.x * per) {
+        for (int k = base + threadIdx.x; k < min(base + per, g.n); k += blockDim.x) {
+            const int l = id ? id[k] : k;
+            const double Eb = c * lam_v[l];
+            const double s = x[k] * g.inv_dx - 0.5;
+            const double fs = floor(s);
+            const double a = s - fs;
+            const int ia = wrap_pow2((int)fs, nx);
+            const int ib = wrap_pow2(ia + 1, nx);
+            dep_add(sacc, nx, ia, (1.0 - a) * Eb, S, shift);
+            dep_add(sacc, nx, ib, a * Eb, S, shift);
+        }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < 2 * nx; i += blockDim.x)
@@ -267,8 +332,35 @@ hipError_t launch_adj_push(const Geo& g, const double* x, const int* id, const d
     static int granted = 0;
     hipError_t e = ensure_lds((const void*)k_adj_push_dep, smem, granted);
     if (e != hipSuccess) return e;
-    const int blocks = (g.n + 256 * 8 - 1) / (256 * 8);
+    const int blocks = std::min((g.n + 256 * 8 - 1) / (256 * 8), 512);
     hipLaunchKernelGGL(k_adj_push_dep, dim3(blocks), dim3(256), smem, st, g, x, id, lam_v, c, key, d.S, d.P, acc);
+    return hipGetLastError();
+}
+
+// One reverse step for states in identity order: k_adj_step_rev, then the
+// field adjoint's integer deposit at the state before the push.
+hipError_t launch_adj_step_rev(const Geo& g, int grid_prec, const double* x1, const double* v1, const double* f_by_id,
+                               const void* fg, const void* Dg, const double* R, double rscale, const double* x0,
+                               const double* E0, double c, double* lam_x, double* lam_v, double* f_bar,
+                               unsigned long long* acc, unsigned* key, hipStream_t st)
+{
+    if (g.n == 0) return hipSuccess;
+    // enough blocks to keep the gathers in flight; one key atomic per block
+    const dim3 gr(std::min(grid_for(g.n, 256), 4096)), bl(256);
+    if (grid_prec == 0)
+        hipLaunchKernelGGL(k_adj_step_rev<double>, gr, bl, 0, st, g, x1, v1, f_by_id, (const double*)fg,
+                           (const double*)Dg, R, rscale, x0, E0, c, lam_x, lam_v, f_bar, key);
+    else
+        hipLaunchKernelGGL(k_adj_step_rev<float>, gr, bl, 0, st, g, x1, v1, f_by_id, (const float*)fg,
+                           (const float*)Dg, R, rscale, x0, E0, c, lam_x, lam_v, f_bar, key);
+    const DepScale d = dep_scale(g.n);
+    const size_t smem = sizeof(unsigned long long) * 2 * (size_t)g.nx;
+    static int granted = 0;
+    hipError_t e = ensure_lds((const void*)k_adj_push_dep, smem, granted);
+    if (e != hipSuccess) return e;
+    const int blocks = std::min((g.n + 256 * 8 - 1) / (256 * 8), 512);
+    hipLaunchKernelGGL(k_adj_push_dep, dim3(blocks), dim3(256), smem, st, g, x0, nullptr, lam_v, c, key, d.S, d.P,
+                       acc);
     return hipGetLastError();
 }
 

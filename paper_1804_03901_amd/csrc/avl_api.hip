@@ -37,13 +37,20 @@ hipError_t launch_validate(const Geo& g, const double* x, const double* v, const
                            hipStream_t st);
 hipError_t launch_to32(const Geo& g, const double* x, const double* v, const double* f, M32 m, int* flags,
                        hipStream_t st);
-hipError_t launch_to64(const Geo& g, M32 m, double* x, double* v, double* f, hipStream_t st);
+hipError_t launch_to64(const Geo& g, M32 m, double* x, double* v, double* f, hipStream_t st,
+                       const int* id = nullptr);
+hipError_t launch_by_id64(int n, const double* x, const double* v, const int* id, double* xo, double* vo,
+                          hipStream_t st);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
 size_t recon3_scratch_bytes(const Geo& g);
 hipError_t launch_iota(int* id, int n, hipStream_t st);
 hipError_t launch_adj_deposit(const Geo& g, int grid_prec, const double* x, const double* v, const int* id,
                               const double* f_by_id, const void* fg, const void* Dg, const double* R, double rscale,
                               double* lam_x, double* lam_v, double* f_bar, int with_positions, hipStream_t st);
+hipError_t launch_adj_step_rev(const Geo& g, int grid_prec, const double* x1, const double* v1, const double* f_by_id,
+                               const void* fg, const void* Dg, const double* R, double rscale, const double* x0,
+                               const double* E0, double c, double* lam_x, double* lam_v, double* f_bar,
+                               unsigned long long* acc, unsigned* key, hipStream_t st);
 hipError_t launch_adj_push(const Geo& g, const double* x, const int* id, const double* E, double c,
                            const double* lam_x_in, const double* lam_v_in, double* lam_x, double* lam_v,
                            unsigned long long* acc, unsigned* key, hipStream_t st);
@@ -1377,8 +1384,8 @@ namespace {
 // both marker buffers, small field buffers.
 struct AdjLayout {
     size_t cp, cp_stride, cp_ids, cp_E, mbytes;
-    size_t seg, seg_stride, st_x, st_v, st_id, st_fg, st_D, st_E;
-    size_t ids[2], lam_x, lam_v, f_bar, f_by_id, f_tmp, Pmu, mu, diag, total;
+    size_t seg, seg_stride, st_x, st_v, st_fg, st_D, st_E;
+    size_t ids[2], lam_x, lam_v, f_bar, f_by_id, Pmu, mu, diag, total;
     int nseg;
 };
 
@@ -1401,7 +1408,6 @@ bool adj_layout(const avl_config* c, const Geo& g, int32_t nsteps, int32_t every
     auto stake = [&](size_t bytes) { size_t r = so; so = align_up(so + bytes); return r; };
     A->st_x = stake(8 * n);
     A->st_v = stake(8 * n);
-    A->st_id = stake(4 * n);
     A->st_fg = stake(esz * G);
     A->st_D = stake(esz * G);
     A->st_E = stake(8 * nx);
@@ -1416,7 +1422,6 @@ bool adj_layout(const avl_config* c, const Geo& g, int32_t nsteps, int32_t every
     A->lam_v = take(8 * n);
     A->f_bar = take(8 * n);
     A->f_by_id = take(8 * n);
-    A->f_tmp = take(8 * n);
     A->Pmu = take(8 * nx);
     A->mu = take(8 * nx);
     A->diag = take(16 * (size_t)nsteps);
@@ -1459,23 +1464,21 @@ int adj_checkpoint(avl_handle* h, char* C, const AdjLayout& A, bool restore)
 }
 
 // State record: FP64 positions and velocities of the current markers (the
-// FP32 form converted exactly), identities, the f grid and the field (its D
-// grid is written by the reconstruction).
-int adj_save(avl_handle* h, char* S, const AdjLayout& A, double* f_tmp)
+// FP32 form converted exactly) in identity order, so that the reverse kernels
+// read them, the weights and the adjoints at the same index, coalesced; the f
+// grid and the field (its D grid is written by the reconstruction).
+int adj_save(avl_handle* h, char* S, const AdjLayout& A)
 {
     const Geo& g = h->g;
     const size_t n = (size_t)g.n;
     if (g.prec == AVL_FP64) {
         const M64& m = h->m64[h->cur];
-        AVL_TRY(hipMemcpyAsync(S + A.st_x, m.x, 8 * n, hipMemcpyDeviceToDevice, h->st));
-        AVL_TRY(hipMemcpyAsync(S + A.st_v, m.v, 8 * n, hipMemcpyDeviceToDevice, h->st));
-        AVL_TRY(hipMemcpyAsync(S + A.st_id, m.id, 4 * n, hipMemcpyDeviceToDevice, h->st));
+        AVL_TRY(launch_by_id64(g.n, m.x, m.v, m.id, (double*)(S + A.st_x), (double*)(S + A.st_v), h->st));
     } else {
         const int rc = ensure_cells(h);
         if (rc) return rc;
         const M32& m = h->m32[h->cur];
-        if (n) AVL_TRY(launch_to64(g, m, (double*)(S + A.st_x), (double*)(S + A.st_v), f_tmp, h->st));
-        AVL_TRY(hipMemcpyAsync(S + A.st_id, m.id, 4 * n, hipMemcpyDeviceToDevice, h->st));
+        if (n) AVL_TRY(launch_to64(g, m, (double*)(S + A.st_x), (double*)(S + A.st_v), nullptr, h->st, m.id));
     }
     const size_t esz = g.prec == AVL_FP64 ? 8 : 4;
     AVL_TRY(hipMemcpyAsync(S + A.st_fg, h->fgrid, esz * (size_t)g.nx * g.nv[0], hipMemcpyDeviceToDevice, h->st));
@@ -1512,7 +1515,6 @@ int avl_adjoint(avl_handle* h, const double* x, const double* v, const double* f
     double* lam_v = (double*)(R + A.lam_v);
     double* f_bar = (double*)(R + A.f_bar);
     double* f_by_id = (double*)(R + A.f_by_id);
-    double* f_tmp = (double*)(R + A.f_tmp);
     double* Pmu = (double*)(R + A.Pmu);
     double* mu = (double*)(R + A.mu);
     double* diag = (double*)(R + A.diag);
@@ -1582,11 +1584,11 @@ int avl_adjoint(avl_handle* h, const double* x, const double* v, const double* f
         h->have_E = true;
         if ((rc = do_sort(h, false, 1.0))) return done(rc);
         if ((rc = do_recon(h, state(0) + A.st_D))) return done(rc);
-        if ((rc = adj_save(h, state(0), A, f_tmp))) return done(rc);
+        if ((rc = adj_save(h, state(0), A))) return done(rc);
         for (int q = 0; q < s1 - s0; ++q) {
             h->rec_D = state(q + 1) + A.st_D;
             if ((rc = one_step(h))) return done(rc);
-            if ((rc = adj_save(h, state(q + 1), A, f_tmp))) return done(rc);
+            if ((rc = adj_save(h, state(q + 1), A))) return done(rc);
         }
         h->rec_D = nullptr;
         for (int q = s1 - s0 - 1; q >= 0; --q) {
@@ -1596,13 +1598,12 @@ int avl_adjoint(avl_handle* h, const double* x, const double* v, const double* f
             if (launch_field(g, nullptr, mu, h->rho_slices, h->rho, Pmu, h->tw, h->green, h->diag, h->ctr, 0, nullptr,
                              h->flags, h->st) != hipSuccess)
                 return done(AVL_EDEVICE);
-            if (launch_adj_deposit(g, gp, (double*)(S1 + A.st_x), (double*)(S1 + A.st_v), (int*)(S1 + A.st_id),
-                                   f_by_id, S1 + A.st_fg, S1 + A.st_D, Pmu, -1.0, lam_x, lam_v, f_bar, 1, h->st) !=
-                hipSuccess)
-                return done(AVL_EDEVICE);
+            // the states are in identity order, so the deposit reverse (state
+            // step+1) and the push reverse (state step) run as one pass
             const double kick = (step == 0 && h->cfg.first_kick) ? 0.5 : 1.0;
-            if (launch_adj_push(g, (double*)(S0 + A.st_x), (int*)(S0 + A.st_id), (double*)(S0 + A.st_E),
-                                c_full * kick, lam_x, lam_v, lam_x, lam_v, acc, key, h->st) != hipSuccess)
+            if (launch_adj_step_rev(g, gp, (double*)(S1 + A.st_x), (double*)(S1 + A.st_v), f_by_id, S1 + A.st_fg,
+                                    S1 + A.st_D, Pmu, -1.0, (double*)(S0 + A.st_x), (double*)(S0 + A.st_E),
+                                    c_full * kick, lam_x, lam_v, f_bar, acc, key, h->st) != hipSuccess)
                 return done(AVL_EDEVICE);
             if (launch_adj_mu(g, (double*)(S0 + A.st_E), step >= 1 ? dxdt2 : 0.0, acc, key, mu, h->st) != hipSuccess)
                 return done(AVL_EDEVICE);
@@ -1613,8 +1614,8 @@ int avl_adjoint(avl_handle* h, const double* x, const double* v, const double* f
             if (launch_field(g, nullptr, mu, h->rho_slices, h->rho, Pmu, h->tw, h->green, h->diag, h->ctr, 0, nullptr,
                              h->flags, h->st) != hipSuccess)
                 return done(AVL_EDEVICE);
-            if (launch_adj_deposit(g, gp, (double*)(S0 + A.st_x), (double*)(S0 + A.st_v), (int*)(S0 + A.st_id),
-                                   f_by_id, S0 + A.st_fg, S0 + A.st_D, Pmu, -1.0, lam_x, lam_v, f_bar, 0, h->st) !=
+            if (launch_adj_deposit(g, gp, (double*)(S0 + A.st_x), (double*)(S0 + A.st_v), nullptr, f_by_id,
+                                   S0 + A.st_fg, S0 + A.st_D, Pmu, -1.0, lam_x, lam_v, f_bar, 0, h->st) !=
                 hipSuccess)
                 return done(AVL_EDEVICE);
         }

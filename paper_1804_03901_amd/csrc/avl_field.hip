@@ -441,9 +441,13 @@ __global__ void k_to32(Geo g, const double* __restrict__ x, const double* __rest
 }
 
 // FP32 form -> FP64 markers: x = (i0 + 1/2 + a) dx, v = vmin + (j0 + 1/2 + b) dv.
-__global__ void k_to64(Geo g, M32 m, double* __restrict__ x, double* __restrict__ v, double* __restrict__ f)
+// Marker i goes to slot id[i] when id is given (identity order), else to
+// slot i; f is written only when given.
+__global__ void k_to64(Geo g, M32 m, double* __restrict__ x, double* __restrict__ v, double* __restrict__ f,
+                       const int* __restrict__ id)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g.n; i += gridDim.x * blockDim.x) {
+        const int o = id ? id[i] : i;
         const int cell = m.cell[i];
         const int ix = cell & (g.nx - 1);
         const int r = cell >> g.lognx;
@@ -458,10 +462,10 @@ __global__ void k_to64(Geo g, M32 m, double* __restrict__ x, double* __restrict_
         }
         double xx = ((double)ix + 0.5 + (double)m.a[i]) * g.dx;
         if (xx >= g.L) xx -= g.L;
-        x[i] = xx;
+        x[o] = xx;
         for (int d = 0; d < g.vdim; ++d)
-            v[(size_t)d * g.n + i] = g.vmin[d] + ((double)(jp[d] - 1) + 0.5 + (double)m.b[(size_t)d * g.np + i]) * g.dv[d];
-        f[i] = (double)m.f[i];
+            v[(size_t)d * g.n + o] = g.vmin[d] + ((double)(jp[d] - 1) + 0.5 + (double)m.b[(size_t)d * g.np + i]) * g.dv[d];
+        if (f) f[o] = (double)m.f[i];
     }
 }
 
@@ -500,11 +504,30 @@ hipError_t launch_to32(const Geo& g, const double* x, const double* v, const dou
     return hipGetLastError();
 }
 
-hipError_t launch_to64(const Geo& g, M32 m, double* x, double* v, double* f, hipStream_t st)
+hipError_t launch_to64(const Geo& g, M32 m, double* x, double* v, double* f, hipStream_t st, const int* id)
 {
     if (g.n == 0) return hipSuccess;
     int blocks = min((g.n + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_to64, dim3(blocks), dim3(256), 0, st, g, m, x, v, f);
+    hipLaunchKernelGGL(k_to64, dim3(blocks), dim3(256), 0, st, g, m, x, v, f, id);
+    return hipGetLastError();
+}
+
+// FP64 markers in identity order: x and v of marker i go to slot id[i].
+__global__ void k_by_id64(int n, const double* __restrict__ x, const double* __restrict__ v,
+                          const int* __restrict__ id, double* __restrict__ xo, double* __restrict__ vo)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int o = id[i];
+        xo[o] = x[i];
+        vo[o] = v[i];
+    }
+}
+
+hipError_t launch_by_id64(int n, const double* x, const double* v, const int* id, double* xo, double* vo,
+                          hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_by_id64, dim3(min((n + 255) / 256, 8192)), dim3(256), 0, st, n, x, v, id, xo, vo);
     return hipGetLastError();
 }
 
