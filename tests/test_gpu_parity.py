@@ -300,3 +300,79 @@ def test_full_size_bump_on_tail_step(precision, options, weights):
     assert cell <= (TOL64_CELL if precision == avl.AVL_FP64 else tol_f)
     assert nrel(t2n(Dg), Do) <= tol_r
     assert nrel(t2n(rho_g), rho_o) <= tol_r
+
+
+@pytest.mark.parametrize("precision", [avl.AVL_FP64, avl.AVL_FP32])
+@pytest.mark.parametrize("weights", ["flat", "logu"])
+def test_markers_on_grid_nodes(precision, weights):
+    """One marker at every cell centre, where its cloud coincides with the
+    cell (Eq. (reconstruction) with all weight on one corner), plus markers at
+    x = 0 and just below x = L (the periodic wrap decided by rounding).  The
+    oracle is matched; with weights within a factor of two (flat) every cell
+    also returns its own marker's f, with D = 1."""
+    _need_gpu()
+    nx, nv = 64, 32
+    w = inputs.bump_on_tail(nx=nx, nv=nv, ppc=1, seed=21).replace(name=f"nodes_{weights}")
+    g = oracle.Grid.from_workload(w)
+    dx, dv = w.L / nx, (w.vmax[0] - w.vmin[0]) / nv
+    jj, ii = np.meshgrid(np.arange(nv), np.arange(nx), indexing="ij")
+    x = ((ii + 0.5) * dx).ravel()
+    v = (w.vmin[0] + (jj + 0.5) * dv).ravel()
+    rng = np.random.default_rng(5)
+    f = rng.uniform(0.5, 1.0, x.size) if weights == "flat" else np.exp(rng.uniform(np.log(1e-8), 0.0, x.size))
+    # extra markers at the domain edges, weight zero-free but tiny, far from the nodes' f
+    xe = np.array([0.0, np.nextafter(w.L, 0.0), w.L * (1 - 1e-15), 0.5 * dx])
+    ve = w.vmin[0] + (np.array([3, 7, 11, 31]) + 0.5) * dv
+    fe = np.full(4, 1e-3)
+    x, v, f = np.concatenate([x, xe]), np.concatenate([v, ve]), np.concatenate([f, fe])
+    sim, _ = sim_for(w, precision, markers=(x, v.reshape(1, -1), f))
+    xs, vs, fs = (t2n(a) for a in sim.markers())
+    N, D, fo = oracle.reconstruct(g, xs, vs.reshape(1, -1), fs)
+    fg, Dg = (t2n(a) for a in sim.reconstruct(want_D=True))
+    tol = TOL64 if precision == avl.AVL_FP64 else 1e-6
+    print(f"[result] nodes {weights} prec={precision}: f {nrel(fg, fo):.2e} D {nrel(Dg, D):.2e} "
+          f"cell {cell_rel(fg, fo, D):.2e}", flush=True)
+    assert nrel(fg, fo) <= tol and nrel(Dg, D) <= tol
+    if precision == avl.AVL_FP64 and weights == "logu":
+        # A marker on a node is located by x (1/dx) here and by x / dx in the
+        # oracle; the two may round to opposite sides of the node, which
+        # moves a weight of the rounding of the cell coordinate (up to about
+        # nx 2^-52 in x, nv 2^-52 in v) to the other neighbour.  A cell next
+        # to a marker up to 1e8 times heavier sees that relative to its own
+        # f, so the bound is 1e-12 of its f plus that weight times the
+        # heaviest f its cloud neighbourhood holds (a dropped or misplaced
+        # term would be of the order of f itself).
+        fn = f[:nx * nv].reshape(nv, nx)
+        nb = fn.copy()
+        for dj in (-1, 0, 1):
+            for di in (-1, 0, 1):
+                sh = np.roll(fn, di, axis=1)
+                sh = np.roll(sh, dj, axis=0) if dj else sh
+                if dj == 1:
+                    sh[0, :] = 0.0
+                elif dj == -1:
+                    sh[-1, :] = 0.0
+                nb = np.maximum(nb, sh)
+        nb = np.maximum(nb, fe.max())
+        err = np.abs(fg - fo).reshape(nv, nx)
+        bound = 1e-12 * np.abs(fo).reshape(nv, nx) + 4 * (nx + nv) * 2.0 ** -52 * nb
+        print(f"[result] nodes logu: worst err / bound {np.max(err / bound):.2e}", flush=True)
+        assert np.all(err <= bound)
+    else:
+        assert cell_rel(fg, fo, D) <= (TOL64_CELL if precision == avl.AVL_FP64 else 1e-5)
+    if weights == "flat":
+        # cells away from the extra markers: each holds its own marker alone
+        own = np.ones((nv, nx), bool)
+        for xv, vv in zip(xe, ve):
+            i = int(np.floor(xv / dx)) % nx
+            j = int(np.floor((vv - w.vmin[0]) / dv))
+            own[max(j - 1, 0):j + 2, :] &= ~np.isin(np.arange(nx), [(i - 1) % nx, i, (i + 1) % nx])
+        f_own = f[:nx * nv].reshape(nv, nx)
+        if precision == avl.AVL_FP32:
+            f_own = f_own.astype(np.float32).astype(np.float64)
+        rel = np.abs(fg.reshape(nv, nx) - f_own) / f_own
+        print(f"[result] nodes identity: max rel {rel[own].max():.2e}, D-1 {np.abs(Dg.reshape(nv, nx)[own] - 1).max():.2e}",
+              flush=True)
+        assert rel[own].max() <= (1e-13 if precision == avl.AVL_FP64 else 1e-6)
+        assert np.abs(Dg.reshape(nv, nx)[own] - 1.0).max() <= (1e-13 if precision == avl.AVL_FP64 else 1e-6)
+    sim.check()
