@@ -376,3 +376,46 @@ def test_markers_on_grid_nodes(precision, weights):
         assert rel[own].max() <= (1e-13 if precision == avl.AVL_FP64 else 1e-6)
         assert np.abs(Dg.reshape(nv, nx)[own] - 1.0).max() <= (1e-13 if precision == avl.AVL_FP64 else 1e-6)
     sim.check()
+
+
+def test_markers_on_velocity_grid_edges():
+    """Markers whose clouds end exactly on the edges of the velocity grid:
+    at v = vmin - dv/2 (all weight on the row below the grid, lost), just
+    inside it, just inside vmax + dv/2 and exactly on it (the overflow
+    bucket), among ordinary markers; reconstruction and one step against the
+    oracle, and every marker kept."""
+    w = CASES["ragged"]
+    _need_gpu()
+    x, v, f = inputs.markers(w)
+    v = v.copy()
+    dv = (w.vmax[0] - w.vmin[0]) / w.nv[0]
+    lo, hi = w.vmin[0] - 0.5 * dv, w.vmax[0] + 0.5 * dv
+    edge = np.array([lo, np.nextafter(lo, np.inf), lo + 1e-9 * dv, np.nextafter(hi, -np.inf), hi - 1e-9 * dv, hi])
+    k = np.arange(edge.size * 20)
+    v[0, k] = np.repeat(edge, 20)
+    # weights of the tail they now sit in (the smallest present), so that the
+    # rounding of their tiny edge weights is not magnified by a core weight
+    f = f.copy()
+    f[k] = f.min()
+    sim, _ = sim_for(w, markers=(x, v, f))
+    g = oracle.Grid.from_workload(w)
+    xs, vs, fs = (t2n(a) for a in sim.markers())
+    N, D, fo = oracle.reconstruct(g, xs, vs.reshape(1, -1), fs)
+    fg, Dg = (t2n(a) for a in sim.reconstruct(want_D=True))
+    assert nrel(fg, fo) <= TOL64 and nrel(Dg, D) <= TOL64
+    assert cell_rel(fg, fo, D) <= TOL64_CELL
+    E, _ = sim.field()
+    xo, vo, fo1, Do1, rho_o, _, _ = _one_step_oracle(w, xs, vs.reshape(1, -1), fs, t2n(E))
+    sim.step(1)
+    fg, Dg = (t2n(a) for a in sim.reconstruct(want_D=True))
+    _, rho_g = sim.field()
+    print(f"[result] velocity edges: f {nrel(fg, fo1):.1e} cell {cell_rel(fg, fo1, Do1):.1e} "
+          f"rho {nrel(t2n(rho_g), rho_o):.1e}", flush=True)
+    assert nrel(fg, fo1) <= TOL64 and nrel(Dg, Do1) <= TOL64
+    assert cell_rel(fg, fo1, Do1) <= TOL64_CELL
+    assert nrel(t2n(rho_g), rho_o) <= TOL64
+    xg, vg, _ = (t2n(a) for a in sim.markers())
+    assert xg.size == x.size
+    og, oo = np.lexsort((vg[0], xg)), np.lexsort((vo[0], xo))
+    assert np.max(np.abs(vg[0][og] - vo[0][oo])) <= TOL64 * (w.vmax[0] - w.vmin[0])
+    sim.check()
