@@ -378,14 +378,19 @@ def test_markers_on_grid_nodes(precision, weights):
     sim.check()
 
 
-def test_markers_on_velocity_grid_edges():
+@pytest.mark.parametrize("precision", [avl.AVL_FP64, avl.AVL_FP32])
+def test_markers_on_velocity_grid_edges(precision):
     """Markers whose clouds end exactly on the edges of the velocity grid:
     at v = vmin - dv/2 (all weight on the row below the grid, lost), just
     inside it, just inside vmax + dv/2 and exactly on it (the overflow
-    bucket), among ordinary markers; reconstruction and one step against the
-    oracle, and every marker kept."""
+    bucket; in the FP32 form those keep stored cell indices), among ordinary
+    markers; reconstruction and one step against the oracle, and every
+    marker kept.  FP32 form: the FP32 push's bounds (1e-5 on f, offsets to
+    1e-5 of a cell)."""
     w = CASES["ragged"]
     _need_gpu()
+    fp64 = precision == avl.AVL_FP64
+    tol_f, tol_cell, tol_rho = (TOL64, TOL64_CELL, TOL64) if fp64 else (1e-5, 1e-5, 1e-6)
     x, v, f = inputs.markers(w)
     v = v.copy()
     dv = (w.vmax[0] - w.vmin[0]) / w.nv[0]
@@ -397,25 +402,28 @@ def test_markers_on_velocity_grid_edges():
     # rounding of their tiny edge weights is not magnified by a core weight
     f = f.copy()
     f[k] = f.min()
-    sim, _ = sim_for(w, markers=(x, v, f))
+    sim, _ = sim_for(w, precision=precision, markers=(x, v, f))
     g = oracle.Grid.from_workload(w)
     xs, vs, fs = (t2n(a) for a in sim.markers())
     N, D, fo = oracle.reconstruct(g, xs, vs.reshape(1, -1), fs)
     fg, Dg = (t2n(a) for a in sim.reconstruct(want_D=True))
-    assert nrel(fg, fo) <= TOL64 and nrel(Dg, D) <= TOL64
-    assert cell_rel(fg, fo, D) <= TOL64_CELL
+    assert nrel(fg, fo) <= tol_f and nrel(Dg, D) <= tol_f
+    assert cell_rel(fg, fo, D) <= tol_cell
     E, _ = sim.field()
     xo, vo, fo1, Do1, rho_o, _, _ = _one_step_oracle(w, xs, vs.reshape(1, -1), fs, t2n(E))
     sim.step(1)
     fg, Dg = (t2n(a) for a in sim.reconstruct(want_D=True))
     _, rho_g = sim.field()
-    print(f"[result] velocity edges: f {nrel(fg, fo1):.1e} cell {cell_rel(fg, fo1, Do1):.1e} "
+    print(f"[result] velocity edges prec={precision}: f {nrel(fg, fo1):.1e} cell {cell_rel(fg, fo1, Do1):.1e} "
           f"rho {nrel(t2n(rho_g), rho_o):.1e}", flush=True)
-    assert nrel(fg, fo1) <= TOL64 and nrel(Dg, Do1) <= TOL64
-    assert cell_rel(fg, fo1, Do1) <= TOL64_CELL
-    assert nrel(t2n(rho_g), rho_o) <= TOL64
+    assert nrel(fg, fo1) <= tol_f and nrel(Dg, Do1) <= tol_f
+    assert cell_rel(fg, fo1, Do1) <= tol_cell
+    assert nrel(t2n(rho_g), rho_o) <= tol_rho
     xg, vg, _ = (t2n(a) for a in sim.markers())
     assert xg.size == x.size
-    og, oo = np.lexsort((vg[0], xg)), np.lexsort((vo[0], xo))
-    assert np.max(np.abs(vg[0][og] - vo[0][oo])) <= TOL64 * (w.vmax[0] - w.vmin[0])
+    if fp64:
+        og, oo = np.lexsort((vg[0], xg)), np.lexsort((vo[0], xo))
+        assert np.max(np.abs(vg[0][og] - vo[0][oo])) <= TOL64 * (w.vmax[0] - w.vmin[0])
+    else:
+        assert np.max(np.abs(np.sort(vg[0]) - np.sort(vo[0]))) <= 1e-5 * w.dv(0)
     sim.check()
