@@ -249,7 +249,8 @@ __device__ __forceinline__ int bucket32(const Geo& g, int cell)
     // jrange is a power of two (a wave-uniform shift, no integer division)
     int jx = (r & (g.jrange - 1)) - g.jpad;
     int yz = r >> __builtin_ctz(g.jrange);
-    if (cell < 0 || jx < 0 || jx > g.nv[0]) return g.nb;
+    // a (vy, vz) row index past the last plane has no bucket either
+    if (cell < 0 || jx < 0 || jx > g.nv[0] || yz >= (g.nv[1] + 1) * (g.nv[2] + 1)) return g.nb;
     return (yz * (g.nv[0] + 1) + jx) * g.nx + ix;
 }
 

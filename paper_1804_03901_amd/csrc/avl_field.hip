@@ -428,9 +428,19 @@ __global__ void k_to32(Geo g, const double* __restrict__ x, const double* __rest
             cell = jp[0] * g.nx + ix;
         } else {
             int jj = jp[0] + g.jpad;
-            if (jj < 0 || jj >= g.jrange || jp[1] < 0 || jp[1] > g.nv[1] || jp[2] < 0 || jp[2] > g.nv[2]) {
+            const bool in_yz = jp[1] >= 0 && jp[1] <= g.nv[1] && jp[2] >= 0 && jp[2] <= g.nv[2];
+            if (jj < 0 || jj >= g.jrange || !in_yz) {
                 atomicOr(flags, FLAG_RANGE);
                 jj = min(max(jj, 0), g.jrange - 1);
+                if (!in_yz) {
+                    // no cell index holds a vy or vz cloud off the grid: store
+                    // one of the overflow bucket (vy, vz clamped, the x-velocity
+                    // index below the grid), so that every kernel stays inside
+                    // its arrays until the flag is reported
+                    jp[1] = min(max(jp[1], 0), g.nv[1]);
+                    jp[2] = min(max(jp[2], 0), g.nv[2]);
+                    jj = 0;
+                }
             }
             cell = ((jp[2] * (g.nv[1] + 1) + jp[1]) * g.jrange + jj) * g.nx + ix;
         }

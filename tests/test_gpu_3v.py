@@ -260,3 +260,93 @@ def test_full_size_two_stream_3v_sampled_planes(precision):
     assert abs(W_g - W_o) <= TOL64 * W_o
     sim.check()
     sim.close()
+
+
+def _edge_markers(w, off_grid):
+    """Markers of w with groups moved onto the lower and upper cloud edges of
+    each velocity axis (vmin - dv/2, vmax + dv/2, and just inside them) and,
+    with off_grid, groups far outside in vy and vz; the moved markers carry
+    the smallest weight present, so that the rounding of their edge weights
+    is not magnified by a core weight.  Without off_grid the vy and vz edges
+    are taken 1e-6 dv inside (an exact edge, or an offset within an FP32
+    rounding of 1, may land outside, which the FP32 form cannot hold for those
+    components; x-velocity clouds may leave the grid in both forms)."""
+    x, v, f = inputs.markers(w)
+    v, f = v.copy(), f.copy()
+    k = 0
+    for d in range(3):
+        dv = (w.vmax[d] - w.vmin[d]) / w.nv[d]
+        lo, hi = w.vmin[d] - 0.5 * dv, w.vmax[d] + 0.5 * dv
+        if off_grid or d == 0:
+            edges = [lo, np.nextafter(lo, np.inf), np.nextafter(hi, -np.inf), hi]
+        else:
+            edges = [lo + 1e-6 * dv, hi - 1e-6 * dv]
+        for e in edges:
+            v[d, k:k + 16] = e
+            f[k:k + 16] = f.min()
+            k += 16
+    if off_grid:
+        v[1, k:k + 16] = w.vmax[1] + 3.0      # outside in vy and vz: no weight anywhere
+        v[2, k + 16:k + 32] = w.vmin[2] - 3.0
+        f[k:k + 32] = f.min()
+    return x, v, f
+
+
+@pytest.mark.parametrize("precision", [avl.AVL_FP64, avl.AVL_FP32])
+def test_3v_markers_on_velocity_grid_edges(precision):
+    """Markers whose clouds end exactly on, or just inside, the edges of each
+    velocity axis (and, in the FP64 form, vy and vz clouds off the grid),
+    among ordinary markers: reconstruction, rho and one step against the
+    oracle, every marker kept."""
+    w = CASES["strips"]
+    fp64 = precision == avl.AVL_FP64
+    x, v, f = _edge_markers(w, off_grid=fp64)
+    tol_f, tol_cell, tol_rho = (TOL64, TOL64_CELL, TOL64) if fp64 else (1e-5, 1e-5, 1e-6)
+    sim, _ = sim_for(w, precision=precision, markers=(x, v, f))
+    g = oracle.Grid.from_workload(w)
+    xs, vs, fs = (t2n(a) for a in sim.markers())
+    vs = vs.reshape(3, -1)
+    _, D, fo = oracle.reconstruct(g, xs, vs, fs)
+    fg, Dg = (t2n(a) for a in sim.reconstruct(want_D=True))
+    assert nrel(fg, fo) <= tol_f and nrel(Dg, D) <= tol_f
+    assert cell_rel(fg, fo, D) <= tol_cell
+    E = t2n(sim.field()[0])
+    xo, vo = oracle.push(g, xs, vs, E)
+    _, Do, fo = oracle.reconstruct(g, xo, vo, fs)
+    rho_o, _, _ = oracle.moments(g, fo)
+    sim.step(1)
+    fg, Dg = (t2n(a) for a in sim.reconstruct(want_D=True))
+    _, rho_g = sim.field()
+    print(f"[result] 3v velocity edges prec={precision}: f {nrel(fg, fo):.1e} cell {cell_rel(fg, fo, Do):.1e} "
+          f"rho {nrel(t2n(rho_g), rho_o):.1e}", flush=True)
+    # after an FP32 push the offsets of markers kicked off an x-velocity cloud
+    # edge are tiny numbers held to FP32 absolute precision, so cells they
+    # dominate carry that relative to their own f: normwise there, as in the
+    # FP32 step test above; cell by cell for the FP64 path
+    assert nrel(fg, fo) <= tol_f
+    if fp64:
+        assert cell_rel(fg, fo, Do) <= tol_cell
+    assert nrel(t2n(rho_g), rho_o) <= tol_rho
+    xg, vg, _ = (t2n(a) for a in sim.markers())
+    assert xg.size == x.size
+    vg = vg.reshape(3, -1)
+    for d in range(3):
+        tol_v = TOL64 * (w.vmax[d] - w.vmin[d]) if fp64 else 1e-5 * w.dv(d)
+        assert np.max(np.abs(np.sort(vg[d]) - np.sort(vo[d]))) <= tol_v, d
+    sim.check()
+
+
+def test_3v_fp32_off_grid_vy_vz_is_reported():
+    """The FP32 form cannot hold a vy or vz cloud off the velocity grid (those
+    components never move, and the cell index has no room for them): such
+    markers are stored in the overflow bucket, every kernel stays inside its
+    arrays, and avl_check reports AVL_EINTERNAL, as the header states."""
+    w = CASES["strips"]
+    x, v, f = _edge_markers(w, off_grid=True)
+    sim, _ = sim_for(w, precision=avl.AVL_FP32, markers=(x, v, f))
+    sim.reconstruct()
+    sim.step(2)
+    torch.cuda.synchronize()
+    with pytest.raises(avl.AvlError) as e:
+        sim.check()
+    assert e.value.status == -8
