@@ -73,7 +73,10 @@ typedef enum {
  *            solve stay FP64.  In 1D-3V the vy and vz clouds of every marker
  *            must touch the velocity grid (they never move; a marker outside
  *            raises AVL_EINTERNAL at the next avl_check), and the x-velocity
- *            index may leave the grid by at most 32 rows. */
+ *            index may leave the grid by at most 32 rows; in 1D-1V the
+ *            velocity index may leave it by up to 2^(30 - log2 nx) - 2 rows.
+ *            Markers beyond these ranges are clamped into them and flagged
+ *            (AVL_EINTERNAL at the next avl_check). */
 typedef enum { AVL_FP64 = 0, AVL_FP32 = 1 } avl_precision;
 
 /* Options.  The reconstruction sums, per run of markers sharing a cell, the

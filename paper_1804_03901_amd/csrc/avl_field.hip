@@ -414,10 +414,19 @@ __global__ void k_to32(Geo g, const double* __restrict__ x, const double* __rest
         if (a >= 1.0f) { a = 0.0f; i0 += 1; }
         const int ix = i0 & (g.nx - 1);
         int jp[3];
+        // velocity rows a cell index holds (the push clamps to the same range)
+        const double lim = (double)(1 << (30 - g.lognx)) - 2.0;
         for (int d = 0; d < g.vdim; ++d) {
             double t = (v[(size_t)d * g.n + i] - g.vmin[d]) * g.inv_dv[d] - 0.5;
             double ft = floor(t);
             float b = (float)(t - ft);
+            if (!(ft >= -lim && ft <= lim)) {
+                // beyond what the form holds: clamped before the integer
+                // conversion (which would overflow) and flagged
+                atomicOr(flags, FLAG_RANGE);
+                ft = fmin(fmax(ft, -lim), lim);
+                b = 0.0f;
+            }
             int j0 = (int)ft;
             if (b >= 1.0f) { b = 0.0f; j0 += 1; }
             m.b[(size_t)d * g.np + i] = b;

@@ -158,3 +158,39 @@ def test_fp32_export_round_trip():
     b = np.lexsort((t2n(v2)[0], t2n(x2)))
     assert np.max(np.abs(t2n(x)[a] - t2n(x2)[b])) <= 1e-12 * w.L
     assert np.max(np.abs(t2n(v)[0][a] - t2n(v2)[0][b])) <= 1e-12 * w.dv(0)
+
+
+def test_fp32_velocity_range_of_the_form():
+    """The FP32 form holds velocity rows up to 2^(30 - log2 nx) - 2 from the
+    grid: markers within that range are kept with their velocities (to FP32
+    offset resolution); any finite velocity beyond it is clamped before the
+    integer conversion and reported by avl_check (AVL_EINTERNAL), with no
+    kernel leaving its arrays."""
+    w = CASES["ragged"]
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    x, v, f = inputs.markers(w)
+    dv = w.dv(0)
+    lim_rows = 2 ** (30 - int(np.log2(w.nx))) - 2
+    far_ok = np.array([w.vmax[0] + 0.5 * lim_rows * dv, w.vmin[0] - 0.5 * lim_rows * dv])
+    v = v.copy()
+    v[0, :2] = far_ok
+    print(f"[case] {w.name} far velocities {far_ok}", flush=True)
+    sim = avl.Simulation(w, x, v.reshape(-1), f, precision=avl.AVL_FP32)
+    sim.step(2)
+    sim.check()
+    _, vg, _ = (t2n(a) for a in sim.markers())
+    for u in far_ok:
+        assert np.min(np.abs(vg[0] - u)) <= 1e-6 * abs(u), u
+    sim.close()
+    for bad in (1e30, -1e30, w.vmax[0] + 4.0 * lim_rows * dv):
+        v2 = v.copy()
+        v2[0, 5] = bad
+        print(f"[case] {w.name} velocity {bad}", flush=True)
+        sim = avl.Simulation(w, x, v2.reshape(-1), f, precision=avl.AVL_FP32)
+        sim.step(1)
+        torch.cuda.synchronize()
+        with pytest.raises(avl.AvlError) as e:
+            sim.check()
+        assert e.value.status == -8
+        sim.close()
