@@ -427,3 +427,36 @@ def test_markers_on_velocity_grid_edges(precision):
     else:
         assert np.max(np.abs(np.sort(vg[0]) - np.sort(vo[0]))) <= 1e-5 * w.dv(0)
     sim.check()
+
+
+@pytest.mark.parametrize("precision", [avl.AVL_FP64, avl.AVL_FP32])
+def test_zero_and_signed_weights(precision):
+    """All weights zero: every run's largest |f| is zero, f_g = 0 exactly and D
+    is unchanged.  Weights of both signs (a perturbation-like f): the sums
+    round every term down onto their grid whatever its sign; against the
+    oracle normwise, and cell by cell where |f| is not cancelled below a
+    thousandth of its largest value."""
+    w = CASES["ragged"]
+    x, v, _ = inputs.markers(w)
+    g = oracle.Grid.from_workload(w)
+    tol = TOL64 if precision == avl.AVL_FP64 else 1e-5
+    sim, _ = sim_for(w, precision=precision, markers=(x, v, np.zeros(x.size)))
+    fg, Dg = (t2n(a) for a in sim.reconstruct(want_D=True))
+    xs, vs, fs = (t2n(a) for a in sim.markers())
+    _, D, _ = oracle.reconstruct(g, xs, vs.reshape(1, -1), fs)
+    assert np.all(fg == 0.0) and nrel(Dg, D) <= tol
+    sim.step(2)
+    assert np.all(t2n(sim.reconstruct()) == 0.0)
+    sim.check()
+    rng = np.random.default_rng(3)
+    f = rng.normal(size=x.size) * np.exp(rng.uniform(-6.0, 0.0, x.size))
+    sim, _ = sim_for(w, precision=precision, markers=(x, v, f))
+    xs, vs, fs = (t2n(a) for a in sim.markers())
+    _, D, fo = oracle.reconstruct(g, xs, vs.reshape(1, -1), fs)
+    fg, Dg = (t2n(a) for a in sim.reconstruct(want_D=True))
+    m = (D >= 0.1) & (np.abs(fo) >= 1e-3 * np.max(np.abs(fo)))
+    rel = np.max(np.abs(fg[m] - fo[m]) / np.abs(fo[m]))
+    print(f"[result] signed weights prec={precision}: f {nrel(fg, fo):.1e} cell {rel:.1e}", flush=True)
+    assert nrel(fg, fo) <= tol and nrel(Dg, D) <= tol
+    assert rel <= (1e-10 if precision == avl.AVL_FP64 else 1e-4)
+    sim.check()
