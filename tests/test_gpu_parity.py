@@ -460,3 +460,42 @@ def test_zero_and_signed_weights(precision):
     assert nrel(fg, fo) <= tol and nrel(Dg, D) <= tol
     assert rel <= (1e-10 if precision == avl.AVL_FP64 else 1e-4)
     sim.check()
+
+
+@pytest.mark.parametrize("precision", [avl.AVL_FP64, avl.AVL_FP32])
+def test_large_kicks_step(precision):
+    """A strongly perturbed plasma on a coarse step (density 1 + 0.9 cos kx,
+    dt = 2, 256 velocity cells): kicks of over ten velocity cells and drifts
+    of tens of x cells a step, so many markers land outside the sort's LDS
+    window and take its one-slot-at-a-time path.  One step against the
+    oracle from the exported state (FP32 form: its push's bounds)."""
+    w = inputs.landau_small().replace(name="large_kicks", mode_amplitude=0.9, dt=2.0, nv=(256, 1, 1))
+    fp64 = precision == avl.AVL_FP64
+    sim, _ = sim_for(w, precision=precision)
+    # the first step: the loaded field is the strongest (plasma oscillation)
+    x, v, f = (t2n(a) for a in sim.markers())
+    E = t2n(sim.field()[0])
+    dv = w.dv(0)
+    kick = np.max(np.abs(E)) * w.dt / dv
+    print(f"[case] large kicks: max |kick| {kick:.1f} cells", flush=True)
+    assert kick > 8.0
+    xo, vo, fo, Do, rho_o, _, _ = _one_step_oracle(w, x, v.reshape(1, -1), f, E)
+    sim.step(1)
+    fg, Dg = (t2n(a) for a in sim.reconstruct(want_D=True))
+    _, rho_g = sim.field()
+    tol_f, tol_rho = (TOL64, TOL64) if fp64 else (1e-5, 1e-6)
+    print(f"[result] large kicks prec={precision}: f {nrel(fg, fo):.1e} cell {cell_rel(fg, fo, Do):.1e} "
+          f"rho {nrel(t2n(rho_g), rho_o):.1e}", flush=True)
+    assert nrel(fg, fo) <= tol_f and nrel(Dg, Do) <= tol_f
+    assert cell_rel(fg, fo, Do) <= (TOL64_CELL if fp64 else 1e-5)
+    assert nrel(t2n(rho_g), rho_o) <= tol_rho
+    xg, vg, _ = (t2n(a) for a in sim.markers())
+    if fp64:
+        og, oo = np.lexsort((vg[0], xg)), np.lexsort((vo[0], xo))
+        assert np.max(np.abs(xg[og] - xo[oo])) <= TOL64 * w.L
+        assert np.max(np.abs(vg[0][og] - vo[0][oo])) <= TOL64 * (w.vmax[0] - w.vmin[0])
+    else:
+        # the FP32 offset update b + e rounds at the FP32 spacing of |e|, the
+        # kick in cells: K 2^-23 of a cell for a kick of K cells
+        assert np.max(np.abs(np.sort(vg[0]) - np.sort(vo[0]))) <= (1e-5 + 4 * kick * 2.0 ** -24) * dv
+    sim.check()
