@@ -621,12 +621,12 @@ __device__ __forceinline__ void scatter_tile(const Geo& g, const SortSmem<PREC>&
 // ovf >= 0: implied cells, stored only at positions >= ovf
 template <int PREC, int VD>
 __device__ __forceinline__ void load_tile(const typename MarkersOf<PREC>::T& src, const Geo& g, Pay<PREC, VD>* p,
-                                          int base, int last, int ovf = -1)
+                                          int base, int last, int ovf = -1, bool with_f = true)
 {
 #pragma unroll
     for (int k = 0; k < kSortMPT; ++k) {
         const int i = min(base + k * kSortThreads + (int)threadIdx.x, last);
-        p[k].load(src, g, i, true, VD, ovf < 0 || i >= ovf);
+        p[k].load(src, g, i, with_f, VD, ovf < 0 || i >= ovf);
     }
 }
 
@@ -699,10 +699,18 @@ __device__ __forceinline__ void scatter_tiled(const Geo& g, typename MarkersOf<P
     int fl = 0;
     Pay<PREC, VD> p[kSortMPT], q[kSortMPT];
     int t = blockIdx.x;
-    load_tile<PREC, VD>(src, g, p, t * kSortTile, min(t * kSortTile + kSortTile, g.n) - 1, ovf);
+    // f is only needed when the marker is stored: each tile's f is loaded
+    // when its processing starts, not with the tile loaded ahead
+    load_tile<PREC, VD>(src, g, p, t * kSortTile, min(t * kSortTile + kSortTile, g.n) - 1, ovf, ID);
     for (; t < ntiles; t += gridDim.x) {
         const int tn = t + gridDim.x;
-        if (tn < ntiles) load_tile<PREC, VD>(src, g, q, tn * kSortTile, min(tn * kSortTile + kSortTile, g.n) - 1, ovf);
+        if constexpr (PREC == 1 && !ID) {
+            const int last = min(t * kSortTile + kSortTile, g.n) - 1;
+#pragma unroll
+            for (int k = 0; k < kSortMPT; ++k) p[k].f = src.f[min(t * kSortTile + k * kSortThreads + (int)threadIdx.x, last)];
+        }
+        if (tn < ntiles)
+            load_tile<PREC, VD>(src, g, q, tn * kSortTile, min(tn * kSortTile + kSortTile, g.n) - 1, ovf, ID);
         scatter_tile<PREC, VD, PUSH, IMPL>(g, sm, p, dst, dtk, bk, offsets, counts, t * kSortTile,
                                            min(t * kSortTile + kSortTile, g.n) - 1, s_b, &s_lo, &s_nb, fl, pv, ovf,
                                            s_aux, g.sbins);
