@@ -261,36 +261,79 @@ __device__ __forceinline__ int bucket32(const Geo& g, int cell)
 // sE[i] holds the kick in units of dv at cell centre i, e_i = (q/m) E_i dt /
 // dv (times the kick fraction), and its forward difference e_{i+1} - e_i
 // (periodic), so the linear gather is one LDS read and one multiply-add.
+// The push of push32 in three parts, so that a pass needing only the new
+// bucket can take them over a group of markers at once.  kick32: the gather
+// and the velocity update, giving the column ix, the new x-velocity row jx
+// (unbounded), the (vy, vz) plane index and the offset bn in [0, 1).
 template <int VD>
-__device__ __forceinline__ void push32(const Geo& g, const float2* sE, const RowShift* rows,
-                                       int& cell, float& a, float& b, int& flags)
+__device__ __forceinline__ void kick32(const Geo& g, const float2* sE, int cell, float a, float b,
+                                       int& ix, int& jx, int& rest, float& bn)
 {
-    int ix = cell & (g.nx - 1);
-    int r = cell >> g.lognx;
-    int jx, rest;
+    ix = cell & (g.nx - 1);
+    const int r = cell >> g.lognx;
     if (VD == 1) { jx = r; rest = 0; }
     else { jx = (r & (g.jrange - 1)) - g.jpad; rest = r >> __builtin_ctz(g.jrange); }
     const float2 e = sE[ix];
-    float bn = b + (e.x + a * e.y);
-    float fl = floorf(bn);
+    bn = b + (e.x + a * e.y);
+    const float fl = floorf(bn);
     jx += (int)fl;
     bn -= fl;
     if (bn >= 1.0f) { bn -= 1.0f; jx += 1; }
-    // rows inside the table take its FP64-built shift, rows beyond it the FP32
-    // formula; both are formed and one selected, without a branch
-    const bool in_table = jx >= 0 && jx <= g.nv[0];
-    const RowShift rs = rows[min(max(jx, 0), g.nv[0])];
+}
+
+// The x shift of row jx in FP32 (rows beyond the FP64-built table).
+__device__ __forceinline__ void row_shift32(const Geo& g, int jx, int& whole, float& frac)
+{
     const float P = ((float)(jx - 1) + g.c0f) * g.gam;
     const float Pf = floorf(P);
-    const int whole = in_table ? rs.whole : (int)Pf;
-    const float frac = in_table ? rs.frac : P - Pf;
+    whole = (int)Pf;
+    frac = P - Pf;
+}
+
+// The drift: the new column from a, the row's shift and bn; a becomes the new
+// offset in [0, 1).
+__device__ __forceinline__ int drift32(const Geo& g, int ix, float& a, float bn, int whole, float frac)
+{
     float an = a + frac + bn * g.gam;
     float ca = floorf(an);
     an -= ca;
     if (an >= 1.0f) { an -= 1.0f; ca += 1.0f; }
-    ix = (ix + whole + (int)ca) & (g.nx - 1);
+    a = an;
+    return (ix + whole + (int)ca) & (g.nx - 1);
+}
+
+// The largest x-velocity row of a 1D-1V cell index: rows up to it keep
+// cell = row * nx + column inside 32 bits; rows beyond are clamped to it and
+// flagged.
+__device__ __forceinline__ int row_limit32(const Geo& g) { return 1 << (30 - g.lognx); }
+
+// Gather + kick + drift of one FP32-form marker.  Velocity moves in units of
+// dv (b carries into the dual row), position in units of dx (a carries into
+// the column, with periodic wrap); the large per-row part of the x shift comes
+// from the FP64-built table so no absolute coordinate is ever held in FP32.
+// sE[i] holds the kick in units of dv at cell centre i, e_i = (q/m) E_i dt /
+// dv (times the kick fraction), and its forward difference e_{i+1} - e_i
+// (periodic), so the linear gather is one LDS read and one multiply-add.
+template <int VD>
+__device__ __forceinline__ void push32(const Geo& g, const float2* sE, const RowShift* rows,
+                                       int& cell, float& a, float& b, int& flags)
+{
+    int ix, jx, rest;
+    float bn;
+    kick32<VD>(g, sE, cell, a, b, ix, jx, rest, bn);
+    // rows inside the table take its FP64-built shift, rows beyond it the FP32
+    // formula; both are formed and one selected, without a branch
+    const bool in_table = jx >= 0 && jx <= g.nv[0];
+    const RowShift rs = rows[min(max(jx, 0), g.nv[0])];
+    int wf;
+    float ff;
+    row_shift32(g, jx, wf, ff);
+    const int whole = in_table ? rs.whole : wf;
+    const float frac = in_table ? rs.frac : ff;
+    float an = a;
+    ix = drift32(g, ix, an, bn, whole, frac);
     if (VD == 1) {
-        const int lim = (1 << (30 - g.lognx));
+        const int lim = row_limit32(g);
         const int jc = min(max(jx, -lim), lim);
         if (jc != jx) flags |= FLAG_RANGE;
         cell = (int)((unsigned)jc << g.lognx) + ix;
@@ -304,6 +347,45 @@ __device__ __forceinline__ void push32(const Geo& g, const float2* sE, const Row
     if (!(an + bn == an + bn)) flags |= FLAG_NONFINITE;
     a = an;
     b = bn;
+}
+
+// The new buckets of K 1D-1V FP32-form markers after push32, without the
+// markers themselves or the flags (for a pass whose markers are pushed again,
+// with the same field, by a pass that raises them).  Every marker reads the
+// table's row shift; the FP32 formula is formed only in a branch, which a
+// wave enters when one of its markers lies beyond the table.  The bucket is
+// bucket32 of push32's clamped cell index, bit for bit.
+template <int K>
+__device__ __forceinline__ void push32_buckets(const Geo& g, const float2* sE, const RowShift* rows,
+                                               const int* cell, const float* a, const float* b, int* bkt)
+{
+    int ix[K], jx[K], whole[K];
+    float bn[K], frac[K];
+    bool beyond = false;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        int rest;
+        kick32<1>(g, sE, cell[k], a[k], b[k], ix[k], jx[k], rest, bn[k]);
+        const RowShift rs = rows[min(max(jx[k], 0), g.nv[0])];
+        whole[k] = rs.whole;
+        frac[k] = rs.frac;
+        beyond |= !(jx[k] >= 0 && jx[k] <= g.nv[0]);
+    }
+    if (beyond) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (!(jx[k] >= 0 && jx[k] <= g.nv[0])) row_shift32(g, jx[k], whole[k], frac[k]);
+    }
+    const int lim = row_limit32(g);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        float an = a[k];
+        const int nix = drift32(g, ix[k], an, bn[k], whole[k], frac[k]);
+        // rows below 0 and from nrow on have no bucket; the lower clamp of
+        // push32 cannot bring a row into range, the upper one can
+        const int jc = min(jx[k], lim);
+        bkt[k] = (unsigned)jc < (unsigned)g.nrow ? (int)((unsigned)jc << g.lognx) + nix : g.nb;
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -411,13 +411,30 @@ __device__ __forceinline__ void count_tile(const Geo& g, const SortSmem<PREC>& s
     if (threadIdx.x < 8) s_tile[threadIdx.x] = 0;
     __syncthreads();
     int bkt[K];
+    if constexpr (PUSH && PREC == 1 && VD == 1) {
+        // 1D-1V FP32 form: only the new buckets; past the last marker the
+        // group holds copies of it, pushed too (the markers' LDS round trips
+        // interleave) and not counted.  The flags are raised by the scatter,
+        // which pushes the same markers with the same field.
+        int c[K];
+        float a[K], b[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        // FP32 form: past the last marker the group holds copies of it, and
-        // pushing them too lets the compiler interleave the markers' LDS
-        // round trips; they are not counted
-        if (PUSH && (PREC == 1 || first + k <= last)) grp.p[k].push(g, sm.sE, sm.sRow, dtk, bk, fl);
-        bkt[k] = first + k <= last ? grp.p[k].bucket(g) : -1;
+        for (int k = 0; k < K; ++k) {
+            c[k] = grp.p[k].cell;
+            a[k] = grp.p[k].a;
+            b[k] = grp.p[k].b[0];
+        }
+        push32_buckets<K>(g, sm.sE, sm.sRow, c, a, b, bkt);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (first + k > last) bkt[k] = -1;
+    } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            // FP32 form: as above, copies of the last marker are pushed too
+            if (PUSH && (PREC == 1 || first + k <= last)) grp.p[k].push(g, sm.sE, sm.sRow, dtk, bk, fl);
+            bkt[k] = first + k <= last ? grp.p[k].bucket(g) : -1;
+        }
     }
     Agg<K> ag;
     ag.build(bkt);
@@ -502,7 +519,7 @@ __global__ __launch_bounds__(kSortThreads) void k_count(Geo g, typename MarkersO
 // ... (one block per resident slot), so the field and drift table are staged
 // once per block instead of once per tile.
 template <int PREC, int VD, bool PUSH, bool IMPL>
-__global__ __launch_bounds__(kSortThreads) void k_count_tiled(Geo g, typename MarkersOf<PREC>::T m,
+__global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_count_tiled(Geo g, typename MarkersOf<PREC>::T m,
                                                          const double* __restrict__ E,
                                                          const RowShift* __restrict__ rows_g,
                                                          double dtk, float bk,
