@@ -220,13 +220,35 @@ struct Prev {
 // kSortThreads SL ints of LDS, free on entry) and gets their buckets in bk[]
 // (undefined past end); with WRITE they are also left in map for other
 // threads, after a barrier.  s_aux: kSortThreads / kWave + 1 ints of LDS.
-template <int SL, bool WRITE>
+// Run offsets of tile_buckets' first pass, loaded ahead of the tile: b0, the
+// run that holds the tile's first position, and the bounds of run b0 + 1 + t
+// for thread t (zero past the last run).
+struct TbAhead {
+    int b0, lo, hi;
+};
+
+__device__ __forceinline__ int tile_first_run(const Prev& pv, int base) { return pv.tfirst[base >> kTfLog]; }
+
+__device__ __forceinline__ TbAhead tile_runs_ahead(const Geo& g, const Prev& pv, int b0)
+{
+    TbAhead a{b0, 0, 0};
+    // clamped: tiles past the start of the overflow run load this too
+    const int b = min(max(b0, 0), g.nb) + 1 + (int)threadIdx.x;
+    if (b < g.nb) {
+        a.lo = pv.off[b];
+        a.hi = pv.off[b + 1];
+    }
+    return a;
+}
+
+// AHEAD: the first pass takes b0 and its offsets from ah instead of loading them.
+template <int SL, bool WRITE, bool AHEAD = false>
 __device__ __forceinline__ void tile_buckets(const Geo& g, const Prev& pv, int base, int end, int* map, int* s_aux,
-                                             int (&bk)[SL])
+                                             int (&bk)[SL], const TbAhead& ah = TbAhead{0, 0, 0})
 {
     static_assert(SL % 4 == 0, "slots are cleared and read as 16-byte vectors");
     const int tid = threadIdx.x;
-    const int b0 = pv.tfirst[base >> kTfLog];          // the run that holds position base
+    const int b0 = AHEAD ? ah.b0 : tile_first_run(pv, base);   // the run that holds position base
     // the LDS is the previous tile's histogram, which its last stores may
     // still be reading (a block walks several tiles)
     __syncthreads();
@@ -239,8 +261,14 @@ __device__ __forceinline__ void tile_buckets(const Geo& g, const Prev& pv, int b
         const int b = bs + tid;
         int lo = end;
         if (b < g.nb) {
-            lo = pv.off[b];
-            const int hi = pv.off[b + 1];
+            int hi;
+            if (AHEAD && bs == b0 + 1) {
+                lo = ah.lo;
+                hi = ah.hi;
+            } else {
+                lo = pv.off[b];
+                hi = pv.off[b + 1];
+            }
             if (lo < hi && lo > base && lo < end) map[lo - base] = b;
         }
         if (tid == kSortThreads - 1) s_aux[kSortThreads / kWave] = (b < g.nb && lo < end) ? 1 : 0;
@@ -380,11 +408,11 @@ struct Agg {
 // One tile of the count pass: the thread's group of K consecutive markers
 // [first, first+K) of the tile [base, last] is in grp (previous order), the
 // field and drift table staged in LDS.
-template <int PREC, int VD, bool PUSH, bool IMPL>
+template <int PREC, int VD, bool PUSH, bool IMPL, bool AHEAD = false>
 __device__ __forceinline__ void count_tile(const Geo& g, const SortSmem<PREC>& sm, Group<PREC, VD, count_mpt<PREC>()>& grp,
                                            double dtk, float bk, int* __restrict__ counts, int* __restrict__ tsum,
                                            int base, int last, int* s_b, int* s_lo, int* s_nb, int* s_tile, int& fl,
-                                           const Prev& pv, int ovf, int* s_aux)
+                                           const Prev& pv, int ovf, int* s_aux, const TbAhead& ah = TbAhead{0, 0, 0})
 {
     constexpr int K = count_mpt<PREC>();
     const int first = base + threadIdx.x * K;
@@ -392,7 +420,7 @@ __device__ __forceinline__ void count_tile(const Geo& g, const SortSmem<PREC>& s
         // implied cells: this thread's K consecutive positions are its own slots
         int ob[K];
         if (base < ovf) {
-            tile_buckets<K, false>(g, pv, base, min(last + 1, ovf), sm.hist, s_aux, ob);
+            tile_buckets<K, false, AHEAD>(g, pv, base, min(last + 1, ovf), sm.hist, s_aux, ob, ah);
 #pragma unroll
             for (int k = 0; k < K; ++k)
                 if (first + k < ovf) grp.p[k].cell = ob[k];
@@ -536,12 +564,27 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4)
     if (threadIdx.x == 0) s_flags = 0;
     if (PUSH) stage_tables<PREC>(g, sm.sE, sm.sRow, E, rows_g, bk);
     int fl = 0;
+    // implied cells: a tile's first-pass run offsets are loaded one tile
+    // ahead, its first run two tiles ahead (as in the scatter)
+    TbAhead ah{0, 0, 0};
+    int b0n = 0;
+    if constexpr (IMPL) {
+        if ((int)blockIdx.x < ntiles) ah = tile_runs_ahead(g, pv, tile_first_run(pv, blockIdx.x * T));
+        if ((int)(blockIdx.x + gridDim.x) < ntiles) b0n = tile_first_run(pv, (blockIdx.x + gridDim.x) * T);
+    }
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         Group<PREC, VD, K> grp;
         const int last = count_tile_last<PREC>(g, t);
         grp.load(m, g, t * T + threadIdx.x * K, last, false, PREC ? 1 : VD, ovf);
-        count_tile<PREC, VD, PUSH, IMPL>(g, sm, grp, dtk, bk, counts, tsum, t * T, last, s_b, &s_lo, &s_nb, s_tile,
-                                         fl, pv, ovf, s_aux);
+        TbAhead an{0, 0, 0};
+        if constexpr (IMPL) {
+            const int tn = t + gridDim.x, tnn = tn + gridDim.x;
+            if (tn < ntiles) an = tile_runs_ahead(g, pv, b0n);
+            if (tnn < ntiles) b0n = tile_first_run(pv, tnn * T);
+        }
+        count_tile<PREC, VD, PUSH, IMPL, IMPL>(g, sm, grp, dtk, bk, counts, tsum, t * T, last, s_b, &s_lo, &s_nb,
+                                               s_tile, fl, pv, ovf, s_aux, ah);
+        ah = an;
     }
     if (fl) atomicOr(&s_flags, fl);
     __syncthreads();
@@ -558,19 +601,20 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4)
 // ---------------------------------------------------------------------------
 // One tile of the scatter: the markers [base, last] of the previous order are
 // in p[] (lane-strided), the field and drift table staged in LDS.
-template <int PREC, int VD, bool PUSH, bool IMPL>
+template <int PREC, int VD, bool PUSH, bool IMPL, bool AHEAD = false>
 __device__ __forceinline__ void scatter_tile(const Geo& g, const SortSmem<PREC>& sm, Pay<PREC, VD>* p,
                                              const typename MarkersOf<PREC>::T& dst, double dtk, float bk,
                                              const int* __restrict__ offsets, int* __restrict__ counts,
                                              int base, int last, int* s_b, int* s_lo, int* s_nb, int& fl,
-                                             const Prev& pv, int ovf, int* s_aux, int maxbins)
+                                             const Prev& pv, int ovf, int* s_aux, int maxbins,
+                                             const TbAhead& ah = TbAhead{0, 0, 0})
 {
     constexpr int K = kSortMPT;
     if constexpr (IMPL) {
         // implied cells: the tile's buckets are left in LDS, read lane-strided
         if (base < ovf) {
             int ob[K];
-            tile_buckets<K, true>(g, pv, base, min(last + 1, ovf), sm.hist, s_aux, ob);
+            tile_buckets<K, true, AHEAD>(g, pv, base, min(last + 1, ovf), sm.hist, s_aux, ob, ah);
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const int i = base + k * kSortThreads + threadIdx.x;
@@ -719,6 +763,16 @@ __device__ __forceinline__ void scatter_tiled(const Geo& g, typename MarkersOf<P
     // f is only needed when the marker is stored: each tile's f is loaded
     // when its processing starts, not with the tile loaded ahead
     load_tile<PREC, VD>(src, g, p, t * kSortTile, min(t * kSortTile + kSortTile, g.n) - 1, ovf, ID);
+    // implied cells: the run offsets of a tile's first pass are loaded one
+    // tile ahead, and its first run two tiles ahead (the offsets' addresses
+    // depend on it), so neither load's latency is waited for when the tile
+    // starts
+    TbAhead ah{0, 0, 0};
+    int b0n = 0;
+    if constexpr (IMPL) {
+        if (t < ntiles) ah = tile_runs_ahead(g, pv, tile_first_run(pv, t * kSortTile));
+        if (t + (int)gridDim.x < ntiles) b0n = tile_first_run(pv, (t + gridDim.x) * kSortTile);
+    }
     for (; t < ntiles; t += gridDim.x) {
         const int tn = t + gridDim.x;
         if constexpr (PREC == 1 && !ID) {
@@ -728,11 +782,18 @@ __device__ __forceinline__ void scatter_tiled(const Geo& g, typename MarkersOf<P
         }
         if (tn < ntiles)
             load_tile<PREC, VD>(src, g, q, tn * kSortTile, min(tn * kSortTile + kSortTile, g.n) - 1, ovf, ID);
-        scatter_tile<PREC, VD, PUSH, IMPL>(g, sm, p, dst, dtk, bk, offsets, counts, t * kSortTile,
-                                           min(t * kSortTile + kSortTile, g.n) - 1, s_b, &s_lo, &s_nb, fl, pv, ovf,
-                                           s_aux, g.sbins);
+        TbAhead an{0, 0, 0};
+        if constexpr (IMPL) {
+            const int tnn = tn + gridDim.x;
+            if (tn < ntiles) an = tile_runs_ahead(g, pv, b0n);
+            if (tnn < ntiles) b0n = tile_first_run(pv, tnn * kSortTile);
+        }
+        scatter_tile<PREC, VD, PUSH, IMPL, IMPL>(g, sm, p, dst, dtk, bk, offsets, counts, t * kSortTile,
+                                                 min(t * kSortTile + kSortTile, g.n) - 1, s_b, &s_lo, &s_nb, fl, pv,
+                                                 ovf, s_aux, g.sbins, ah);
 #pragma unroll
         for (int k = 0; k < kSortMPT; ++k) p[k] = q[k];
+        ah = an;
     }
     if (fl) atomicOr(&s_flags, fl);
     __syncthreads();
