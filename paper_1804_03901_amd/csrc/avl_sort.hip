@@ -274,8 +274,9 @@ __device__ __forceinline__ void tile_buckets(const Geo& g, const Prev& pv, int b
         if (tid == kSortThreads - 1) s_aux[kSortThreads / kWave] = (b < g.nb && lo < end) ? 1 : 0;
         __syncthreads();
         const int more = s_aux[kSortThreads / kWave];
-        __syncthreads();
         if (!more) break;
+        // the flag is written again by the next pass
+        __syncthreads();
     }
     // running maximum over the slots: within the thread, then across threads
 #pragma unroll
@@ -310,7 +311,7 @@ __device__ __forceinline__ void tile_buckets(const Geo& g, const Prev& pv, int b
 // The LDS window of a sort block: bucket rows around the rows of the block's
 // first and last marker (which bound the block's rows, the input being
 // sorted), widened by one row each way, at most maxbins buckets.
-__device__ __forceinline__ void set_window(const Geo& g, int b0, int b1, int* s_lo, int* s_nb, int maxbins)
+__device__ __forceinline__ void set_window(const Geo& g, int b0, int b1, int* lo_out, int* nb_out, int maxbins)
 {
     int r0 = (b0 >= g.nb ? g.nrow - 1 : b0 >> g.lognx);
     int r1 = (b1 >= g.nb ? g.nrow - 1 : b1 >> g.lognx);
@@ -319,8 +320,8 @@ __device__ __forceinline__ void set_window(const Geo& g, int b0, int b1, int* s_
     hi = min(hi, g.nrow - 1);
     int maxrows = maxbins >> g.lognx;
     if (hi - lo + 1 > maxrows) hi = lo + maxrows - 1;
-    *s_lo = lo << g.lognx;
-    *s_nb = (hi - lo + 1) << g.lognx;
+    *lo_out = lo << g.lognx;
+    *nb_out = (hi - lo + 1) << g.lognx;
 }
 
 // Stage the field and, in the FP32 form, the drift table into LDS.  The FP64
@@ -411,7 +412,7 @@ struct Agg {
 template <int PREC, int VD, bool PUSH, bool IMPL, bool AHEAD = false>
 __device__ __forceinline__ void count_tile(const Geo& g, const SortSmem<PREC>& sm, Group<PREC, VD, count_mpt<PREC>()>& grp,
                                            double dtk, float bk, int* __restrict__ counts, int* __restrict__ tsum,
-                                           int base, int last, int* s_b, int* s_lo, int* s_nb, int* s_tile, int& fl,
+                                           int base, int last, int* s_b, int* s_tile, int& fl,
                                            const Prev& pv, int ovf, int* s_aux, const TbAhead& ah = TbAhead{0, 0, 0})
 {
     constexpr int K = count_mpt<PREC>();
@@ -432,9 +433,9 @@ __device__ __forceinline__ void count_tile(const Geo& g, const SortSmem<PREC>& s
         if (first + k == last) s_b[1] = grp.p[k].bucket(g);
     }
     __syncthreads();
-    if (threadIdx.x == 0) set_window(g, s_b[0], s_b[1], s_lo, s_nb, g.hist_bins);
-    __syncthreads();
-    const int lo = *s_lo, nbw = *s_nb;
+    // every thread forms the window from the tile's two end buckets itself
+    int lo, nbw;
+    set_window(g, s_b[0], s_b[1], &lo, &nbw, g.hist_bins);
     for (int i = threadIdx.x; i < nbw; i += blockDim.x) sm.hist[i] = 0;
     if (threadIdx.x < 8) s_tile[threadIdx.x] = 0;
     __syncthreads();
@@ -515,7 +516,7 @@ __device__ __forceinline__ void count_block(const Geo& g, const typename Markers
 {
     extern __shared__ __align__(16) unsigned char smem[];
     SortSmem<PREC> sm(smem, g);
-    __shared__ int s_b[2], s_lo, s_nb, s_flags, s_tile[8], s_aux[kSortThreads / kWave + 1];
+    __shared__ int s_b[2], s_flags, s_tile[8], s_aux[kSortThreads / kWave + 1];
     if (threadIdx.x == 0) s_flags = 0;
     if (PUSH) stage_tables<PREC>(g, sm.sE, sm.sRow, E, rows_g, bk);
     constexpr int K = count_mpt<PREC>();
@@ -525,7 +526,7 @@ __device__ __forceinline__ void count_block(const Geo& g, const typename Markers
     const int ovf = IMPL ? pv.off[g.nb] : -1;
     grp.load(m, g, base + threadIdx.x * K, last, false, PREC ? 1 : VD, ovf);
     int fl = 0;
-    count_tile<PREC, VD, PUSH, IMPL>(g, sm, grp, dtk, bk, counts, tsum, base, last, s_b, &s_lo, &s_nb, s_tile, fl, pv,
+    count_tile<PREC, VD, PUSH, IMPL>(g, sm, grp, dtk, bk, counts, tsum, base, last, s_b, s_tile, fl, pv,
                                      ovf, s_aux);
     if (fl) atomicOr(&s_flags, fl);
     __syncthreads();
@@ -556,7 +557,7 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     SortSmem<PREC> sm(smem, g);
-    __shared__ int s_b[2], s_lo, s_nb, s_flags, s_tile[8], s_aux[kSortThreads / kWave + 1];
+    __shared__ int s_b[2], s_flags, s_tile[8], s_aux[kSortThreads / kWave + 1];
     constexpr int K = count_mpt<PREC>();
     constexpr int T = kSortThreads * K;
     const int ntiles = (g.n + T - 1) / T;
@@ -582,7 +583,7 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4)
             if (tn < ntiles) an = tile_runs_ahead(g, pv, b0n);
             if (tnn < ntiles) b0n = tile_first_run(pv, tnn * T);
         }
-        count_tile<PREC, VD, PUSH, IMPL, IMPL>(g, sm, grp, dtk, bk, counts, tsum, t * T, last, s_b, &s_lo, &s_nb,
+        count_tile<PREC, VD, PUSH, IMPL, IMPL>(g, sm, grp, dtk, bk, counts, tsum, t * T, last, s_b,
                                                s_tile, fl, pv, ovf, s_aux, ah);
         ah = an;
     }
@@ -605,7 +606,7 @@ template <int PREC, int VD, bool PUSH, bool IMPL, bool AHEAD = false>
 __device__ __forceinline__ void scatter_tile(const Geo& g, const SortSmem<PREC>& sm, Pay<PREC, VD>* p,
                                              const typename MarkersOf<PREC>::T& dst, double dtk, float bk,
                                              const int* __restrict__ offsets, int* __restrict__ counts,
-                                             int base, int last, int* s_b, int* s_lo, int* s_nb, int& fl,
+                                             int base, int last, int* s_b, int& fl,
                                              const Prev& pv, int ovf, int* s_aux, int maxbins,
                                              const TbAhead& ah = TbAhead{0, 0, 0})
 {
@@ -629,9 +630,9 @@ __device__ __forceinline__ void scatter_tile(const Geo& g, const SortSmem<PREC>&
         if (i == last) s_b[1] = p[k].bucket(g);
     }
     __syncthreads();
-    if (threadIdx.x == 0) set_window(g, s_b[0], s_b[1], s_lo, s_nb, maxbins);
-    __syncthreads();
-    const int lo = *s_lo, nbw = *s_nb;
+    // every thread forms the window from the tile's two end buckets itself
+    int lo, nbw;
+    set_window(g, s_b[0], s_b[1], &lo, &nbw, maxbins);
     for (int i = threadIdx.x; i < nbw; i += blockDim.x) sm.hist[i] = 0;
     __syncthreads();
     int bkt[K], rank[K];
@@ -703,7 +704,7 @@ __device__ __forceinline__ void scatter_block(const Geo& g, const typename Marke
 {
     extern __shared__ __align__(16) unsigned char smem[];
     SortSmem<PREC> sm(smem, g);
-    __shared__ int s_b[2], s_lo, s_nb, s_flags, s_aux[kSortThreads / kWave + 1];
+    __shared__ int s_b[2], s_flags, s_aux[kSortThreads / kWave + 1];
     const int base = blk * kSortTile;
     const int last = min(base + kSortTile, g.n) - 1;
     const int ovf = IMPL ? pv.off[g.nb] : -1;
@@ -712,7 +713,7 @@ __device__ __forceinline__ void scatter_block(const Geo& g, const typename Marke
     Pay<PREC, VD> p[kSortMPT];
     load_tile<PREC, VD>(src, g, p, base, last, ovf);
     int fl = 0;
-    scatter_tile<PREC, VD, PUSH, IMPL>(g, sm, p, dst, dtk, bk, offsets, counts, base, last, s_b, &s_lo, &s_nb, fl,
+    scatter_tile<PREC, VD, PUSH, IMPL>(g, sm, p, dst, dtk, bk, offsets, counts, base, last, s_b, fl,
                                        pv, ovf, s_aux, maxbins);
     if (fl) atomicOr(&s_flags, fl);
     __syncthreads();
@@ -752,7 +753,7 @@ __device__ __forceinline__ void scatter_tiled(const Geo& g, typename MarkersOf<P
     }
     extern __shared__ __align__(16) unsigned char smem[];
     SortSmem<PREC> sm(smem, g);
-    __shared__ int s_b[2], s_lo, s_nb, s_flags, s_aux[kSortThreads / kWave + 1];
+    __shared__ int s_b[2], s_flags, s_aux[kSortThreads / kWave + 1];
     const int ntiles = (g.n + kSortTile - 1) / kSortTile;
     const int ovf = IMPL ? pv.off[g.nb] : -1;
     if (threadIdx.x == 0) s_flags = 0;
@@ -789,7 +790,7 @@ __device__ __forceinline__ void scatter_tiled(const Geo& g, typename MarkersOf<P
             if (tnn < ntiles) b0n = tile_first_run(pv, tnn * kSortTile);
         }
         scatter_tile<PREC, VD, PUSH, IMPL, IMPL>(g, sm, p, dst, dtk, bk, offsets, counts, t * kSortTile,
-                                                 min(t * kSortTile + kSortTile, g.n) - 1, s_b, &s_lo, &s_nb, fl, pv,
+                                                 min(t * kSortTile + kSortTile, g.n) - 1, s_b, fl, pv,
                                                  ovf, s_aux, g.sbins, ah);
 #pragma unroll
         for (int k = 0; k < kSortMPT; ++k) p[k] = q[k];
