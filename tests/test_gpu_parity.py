@@ -499,3 +499,49 @@ def test_large_kicks_step(precision):
         # kick in cells: K 2^-23 of a cell for a kick of K cells
         assert np.max(np.abs(np.sort(vg[0]) - np.sort(vo[0]))) <= (1e-5 + 4 * kick * 2.0 ** -24) * dv
     sim.check()
+
+
+@pytest.mark.parametrize("precision", [avl.AVL_FP64, avl.AVL_FP32])
+def test_long_overflow_run_step(precision):
+    """A third of the markers outside the velocity grid, above and below it:
+    their run (the overflow bucket, stored cell indices in the FP32 form) spans
+    many sort tiles, so whole count and scatter tiles lie past its start.  One
+    step against the oracle from the exported state, then more steps keep
+    every marker and the multiset of weights (FP32 form: its push's bounds)."""
+    w = CASES["ragged"]
+    _need_gpu()
+    fp64 = precision == avl.AVL_FP64
+    x, v, f = inputs.markers(w)
+    v = v.copy()
+    dv = w.dv(0)
+    rng = np.random.default_rng(71)
+    out = rng.random(x.size) < 1.0 / 3.0
+    up = rng.random(x.size) < 0.5
+    spread = 2.0 + 20.0 * rng.random(x.size)
+    v[0] = np.where(out & up, w.vmax[0] + spread * dv, np.where(out, w.vmin[0] - spread * dv, v[0]))
+    sim, _ = sim_for(w, precision=precision, markers=(x, v, f))
+    n_out = int(out.sum())
+    print(f"[case] long overflow run: {n_out} of {x.size} markers outside", flush=True)
+    assert n_out > 4 * 4096
+    xs, vs, fs = (t2n(a) for a in sim.markers())
+    E = t2n(sim.field()[0])
+    xo, vo, fo, Do, rho_o, _, _ = _one_step_oracle(w, xs, vs.reshape(1, -1), fs, E)
+    sim.step(1)
+    fg, Dg = (t2n(a) for a in sim.reconstruct(want_D=True))
+    _, rho_g = sim.field()
+    tol_f, tol_rho = (TOL64, TOL64) if fp64 else (1e-5, 1e-6)
+    print(f"[result] long overflow run prec={precision}: f {nrel(fg, fo):.1e} cell {cell_rel(fg, fo, Do):.1e} "
+          f"rho {nrel(t2n(rho_g), rho_o):.1e}", flush=True)
+    assert nrel(fg, fo) <= tol_f and nrel(Dg, Do) <= tol_f
+    assert cell_rel(fg, fo, Do) <= (TOL64_CELL if fp64 else 1e-5)
+    assert nrel(t2n(rho_g), rho_o) <= tol_rho
+    xg, vg, _ = (t2n(a) for a in sim.markers())
+    kick = np.max(np.abs(E)) * w.dt / dv
+    assert np.max(np.abs(np.sort(vg[0]) - np.sort(vo[0]))) <= (TOL64 * (w.vmax[0] - w.vmin[0]) if fp64 else
+                                                            (1e-5 + 4 * kick * 2.0 ** -24) * dv)
+    sim.step(4)
+    xg, vg, fg1 = (t2n(a) for a in sim.markers())
+    assert xg.size == x.size
+    assert np.array_equal(np.sort(fg1), np.sort(fs))
+    assert np.sum((vg[0] > w.vmax[0] + dv) | (vg[0] < w.vmin[0] - dv)) > 4 * 4096
+    sim.check()
