@@ -196,3 +196,40 @@ def test_adjoint_at_full_size():
     print(f"full size: A1 adjoint {float(gA[0]):.10e} fd64 {fdA:.10e}; drift {gd:.10e} fd64 {fdd:.10e}")
     assert abs(float(gA[0]) - fdA) <= 1e-4 * abs(fdA)
     assert abs(gd - fdd) <= 1e-4 * abs(fdd)
+
+
+@pytest.mark.parametrize("precision", [avl.AVL_FP64, avl.AVL_FP32])
+def test_gradient_with_markers_outside_the_velocity_grid(precision):
+    """A fifth of the markers beyond the velocity grid (the overflow run; in
+    the FP32 form the recorded states keep their stored cell indices): the
+    weight gradient's directional derivative against central differences of
+    the FP64 path.  Those markers reach no grid cell, so their gradient is
+    zero, and the others' is unchanged in kind."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    x, v, f = inputs.markers_threaded(W)
+    v = v.copy()
+    dv = W.dv(0)
+    rng = np.random.default_rng(17)
+    out = rng.random(x.size) < 0.2
+    up = rng.random(x.size) < 0.5
+    spread = 2.0 + 6.0 * rng.random(x.size)
+    v[0] = np.where(out & up, W.vmax[0] + spread * dv, np.where(out, W.vmin[0] - spread * dv, v[0]))
+    dev = torch.device("cuda:0")
+    xt = torch.tensor(x, device=dev)
+    vt = torch.tensor(v.reshape(-1), device=dev)
+    ft = torch.tensor(f, device=dev)
+    print(f"[case] adjoint outside-grid prec={precision} n={x.size} out={int(out.sum())}", flush=True)
+    sim = avl.Simulation(W, x, v.reshape(-1), f, precision=precision)
+    _, g = adjoint.energy_and_gradient(sim, xt, vt, ft, NSTEPS, every=10)
+    sim64 = sim if precision == avl.AVL_FP64 else avl.Simulation(W, x, v.reshape(-1), f, precision=avl.AVL_FP64)
+    d = torch.tensor(rng.normal(size=f.size) * f, device=dev)
+    h = 1e-6
+    Jp, _ = adjoint.energy_and_gradient(sim64, xt, vt, ft + h * d, NSTEPS, want_grad=False)
+    Jm, _ = adjoint.energy_and_gradient(sim64, xt, vt, ft - h * d, NSTEPS, want_grad=False)
+    fd = (float(Jp) - float(Jm)) / (2 * h)
+    ad = float((g * d).sum())
+    print(f"[result] outside-grid prec={precision}: adjoint {ad:.10e} fd64 {fd:.10e}", flush=True)
+    assert abs(ad - fd) <= 1e-4 * abs(fd)
+    assert float(g[torch.tensor(out, device=dev)].abs().max()) == 0.0
+    sim.check()
