@@ -32,18 +32,50 @@ def small_scan():
     return ws
 
 
-def make_batch(ws, precision):
+def make_batch(ws, precision, mk=None):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    mk = [inputs.markers(w) for w in ws]
-    print(f"[case] batch of {len(ws)} prec={precision} n={sum(w.n_markers for w in ws)}", flush=True)
+    mk = mk if mk is not None else [inputs.markers(w) for w in ws]
+    print(f"[case] batch of {len(ws)} prec={precision} n={sum(m[0].size for m in mk)}", flush=True)
     return avl.Batch(ws, mk, precision=precision), mk
+
+
+def outside_markers(w, frac, seed):
+    """The instance's markers with a fraction moved 2 to 10 cells beyond the
+    velocity grid, above or below (their run: the overflow bucket)."""
+    x, v, f = inputs.markers(w)
+    v = v.copy()
+    dv = w.dv(0)
+    rng = np.random.default_rng(seed)
+    out = rng.random(x.size) < frac
+    up = rng.random(x.size) < 0.5
+    spread = 2.0 + 8.0 * rng.random(x.size)
+    v[0] = np.where(out & up, w.vmax[0] + spread * dv, np.where(out, w.vmin[0] - spread * dv, v[0]))
+    return x, v, f
 
 
 @pytest.mark.parametrize("precision", [avl.AVL_FP64, avl.AVL_FP32])
 def test_batch_step_matches_oracle_per_instance(precision):
     ws = small_scan()
     b, _ = make_batch(ws, precision)
+    _step_against_oracle(ws, b, precision)
+
+
+@pytest.mark.parametrize("precision", [avl.AVL_FP64, avl.AVL_FP32])
+def test_batch_with_an_overflow_run(precision):
+    """An instance with 30% of its markers beyond the velocity grid (a long
+    overflow run; in the FP32 form those keep stored cell indices) among
+    ordinary ones: per-instance parity with the oracle as above."""
+    ws = small_scan()[:3]
+    ws.append(inputs.bump_on_tail(nx=64, nv=30, ppc=6, seed=19).replace(name="overflow_instance"))
+    mk = [inputs.markers(w) for w in ws[:3]] + [outside_markers(ws[3], 0.3, 23)]
+    b, _ = make_batch(ws, precision, mk)
+    _step_against_oracle(ws, b, precision)
+
+
+def _step_against_oracle(ws, b, precision):
+    """Two batched steps, then one more compared instance by instance with the
+    oracle's step from the exported state."""
     b.step(2)
     states = []
     for i, w in enumerate(ws):
