@@ -450,6 +450,21 @@ __device__ __forceinline__ int fix_exp_of_key(unsigned k, float) { return (int)(
 __device__ __forceinline__ int fix_exp_of_key(unsigned k, double) { return (int)(k >> 20) - 1023; }
 template <typename T> __device__ __forceinline__ int fix_exp_bits(T x) { return fix_exp_of_key(fix_key(x), x); }
 
+// Issue priority from progress: a wave that has done `done` of its `total`
+// units of work (rows, tiles) takes priority 3 in its first quarter down to 0
+// in its last.  A compute unit's waves then issue in the order of how far
+// behind they are, so the ones that fell behind catch up and fewer are still
+// running at the end of a launch, when the memory system is no longer
+// saturated.  Priority only orders issue; results do not depend on it.
+__device__ __forceinline__ void prio_by_progress(int done, int total)
+{
+    const int pr = 3 - min(3, (4 * done) / max(total, 1));
+    if (pr >= 3) __builtin_amdgcn_s_setprio(3);
+    else if (pr == 2) __builtin_amdgcn_s_setprio(2);
+    else if (pr == 1) __builtin_amdgcn_s_setprio(1);
+    else __builtin_amdgcn_s_setprio(0);
+}
+
 __device__ __forceinline__ void fixsum_pin(double& v) { asm volatile("" : "+v"(v)); }
 
 // FP64 rounding mode (MODE register, FP_ROUND bits 3:2): toward -infinity, and

@@ -636,9 +636,11 @@ __device__ __forceinline__ void recon_task(const Geo& g, const typename RT<PREC>
     // (the compiler then keeps the waits for loads at their full depth); a
     // row past the chunk has empty runs and writes nothing
     for (int k = 0; k < nrows; k += DEPTH) {
+        prio_by_progress(k, nrows);
 #pragma unroll
         for (int q = 0; q < DEPTH; ++q) row(k + q, regs[q], wreg[q]);
     }
+    __builtin_amdgcn_s_setprio(0);
     if (tgt_ok) rho_part[(size_t)chunk * nx + col] = rp;
 }
 

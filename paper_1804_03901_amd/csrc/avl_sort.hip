@@ -573,7 +573,9 @@ __global__ __launch_bounds__(kSortThreads) __attribute__((amdgpu_waves_per_eu(4)
         if ((int)blockIdx.x < ntiles) ah = tile_runs_ahead(g, pv, tile_first_run(pv, blockIdx.x * T));
         if ((int)(blockIdx.x + gridDim.x) < ntiles) b0n = tile_first_run(pv, (blockIdx.x + gridDim.x) * T);
     }
+    const int my_tiles = (ntiles - (int)blockIdx.x + (int)gridDim.x - 1) / (int)gridDim.x;
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        prio_by_progress((t - (int)blockIdx.x) / (int)gridDim.x, my_tiles);
         Group<PREC, VD, K> grp;
         const int last = count_tile_last<PREC>(g, t);
         grp.load(m, g, t * T + threadIdx.x * K, last, false, PREC ? 1 : VD, ovf);
@@ -774,8 +776,10 @@ __device__ __forceinline__ void scatter_tiled(const Geo& g, typename MarkersOf<P
         if (t < ntiles) ah = tile_runs_ahead(g, pv, tile_first_run(pv, t * kSortTile));
         if (t + (int)gridDim.x < ntiles) b0n = tile_first_run(pv, (t + gridDim.x) * kSortTile);
     }
+    const int my_tiles = (ntiles - (int)blockIdx.x + (int)gridDim.x - 1) / (int)gridDim.x;
     for (; t < ntiles; t += gridDim.x) {
         const int tn = t + gridDim.x;
+        prio_by_progress((t - (int)blockIdx.x) / (int)gridDim.x, my_tiles);
         if constexpr (PREC == 1 && !ID) {
             const int last = min(t * kSortTile + kSortTile, g.n) - 1;
 #pragma unroll
