@@ -220,6 +220,9 @@ void k_recon_3v(Geo g, typename R3<PREC>::M m, const int* __restrict__ offsets, 
     double rp[4] = {0.0, 0.0, 0.0, 0.0};
 
     while (cur.r <= nvx) {
+        // issue priority from progress (the FP32 form; the FP64 form's three
+        // waves a compute unit ran slower with it)
+        if constexpr (PREC == 1) prio_by_progress(cur.r, nvx + 1);
         const int iy = cur.iy, iz = cur.iz;
         const bool staged = fits(seg);
         const int p0 = staged ? ((wrapped && lane == 0) ? seg.nmain : beg - seg.lo) : beg;
@@ -357,6 +360,7 @@ void k_recon_3v(Geo g, typename R3<PREC>::M m, const int* __restrict__ offsets, 
         seg_bounds(ahead, nbeg, nend);
         advance(ahead);
     }
+    if constexpr (PREC == 1) __builtin_amdgcn_s_setprio(0);
     if (tgt_ok) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
