@@ -409,7 +409,7 @@ __device__ __forceinline__ void prefetch(const typename RT<PREC>::M& m, const Se
 // the FP64 form one.
 template <int PREC> constexpr int recon_depth() { return PREC ? 2 : 1; }
 
-template <int PREC, bool KAHAN, bool SPARSE>
+template <int PREC, bool KAHAN, bool SPARSE, bool PRIO = false>
 __device__ __forceinline__ void recon_task(const Geo& g, const typename RT<PREC>::M& m,
                                            const int* __restrict__ offsets, typename RT<PREC>::T* __restrict__ fgrid,
                                            typename RT<PREC>::T* __restrict__ Dgrid, double* __restrict__ rho_part,
@@ -635,12 +635,14 @@ __device__ __forceinline__ void recon_task(const Geo& g, const typename RT<PREC>
     // whole groups of DEPTH rows, so every pass of the loop body is the same
     // (the compiler then keeps the waits for loads at their full depth); a
     // row past the chunk has empty runs and writes nothing
+    // PRIO: issue priority from progress (one instance's tasks, all of about
+    // the same size; the batched kernel's tasks differ too much for it)
     for (int k = 0; k < nrows; k += DEPTH) {
-        prio_by_progress(k, nrows);
+        if constexpr (PRIO) prio_by_progress(k, nrows);
 #pragma unroll
         for (int q = 0; q < DEPTH; ++q) row(k + q, regs[q], wreg[q]);
     }
-    __builtin_amdgcn_s_setprio(0);
+    if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
     if (tgt_ok) rho_part[(size_t)chunk * nx + col] = rp;
 }
 
@@ -660,7 +662,7 @@ __global__ __launch_bounds__(kWave) void k_recon_1v(Geo g, typename RT<PREC>::M 
 {
     const int task = dealt_task(tasks_per_xcd, g.nstrip * g.nchunk);
     if (task < 0) return;
-    recon_task<PREC, KAHAN, SPARSE>(g, m, offsets, fgrid, Dgrid, rho_part, task);
+    recon_task<PREC, KAHAN, SPARSE, true>(g, m, offsets, fgrid, Dgrid, rho_part, task);
 }
 
 // Batched reconstruction: the tasks of every instance form one list, dealt
