@@ -214,12 +214,6 @@ struct Prev {
     const int* tfirst;
 };
 
-// Buckets of the positions [base, end) of a tile (base a multiple of
-// kTfStride, end at most the start of the overflow run): the largest b with
-// off[b] <= p.  Thread t owns the SL slots [t SL, t SL + SL) of `map` (T =
-// kSortThreads SL ints of LDS, free on entry) and gets their buckets in bk[]
-// (undefined past end); with WRITE they are also left in map for other
-// threads, after a barrier.  s_aux: kSortThreads / kWave + 1 ints of LDS.
 // Run offsets of tile_buckets' first pass, loaded ahead of the tile: b0, the
 // run that holds the tile's first position, and the bounds of run b0 + 1 + t
 // for thread t (zero past the last run).
@@ -241,6 +235,12 @@ __device__ __forceinline__ TbAhead tile_runs_ahead(const Geo& g, const Prev& pv,
     return a;
 }
 
+// Buckets of the positions [base, end) of a tile (base a multiple of
+// kTfStride, end at most the start of the overflow run): the largest b with
+// off[b] <= p.  Thread t owns the SL slots [t SL, t SL + SL) of `map` (T =
+// kSortThreads SL ints of LDS, free on entry) and gets their buckets in bk[]
+// (undefined past end); with WRITE they are also left in map for other
+// threads, after a barrier.  s_aux: kSortThreads / kWave + 1 ints of LDS.
 // AHEAD: the first pass takes b0 and its offsets from ah instead of loading them.
 template <int SL, bool WRITE, bool AHEAD = false>
 __device__ __forceinline__ void tile_buckets(const Geo& g, const Prev& pv, int base, int end, int* map, int* s_aux,
